@@ -1,0 +1,101 @@
+"""Named synthetic workloads.
+
+* ``tiny``         16x8x4 grid, 90 wet columns, 300 points, one-tracer N model,
+                   one euphotic layer.
+* ``global_2p8``   128x64x15 grid (2.8125 degrees, as in section 7 of the paper),
+                   exactly 4448 wet columns and 52749 points, N-DOP model, two
+                   euphotic layers.
+* ``ensemble_1p4`` 256x128x23 grid (1.40625 degrees), 22000 wet columns and
+                   500000 points, N-DOP model, two euphotic layers.
+
+All use twelve monthly matrices of each kind and 2880 steps per model year.
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from .grid import Grid, make_grid
+from .params import MODEL_N, MODEL_NDOP, NTRACER, NPARAM
+from .transport import Transport, make_transport
+
+
+@dataclass
+class Inputs:
+    name: str
+    grid: Grid
+    tm: Transport
+    model: int
+    neuphotic: int
+    y_init: tuple          # constant initial value per tracer
+
+    @property
+    def n(self):
+        return self.grid.n
+
+    @property
+    def ntracer(self):
+        return NTRACER[self.model]
+
+    @property
+    def nparam(self):
+        return NPARAM[self.model]
+
+    @property
+    def nstep(self):
+        return self.tm.nstep
+
+    @property
+    def nmat(self):
+        return self.tm.nmat
+
+    def initial_state(self, nbatch: int = 1) -> np.ndarray:
+        """Row-major ``n x (nbatch*ntracer)`` constant initial field."""
+        row = np.tile(np.asarray(self.y_init, dtype=np.float64), nbatch)
+        return np.broadcast_to(row, (self.n, row.size)).copy()
+
+    def desc_arrays(self) -> dict:
+        """Flat arrays in the order of the transport-matrix descriptor."""
+        g, t = self.grid, self.tm
+        return dict(
+            n=g.n, ncol=g.ncol, nlayer=g.nlayer,
+            col_start=np.ascontiguousarray(g.col_start, dtype=np.int32),
+            lat=np.ascontiguousarray(g.lat, dtype=np.float64),
+            area=np.ascontiguousarray(g.area, dtype=np.float64),
+            dz=np.ascontiguousarray(g.dz, dtype=np.float64),
+            nmat=t.nmat, nstep=t.nstep, model=self.model, neuphotic=self.neuphotic,
+            ae_rowptr=t.ae_rowptr, ae_colidx=t.ae_colidx, ae_val=np.ascontiguousarray(t.ae_val),
+            ai_rowptr=t.ai_rowptr, ai_colidx=t.ai_colidx, ai_val=np.ascontiguousarray(t.ai_val),
+        )
+
+
+def _build(name, nlon, nlat, nlayer, ncol, n, model, neu, y_init, seed, nmat=12, nstep=2880):
+    grid = make_grid(nlon, nlat, nlayer, ncol, n, seed)
+    tm = make_transport(grid, seed + 1, nmat=nmat, nstep=nstep)
+    return Inputs(name=name, grid=grid, tm=tm, model=model, neuphotic=neu, y_init=y_init)
+
+
+def tiny(seed: int = 7, model: int = MODEL_N, nstep: int = 2880) -> Inputs:
+    y0 = (2.17,) if model == MODEL_N else (2.17, 1e-4)
+    neu = 1 if model == MODEL_N else 2
+    return _build("tiny_16x8x4", 16, 8, 4, 90, 300, model, neu, y0, seed, nstep=nstep)
+
+
+def global_2p8(seed: int = 11, nstep: int = 2880) -> Inputs:
+    return _build("global_128x64x15", 128, 64, 15, 4448, 52749, MODEL_NDOP, 2, (2.17, 1e-4), seed,
+                  nstep=nstep)
+
+
+def ensemble_1p4(seed: int = 13, nstep: int = 2880) -> Inputs:
+    return _build("ensemble_256x128x23", 256, 128, 23, 22000, 500000, MODEL_NDOP, 2, (2.17, 1e-4), seed,
+                  nstep=nstep)
+
+
+def small_ndop(seed: int = 5, nstep: int = 2880) -> Inputs:
+    """A 32x16x8 N-DOP grid (about 2.7k points): several tiles and a ragged tail."""
+    return _build("small_32x16x8", 32, 16, 8, 400, 2700, MODEL_NDOP, 2, (2.17, 1e-4), seed, nstep=nstep)
+
+
+def by_name(name: str) -> Inputs:
+    table = {"tiny": tiny, "global": global_2p8, "ensemble": ensemble_1p4, "small": small_ndop}
+    return table[name]()

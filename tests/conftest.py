@@ -1,0 +1,31 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+@pytest.fixture(scope="session")
+def tiny_n():
+    import synth
+    return synth.tiny()
+
+
+@pytest.fixture(scope="session")
+def tiny_ndop():
+    import synth
+    return synth.tiny(model=synth.MODEL_NDOP)
+
+
+@pytest.fixture(scope="session")
+def small_ndop():
+    import synth
+    return synth.small_ndop()

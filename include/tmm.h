@@ -1,0 +1,155 @@
+/*
+ * libtmm -- transport-matrix time stepping of marine biogeochemical tracers
+ * on one AMD Instinct MI355X (gfx950), float64 throughout.
+ *
+ * The method is the one of Piwonski & Slawig, "The Idea and Concept of
+ * Metos3D" (arXiv 1410.0204):
+ *
+ *   y_{j+1} = A_imp(t_j) (A_exp(t_j) y_j + dt * q(y_j, u)),   j = 0..nstep-1
+ *
+ * (section 3), where A_exp / A_imp are linear interpolations between twelve
+ * monthly explicit (horizontal) and implicit (vertical) transport matrices
+ * (sections 3 and 7), q is a biogeochemical model evaluated per water column
+ * (sections 2.2 and 5), and nstep = 2880 steps make one model year.  The
+ * year map y(T) = phi(y(0)) (section 4) is the unit of work of spin-up and of
+ * matrix-free Newton-Krylov solvers (section 6).
+ *
+ * Conventions (following the C form of the paper's interface, section 5.2):
+ * reals are double, counts are int, arrays are a pointer plus int sizes.
+ *
+ * State layout.  A state is a device array of n rows by W = nbatch*ntracer
+ * columns, row-major: y[i*W + b*ntracer + tr] is tracer tr of ensemble member
+ * b at grid point i.  Grid points of one water column are contiguous, surface
+ * first (section 5.1).
+ *
+ * Ownership.  The caller owns every buffer.  The library never allocates
+ * device memory: it works inside one caller-provided device workspace of
+ * tmm_workspace_bytes() bytes, which must stay allocated until tmm_destroy().
+ * Host arrays of the descriptor are read during tmm_create() only.
+ *
+ * Errors.  Every call returns TMM_OK (0) or a negative status; a call that
+ * fails validation changes nothing.  Kernels run asynchronously on the stream
+ * given at creation; calls that return host results (resid_host, J_host,
+ * dJdu_host) synchronise that stream and report device errors there.
+ * A handle is not thread-safe; use one handle per stream.
+ */
+#ifndef TMM_H
+#define TMM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tmm_ctx *tmm_handle;
+
+enum {
+    TMM_OK = 0,
+    TMM_EINVAL = -1,        /* invalid argument or descriptor */
+    TMM_ENOMEM = -2,        /* workspace too small */
+    TMM_EDEVICE = -3,       /* HIP runtime error */
+    TMM_ESTATE = -4,        /* call not valid in the handle's state (e.g. no parameters set) */
+    TMM_ENONFINITE = -5,    /* non-finite value found in a result */
+    TMM_EUNSUPPORTED = -6   /* valid request outside what this build supports */
+};
+
+/* Biogeochemical models (section 2.2).  Parameter order is the order of the
+ * paper's parameter table. */
+enum {
+    TMM_MODEL_N = 1,        /* 1 tracer (nutrient); u = alpha, K_H2O, K_N, K_I, b */
+    TMM_MODEL_NDOP = 2      /* PO4-DOP (section 2.2.1), 2 tracers;
+                               u = alpha, K_H2O, K_1, K_I, lambda'_2, sigma_2, b */
+};
+
+/* Directional derivative of the year map (section 6.1). */
+enum {
+    TMM_JVP_FD = 0,         /* finite difference (phi(y+h v) - phi(y))/h, h = 1e-8 |y|/|v| per member */
+    TMM_JVP_TANGENT = 1     /* exact forward-mode tangent */
+};
+
+typedef struct {
+    int n;                  /* wet grid points */
+    int ncol;               /* water columns */
+    int nlayer;             /* maximum layers per column (<= 64) */
+    const int *col_start;   /* [ncol+1] first row of each column; col_start[ncol] = n */
+    const double *lat;      /* [ncol] latitude of each column, degrees */
+    const double *area;     /* [ncol] horizontal area of each column, m^2 */
+    const double *dz;       /* [nlayer] layer heights h_k, m, surface first */
+    int nmat;               /* monthly matrices of each kind (12) */
+    int nstep;              /* steps per model year (2880); nstep/nmat must be even */
+    int model;              /* TMM_MODEL_* */
+    int neuphotic;          /* euphotic layers (2 in the paper's experiments, section 7) */
+    int nbatch_max;         /* largest ensemble (member count) the handle must hold */
+    int adjoint_nbatch_max; /* largest ensemble for tmm_year_adjoint (0 disables it) */
+    int ckpt_every;         /* steps between adjoint checkpoints; divides nstep (ignored if no adjoint) */
+    /* explicit (horizontal) matrices, CSR with one pattern for all months */
+    int ae_nnz;
+    const int *ae_rowptr;   /* [n+1] */
+    const int *ae_colidx;   /* [ae_nnz] */
+    const double *ae_val;   /* [nmat][ae_nnz] */
+    /* implicit (vertical) matrices, CSR; every entry must couple two points
+     * of the same water column (section 3: implicit operators act vertically) */
+    int ai_nnz;
+    const int *ai_rowptr;
+    const int *ai_colidx;
+    const double *ai_val;   /* [nmat][ai_nnz] */
+} tmm_desc;
+
+/* Device workspace size for a descriptor.  Returns TMM_EINVAL for a bad
+ * descriptor. */
+int tmm_workspace_bytes(const tmm_desc *desc, size_t *bytes);
+
+/* Validates the descriptor, converts the matrices to the device formats and
+ * uploads them into the workspace (device pointer, at least
+ * tmm_workspace_bytes() bytes, 256-byte aligned).  hip_stream is a
+ * hipStream_t (NULL = default stream) used by every later call. */
+int tmm_create(const tmm_desc *desc, void *dev_workspace, size_t bytes,
+               void *hip_stream, tmm_handle *out);
+
+/* Synchronises the stream and releases host-side state.  Safe on NULL. */
+int tmm_destroy(tmm_handle h);
+
+/* Sets nbatch parameter vectors (host array [nbatch][nparam], order of the
+ * paper's parameter table, section 2.2.1) and rebuilds the per-member
+ * tables (light attenuation, Martin-curve remineralisation).  Every
+ * parameter must be finite, K_1, K_I > 0, 0 <= sigma_2 <= 1. */
+int tmm_set_params(tmm_handle h, int nbatch, const double *u);
+
+/* One time step j (section 3): y_out = Ai(t_j)(Ae(t_j) y_in + dt q(y_in)).
+ * y_in, y_out: device, n x W, must not overlap. */
+int tmm_step(tmm_handle h, int j, const double *y_in, double *y_out);
+
+/* Model years (section 4).  Runs nyears years from y0 and writes the final
+ * state to y1 (device, n x W; y1 may equal y0).  years_per_member (host,
+ * [nbatch], nullable) gives per-member lengths <= nyears: member b stops after
+ * years_per_member[b] years and y1 holds its state then.  resid_host
+ * (nullable, [nyears][nbatch]) receives ||y - phi(y)||_2 of each member for
+ * each year it ran (0 afterwards); passing it synchronises. */
+int tmm_year(tmm_handle h, int nyears, const int *years_per_member,
+             const double *y0, double *y1, double *resid_host);
+
+/* Directional derivative of the year map (section 6.1): jv = phi'(y) v by
+ * mode TMM_JVP_FD or TMM_JVP_TANGENT; phi_y (nullable) receives phi(y).
+ * All device, n x W. */
+int tmm_year_jvp(tmm_handle h, int mode, const double *y, const double *v,
+                 double *phi_y, double *jv);
+
+/* Gradient of the least-squares misfit
+ *   J_b = sum_m sum_i sum_tr V_i (y_{s_m} - obs_m)^2 / (2 nmat V_tot),
+ * s_m = (m+1) nstep/nmat, over one model year from y0, by a discrete adjoint
+ * (the derivative route the paper names in sections 1.2, 6.1 and 9) with
+ * checkpoints every ckpt_every steps and recomputation in between.
+ * y0, obs ([nmat][n][W]) and dJdy0 (nullable, n x W) are device arrays;
+ * J_host [nbatch] and dJdu_host [nbatch][nparam] are host arrays.
+ * ckpt_every must equal the descriptor's value.  Synchronises. */
+int tmm_year_adjoint(tmm_handle h, const double *y0, const double *obs, int ckpt_every,
+                     double *J_host, double *dJdu_host, double *dJdy0);
+
+/* Static text for a status code. */
+const char *tmm_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

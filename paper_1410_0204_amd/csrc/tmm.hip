@@ -1,0 +1,816 @@
+// libtmm host code: descriptor validation, device formats, launches, and the
+// C ABI declared in include/tmm.h.
+//
+// The library allocates no device memory.  Everything lives in the caller's
+// workspace, laid out by plan_workspace().
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "tmm.h"
+#include "tmm_device.hpp"
+
+namespace {
+
+constexpr int kMaxTileRows = 256;          // rows per tile (LDS maps are sized for this)
+constexpr int kLdsBudget = 48 * 1024;      // dynamic LDS per workgroup
+constexpr size_t kAlign = 256;
+
+#define TMM_TRY(expr)                                   \
+    do {                                                \
+        if ((expr) != hipSuccess) return TMM_EDEVICE;   \
+    } while (0)
+
+#define TMM_LAUNCHED()                                  \
+    do {                                                \
+        if (hipGetLastError() != hipSuccess) return TMM_EDEVICE; \
+    } while (0)
+
+int ntracer_of(int model) { return model == TMM_MODEL_N ? 1 : model == TMM_MODEL_NDOP ? 2 : -1; }
+int nparam_of(int model) { return model == TMM_MODEL_N ? 5 : model == TMM_MODEL_NDOP ? 7 : -1; }
+
+// One partition of the water columns into tiles of at most max_rows rows.
+struct Tiling {
+    int max_rows = 0;
+    int ntile = 0;
+    std::vector<int> tile_col;   // host copy
+    int* d_tile_col = nullptr;
+};
+
+std::vector<int> make_tiles(const std::vector<int>& col_start, int max_rows) {
+    std::vector<int> t{0};
+    const int ncol = (int)col_start.size() - 1;
+    int rows = 0, cols = 0;
+    for (int c = 0; c < ncol; ++c) {
+        const int nc = col_start[c + 1] - col_start[c];
+        if (cols > 0 && (rows + nc > max_rows || cols == kMaxTileRows)) {
+            t.push_back(c);
+            rows = 0;
+            cols = 0;
+        }
+        rows += nc;
+        cols += 1;
+    }
+    t.push_back(ncol);
+    return t;
+}
+
+std::vector<int> tiling_sizes(int nlayer) {
+    std::vector<int> s;
+    for (int r : {std::max(nlayer, 32), 64, 128, 256})
+        if (r >= nlayer && r <= kMaxTileRows && std::find(s.begin(), s.end(), r) == s.end()) s.push_back(r);
+    return s;
+}
+
+// Host-side summary of a validated descriptor.
+struct Plan {
+    int n = 0, ncol = 0, nlayer = 0, nmat = 0, nstep = 0, model = 0, neu = 0;
+    int nbatch_max = 0, adj_nb = 0, ckpt = 0, ntr = 0, nparam = 0;
+    int npad = 0, ew = 0, etw = 0;
+    size_t nblk = 0;                       // sum of n_c^2
+    std::vector<int> col_start, tiles_sizes;
+    int ntile_max = 0;
+    // workspace offsets (bytes)
+    size_t o_ae, o_aecol, o_aet, o_aetcol, o_aicm, o_airm, o_colstart, o_blk, o_lat, o_area, o_dz;
+    std::vector<size_t> o_tiles;
+    size_t o_u, o_light, o_rho, o_drho, o_member, o_scol, o_dcol;
+    size_t o_ybuf[3], o_vbuf[2], o_part, o_vec, o_ubt, o_jpart, o_ckpt, o_seg, o_final, o_mu[2];
+    size_t vec_stride;
+    size_t total;
+};
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int validate(const tmm_desc* d, Plan& P) {
+    if (!d) return TMM_EINVAL;
+    if (d->n < 1 || d->ncol < 1 || d->nlayer < 1 || d->nlayer > tmm::kMaxLayers) return TMM_EINVAL;
+    if (!d->col_start || !d->lat || !d->area || !d->dz) return TMM_EINVAL;
+    if (ntracer_of(d->model) < 0) return TMM_EINVAL;
+    if (d->nmat < 1 || d->nstep < 1 || d->nstep % d->nmat || (d->nstep / d->nmat) % 2) return TMM_EINVAL;
+    if (d->neuphotic < 1 || d->neuphotic > d->nlayer) return TMM_EINVAL;
+    if (d->nbatch_max < 1 || d->adjoint_nbatch_max < 0 || d->adjoint_nbatch_max > d->nbatch_max) return TMM_EINVAL;
+    if (d->adjoint_nbatch_max > 0 && (d->ckpt_every < 1 || d->nstep % d->ckpt_every)) return TMM_EINVAL;
+    if (d->adjoint_nbatch_max * nparam_of(d->model) > 128) return TMM_EINVAL;
+    if (d->ae_nnz < d->n || !d->ae_rowptr || !d->ae_colidx || !d->ae_val) return TMM_EINVAL;
+    if (d->ai_nnz < d->n || !d->ai_rowptr || !d->ai_colidx || !d->ai_val) return TMM_EINVAL;
+    if (d->col_start[0] != 0 || d->col_start[d->ncol] != d->n) return TMM_EINVAL;
+    for (int c = 0; c < d->ncol; ++c) {
+        const int nc = d->col_start[c + 1] - d->col_start[c];
+        if (nc < 1 || nc > d->nlayer) return TMM_EINVAL;
+    }
+    for (int c = 0; c < d->ncol; ++c)
+        if (!std::isfinite(d->lat[c]) || !std::isfinite(d->area[c]) || d->area[c] <= 0.0) return TMM_EINVAL;
+    for (int k = 0; k < d->nlayer; ++k)
+        if (!std::isfinite(d->dz[k]) || d->dz[k] <= 0.0) return TMM_EINVAL;
+    auto check_csr = [&](const int* rp, const int* ci, int nnz) {
+        if (rp[0] != 0 || rp[d->n] != nnz) return false;
+        for (int i = 0; i < d->n; ++i)
+            if (rp[i + 1] < rp[i]) return false;
+        for (int e = 0; e < nnz; ++e)
+            if (ci[e] < 0 || ci[e] >= d->n) return false;
+        return true;
+    };
+    if (!check_csr(d->ae_rowptr, d->ae_colidx, d->ae_nnz)) return TMM_EINVAL;
+    if (!check_csr(d->ai_rowptr, d->ai_colidx, d->ai_nnz)) return TMM_EINVAL;
+    // implicit matrices act within water columns only
+    std::vector<int> row_col(d->n);
+    for (int c = 0; c < d->ncol; ++c)
+        for (int r = d->col_start[c]; r < d->col_start[c + 1]; ++r) row_col[r] = c;
+    for (int i = 0; i < d->n; ++i)
+        for (int e = d->ai_rowptr[i]; e < d->ai_rowptr[i + 1]; ++e)
+            if (row_col[d->ai_colidx[e]] != row_col[i]) return TMM_EINVAL;
+
+    P.n = d->n; P.ncol = d->ncol; P.nlayer = d->nlayer; P.nmat = d->nmat; P.nstep = d->nstep;
+    P.model = d->model; P.neu = d->neuphotic; P.nbatch_max = d->nbatch_max;
+    P.adj_nb = d->adjoint_nbatch_max; P.ckpt = P.adj_nb > 0 ? d->ckpt_every : 0;
+    P.ntr = ntracer_of(d->model); P.nparam = nparam_of(d->model);
+    P.npad = (d->n + 63) / 64 * 64;
+    P.col_start.assign(d->col_start, d->col_start + d->ncol + 1);
+    int ew = 0;
+    std::vector<int> tcount(d->n, 0);
+    for (int i = 0; i < d->n; ++i) {
+        ew = std::max(ew, d->ae_rowptr[i + 1] - d->ae_rowptr[i]);
+        for (int e = d->ae_rowptr[i]; e < d->ae_rowptr[i + 1]; ++e) tcount[d->ae_colidx[e]]++;
+    }
+    P.ew = ew;
+    P.etw = *std::max_element(tcount.begin(), tcount.end());
+    if (P.etw < 1) P.etw = 1;
+    P.nblk = 0;
+    for (int c = 0; c < d->ncol; ++c) {
+        const size_t nc = d->col_start[c + 1] - d->col_start[c];
+        P.nblk += nc * nc;
+    }
+    if (P.nblk > (size_t)INT32_MAX) return TMM_EUNSUPPORTED;
+    P.tiles_sizes = tiling_sizes(d->nlayer);
+    P.ntile_max = 0;
+    for (int r : P.tiles_sizes)
+        P.ntile_max = std::max(P.ntile_max, (int)make_tiles(P.col_start, r).size() - 1);
+
+    // workspace layout
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    const size_t nm = d->nmat, npad = P.npad;
+    P.o_ae = take(nm * P.ew * npad * 8);
+    P.o_aecol = take((size_t)P.ew * npad * 4);
+    P.o_aet = take(nm * P.etw * npad * 8);
+    P.o_aetcol = take((size_t)P.etw * npad * 4);
+    P.o_aicm = take(nm * P.nblk * 8);
+    P.o_airm = take(nm * P.nblk * 8);
+    P.o_colstart = take((size_t)(d->ncol + 1) * 4);
+    P.o_blk = take((size_t)d->ncol * 4);
+    P.o_lat = take((size_t)d->ncol * 8);
+    P.o_area = take((size_t)d->ncol * 8);
+    P.o_dz = take((size_t)d->nlayer * 8);
+    P.o_tiles.clear();
+    for (size_t t = 0; t < P.tiles_sizes.size(); ++t) P.o_tiles.push_back(take((size_t)(d->ncol + 1) * 4));
+    const size_t nbm = d->nbatch_max;
+    P.o_u = take(nbm * P.nparam * 8);
+    P.o_light = take(nbm * d->nlayer * 8);
+    P.o_rho = take(nbm * (d->nlayer + 1) * d->nlayer * 8);
+    P.o_drho = take(nbm * (d->nlayer + 1) * d->nlayer * 8);
+    P.o_member = take(nbm * 4);
+    P.o_scol = take(nbm * 4);
+    P.o_dcol = take(nbm * 4);
+    const size_t state = (size_t)d->n * nbm * P.ntr * 8;
+    for (auto& b : P.o_ybuf) b = take(state);
+    for (auto& b : P.o_vbuf) b = take(state);
+    const size_t nq = std::max<size_t>(nbm, (size_t)P.adj_nb * P.nparam);
+    P.o_part = take((size_t)P.ntile_max * nq * 8);
+    P.vec_stride = std::max<size_t>(std::max<size_t>(nbm, (size_t)P.adj_nb * P.nparam), 8);
+    P.o_vec = take(16 * P.vec_stride * 8);
+    if (P.adj_nb > 0) {
+        const size_t astate = (size_t)d->n * P.adj_nb * P.ntr * 8;
+        P.o_ubt = take((size_t)P.ntile_max * P.adj_nb * P.nparam * 8);
+        P.o_jpart = take(nm * P.ntile_max * P.adj_nb * 8);
+        P.o_ckpt = take((size_t)(d->nstep / P.ckpt) * astate);
+        P.o_seg = take((size_t)P.ckpt * astate);
+        P.o_final = take(astate);
+        P.o_mu[0] = take(astate);
+        P.o_mu[1] = take(astate);
+    } else {
+        P.o_ubt = P.o_jpart = P.o_ckpt = P.o_seg = P.o_final = P.o_mu[0] = P.o_mu[1] = 0;
+    }
+    P.total = o;
+    return TMM_OK;
+}
+
+}  // namespace
+
+struct tmm_ctx {
+    Plan P;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    std::vector<Tiling> tilings;
+    int nbatch = 0;            // members set by tmm_set_params
+    double vtot = 0.0;         // total wet volume
+    std::vector<int> h_member, h_scol, h_dcol;
+    std::vector<double> h_vec;
+
+    template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+
+    tmm::Grid grid(const Tiling& t) const {
+        tmm::Grid g;
+        g.n = P.n; g.npad = P.npad; g.nlayer = P.nlayer; g.neu = P.neu; g.nstep = P.nstep; g.nmat = P.nmat;
+        g.tile_col = t.d_tile_col;
+        g.col_start = at<int>(P.o_colstart);
+        g.blk_off = at<int>(P.o_blk);
+        g.lat = at<double>(P.o_lat);
+        g.area = at<double>(P.o_area);
+        g.dz = at<double>(P.o_dz);
+        return g;
+    }
+    tmm::Model model() const {
+        tmm::Model m;
+        m.model = P.model; m.ntr = P.ntr; m.nparam = P.nparam;
+        m.u = at<double>(P.o_u);
+        m.light = at<double>(P.o_light);
+        m.rho = at<double>(P.o_rho);
+        m.drho = at<double>(P.o_drho);
+        m.member = at<int>(P.o_member);
+        return m;
+    }
+    tmm::Mats mats() const {
+        tmm::Mats m;
+        m.ew = P.ew; m.etw = P.etw;
+        m.ae_month = (size_t)P.ew * P.npad;
+        m.aet_month = (size_t)P.etw * P.npad;
+        m.ai_month = P.nblk;
+        m.ae = at<double>(P.o_ae);
+        m.ae_col = at<int>(P.o_aecol);
+        m.aet = at<double>(P.o_aet);
+        m.aet_col = at<int>(P.o_aetcol);
+        m.ai_cm = at<double>(P.o_aicm);
+        m.ai_rm = at<double>(P.o_airm);
+        return m;
+    }
+    double* ybuf(int i) const { return at<double>(P.o_ybuf[i]); }
+    double* vbuf(int i) const { return at<double>(P.o_vbuf[i]); }
+    double* part() const { return at<double>(P.o_part); }
+    // small vectors: 16 rows of vec_stride doubles (per slot, or per slot and parameter)
+    double* vec(int row) const { return at<double>(P.o_vec) + (size_t)row * P.vec_stride; }
+
+    // Largest tiling whose rows fit the LDS budget for width W and mult buffers.
+    const Tiling& tiling_for(int W, int mult, int extra_bytes = 0) const {
+        const Tiling* best = &tilings.front();
+        for (const Tiling& t : tilings) {
+            const size_t lds = (size_t)t.max_rows * W * 8 * mult + extra_bytes;
+            if (lds <= (size_t)kLdsBudget && t.max_rows <= (W <= 4 ? 128 : kMaxTileRows)) best = &t;
+        }
+        return *best;
+    }
+};
+
+namespace {
+
+int launch_blocks(size_t work, int block = 256) {
+    size_t b = (work + block - 1) / block;
+    return (int)std::min<size_t>(std::max<size_t>(b, 1), 4096);
+}
+
+int fill(tmm_ctx* h, double* x, size_t len, double v) {
+    hipLaunchKernelGGL(tmm::k_fill, dim3(launch_blocks(len)), dim3(256), 0, h->stream, x, len, v);
+    TMM_LAUNCHED();
+    return TMM_OK;
+}
+
+int copy(tmm_ctx* h, double* dst, const double* src, size_t len) {
+    hipLaunchKernelGGL(tmm::k_copy, dim3(launch_blocks(len)), dim3(256), 0, h->stream, dst, src, len);
+    TMM_LAUNCHED();
+    return TMM_OK;
+}
+
+// Forward step j for nb state slots (W = nb*ntr); tangent when v != nullptr.
+int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const double* v, double* vo) {
+    const int W = nb * h->P.ntr;
+    const bool tangent = v != nullptr;
+    const Tiling& t = h->tiling_for(W, tangent ? 2 : 1);
+    const int CW = W == 1 ? 1 : 2;
+    const int tpr = (W + CW - 1) / CW;
+    const int block = W <= 4 ? 128 : 256;
+    const size_t lds = (size_t)t.max_rows * W * 8 * (tangent ? 2 : 1);
+    const double dtd = tmm::kDaysPerYear / h->P.nstep;
+    tmm::Grid g = h->grid(t);
+    tmm::Model md = h->model();
+    tmm::Mats mt = h->mats();
+    dim3 grid(t.ntile), blk(block);
+    if (CW == 1 && !tangent)
+        hipLaunchKernelGGL((tmm::k_step<1, false, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->stream,
+                           g, md, mt, W, tpr, j, dtd, y, yo, v, vo);
+    else if (CW == 1)
+        hipLaunchKernelGGL((tmm::k_step<1, true, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->stream,
+                           g, md, mt, W, tpr, j, dtd, y, yo, v, vo);
+    else if (!tangent)
+        hipLaunchKernelGGL((tmm::k_step<2, false, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->stream,
+                           g, md, mt, W, tpr, j, dtd, y, yo, v, vo);
+    else
+        hipLaunchKernelGGL((tmm::k_step<2, true, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->stream,
+                           g, md, mt, W, tpr, j, dtd, y, yo, v, vo);
+    TMM_LAUNCHED();
+    return TMM_OK;
+}
+
+// One model year for nb slots from y to out, ping-ponging through a, b.  The
+// last step writes out directly.  Tangent when v != nullptr (vout, va, vb).
+int run_year(tmm_ctx* h, int nb, const double* y, double* out, double* a, double* b,
+             const double* v = nullptr, double* vout = nullptr, double* va = nullptr, double* vb = nullptr) {
+    const double* cur = y;
+    const double* vcur = v;
+    for (int j = 0; j < h->P.nstep; ++j) {
+        const bool last = j == h->P.nstep - 1;
+        double* nxt = last ? out : (j % 2 == 0 ? a : b);
+        double* vnxt = v ? (last ? vout : (j % 2 == 0 ? va : vb)) : nullptr;
+        int rc = launch_step(h, j, nb, cur, nxt, vcur, vnxt);
+        if (rc) return rc;
+        cur = nxt;
+        vcur = vnxt;
+    }
+    return TMM_OK;
+}
+
+// part[tile][slot] = sum of weight*(a-b)^2 per slot, then out[slot] = scale*sum (sqrt optional).
+int sqdiff(tmm_ctx* h, int nb, const double* a, const double* b, int volume, double scale, int take_sqrt,
+           double* out, int accumulate = 0, double* part = nullptr, int part_stride_tiles = 0) {
+    const Tiling& t = h->tilings.front();
+    tmm::Grid g = h->grid(t);
+    double* pp = part ? part : h->part();
+    hipLaunchKernelGGL((tmm::k_tile_sqdiff<kMaxTileRows, kMaxTileRows>), dim3(t.ntile), dim3(256), 0, h->stream,
+                       g, nb * h->P.ntr, h->P.ntr, nb, a, b, volume, pp);
+    TMM_LAUNCHED();
+    (void)part_stride_tiles;
+    if (out) {
+        hipLaunchKernelGGL(tmm::k_sum_tiles, dim3(1), dim3(256), 0, h->stream, t.ntile, nb, nb, pp, scale,
+                           accumulate, take_sqrt, out);
+        TMM_LAUNCHED();
+    }
+    return TMM_OK;
+}
+
+int upload(tmm_ctx* h, void* dst, const void* src, size_t bytes) {
+    TMM_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
+    return TMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tmm_strerror(int status) {
+    switch (status) {
+        case TMM_OK: return "ok";
+        case TMM_EINVAL: return "invalid argument or descriptor";
+        case TMM_ENOMEM: return "workspace too small";
+        case TMM_EDEVICE: return "HIP runtime error";
+        case TMM_ESTATE: return "call not valid in the handle's state";
+        case TMM_ENONFINITE: return "non-finite value in a result";
+        case TMM_EUNSUPPORTED: return "unsupported request";
+        default: return "unknown status";
+    }
+}
+
+int tmm_workspace_bytes(const tmm_desc* desc, size_t* bytes) {
+    if (!bytes) return TMM_EINVAL;
+    Plan P;
+    int rc = validate(desc, P);
+    if (rc) return rc;
+    *bytes = P.total;
+    return TMM_OK;
+}
+
+int tmm_create(const tmm_desc* d, void* dev_workspace, size_t bytes, void* hip_stream, tmm_handle* out) {
+    if (!out || !dev_workspace) return TMM_EINVAL;
+    *out = nullptr;
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) return TMM_EINVAL;
+    tmm_ctx* h = new (std::nothrow) tmm_ctx();
+    if (!h) return TMM_ENOMEM;
+    int rc = validate(d, h->P);
+    if (rc) { delete h; return rc; }
+    if (bytes < h->P.total) { delete h; return TMM_ENOMEM; }
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->ws = static_cast<char*>(dev_workspace);
+    const Plan& P = h->P;
+    auto fail = [&](int code) { (void)hipStreamSynchronize(h->stream); delete h; return code; };
+
+    // Ae in slot-major ELL; padding entries point at the row itself with value 0.
+    {
+        std::vector<int> col((size_t)P.ew * P.npad);
+        std::vector<int> pos(d->ae_nnz);
+        for (int i = 0; i < P.npad; ++i) {
+            const int len = i < P.n ? d->ae_rowptr[i + 1] - d->ae_rowptr[i] : 0;
+            for (int s = 0; s < P.ew; ++s) {
+                const size_t at = (size_t)s * P.npad + i;
+                if (s < len) {
+                    const int e = d->ae_rowptr[i] + s;
+                    col[at] = d->ae_colidx[e];
+                    pos[e] = (int)at;
+                } else {
+                    col[at] = i < P.n ? i : 0;
+                }
+            }
+        }
+        if (upload(h, h->at<int>(P.o_aecol), col.data(), col.size() * 4)) return fail(TMM_EDEVICE);
+        std::vector<double> val((size_t)P.ew * P.npad);
+        for (int m = 0; m < P.nmat; ++m) {
+            std::fill(val.begin(), val.end(), 0.0);
+            const double* src = d->ae_val + (size_t)m * d->ae_nnz;
+            for (int e = 0; e < d->ae_nnz; ++e) val[pos[e]] = src[e];
+            if (upload(h, h->at<double>(P.o_ae) + (size_t)m * val.size(), val.data(), val.size() * 8))
+                return fail(TMM_EDEVICE);
+            if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(TMM_EDEVICE);
+        }
+        // Ae^T: row c of the transpose lists (i, a_ic) in increasing i
+        std::vector<int> tlen(P.npad, 0);
+        std::vector<int> tcol((size_t)P.etw * P.npad);
+        std::vector<int> tpos(d->ae_nnz);
+        for (int i = 0; i < P.n; ++i)
+            for (int e = d->ae_rowptr[i]; e < d->ae_rowptr[i + 1]; ++e) {
+                const int c = d->ae_colidx[e];
+                const size_t at = (size_t)tlen[c]++ * P.npad + c;
+                tcol[at] = i;
+                tpos[e] = (int)at;
+            }
+        for (int c = 0; c < P.npad; ++c)
+            for (int s = tlen[c]; s < P.etw; ++s) tcol[(size_t)s * P.npad + c] = c < P.n ? c : 0;
+        if (upload(h, h->at<int>(P.o_aetcol), tcol.data(), tcol.size() * 4)) return fail(TMM_EDEVICE);
+        std::vector<double> tval((size_t)P.etw * P.npad);
+        for (int m = 0; m < P.nmat; ++m) {
+            std::fill(tval.begin(), tval.end(), 0.0);
+            const double* src = d->ae_val + (size_t)m * d->ae_nnz;
+            for (int e = 0; e < d->ae_nnz; ++e) tval[tpos[e]] = src[e];
+            if (upload(h, h->at<double>(P.o_aet) + (size_t)m * tval.size(), tval.data(), tval.size() * 8))
+                return fail(TMM_EDEVICE);
+            if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(TMM_EDEVICE);
+        }
+    }
+    // Ai as dense per-column blocks, column-major and row-major.
+    {
+        std::vector<int> blk(P.ncol), row_col(P.n);
+        size_t off = 0;
+        for (int c = 0; c < P.ncol; ++c) {
+            blk[c] = (int)off;
+            const size_t nc = P.col_start[c + 1] - P.col_start[c];
+            off += nc * nc;
+            for (int r = P.col_start[c]; r < P.col_start[c + 1]; ++r) row_col[r] = c;
+        }
+        if (upload(h, h->at<int>(P.o_blk), blk.data(), blk.size() * 4)) return fail(TMM_EDEVICE);
+        std::vector<double> cm(P.nblk), rm(P.nblk);
+        for (int m = 0; m < P.nmat; ++m) {
+            std::fill(cm.begin(), cm.end(), 0.0);
+            std::fill(rm.begin(), rm.end(), 0.0);
+            const double* src = d->ai_val + (size_t)m * d->ai_nnz;
+            for (int i = 0; i < P.n; ++i) {
+                const int c = row_col[i];
+                const int nc = P.col_start[c + 1] - P.col_start[c];
+                const int k = i - P.col_start[c];
+                for (int e = d->ai_rowptr[i]; e < d->ai_rowptr[i + 1]; ++e) {
+                    const int s = d->ai_colidx[e] - P.col_start[c];
+                    cm[(size_t)blk[c] + (size_t)s * nc + k] += src[e];
+                    rm[(size_t)blk[c] + (size_t)k * nc + s] += src[e];
+                }
+            }
+            if (upload(h, h->at<double>(P.o_aicm) + (size_t)m * P.nblk, cm.data(), P.nblk * 8) ||
+                upload(h, h->at<double>(P.o_airm) + (size_t)m * P.nblk, rm.data(), P.nblk * 8))
+                return fail(TMM_EDEVICE);
+            if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(TMM_EDEVICE);
+        }
+    }
+    if (upload(h, h->at<int>(P.o_colstart), P.col_start.data(), P.col_start.size() * 4) ||
+        upload(h, h->at<double>(P.o_lat), d->lat, (size_t)P.ncol * 8) ||
+        upload(h, h->at<double>(P.o_area), d->area, (size_t)P.ncol * 8) ||
+        upload(h, h->at<double>(P.o_dz), d->dz, (size_t)P.nlayer * 8))
+        return fail(TMM_EDEVICE);
+    for (size_t t = 0; t < P.tiles_sizes.size(); ++t) {
+        Tiling tl;
+        tl.max_rows = P.tiles_sizes[t];
+        tl.tile_col = make_tiles(P.col_start, tl.max_rows);
+        tl.ntile = (int)tl.tile_col.size() - 1;
+        tl.d_tile_col = h->at<int>(P.o_tiles[t]);
+        if (upload(h, tl.d_tile_col, tl.tile_col.data(), tl.tile_col.size() * 4)) return fail(TMM_EDEVICE);
+        h->tilings.push_back(std::move(tl));
+    }
+    h->h_member.resize(P.nbatch_max);
+    h->h_scol.resize(P.nbatch_max);
+    h->h_dcol.resize(P.nbatch_max);
+    // total wet volume, for the misfit normalisation
+    {
+        const Tiling& t = h->tilings.front();
+        tmm::Grid g = h->grid(t);
+        hipLaunchKernelGGL((tmm::k_tile_volume<kMaxTileRows, kMaxTileRows>), dim3(t.ntile), dim3(256), 0,
+                           h->stream, g, h->part());
+        hipLaunchKernelGGL(tmm::k_sum_tiles, dim3(1), dim3(64), 0, h->stream, t.ntile, 1, 1, h->part(), 1.0, 0, 0,
+                           h->vec(15));
+        if (hipGetLastError() != hipSuccess) return fail(TMM_EDEVICE);
+        if (hipMemcpyAsync(&h->vtot, h->vec(15), 8, hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+            return fail(TMM_EDEVICE);
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(TMM_EDEVICE);
+    *out = h;
+    return TMM_OK;
+}
+
+int tmm_destroy(tmm_handle h) {
+    if (!h) return TMM_OK;
+    int rc = hipStreamSynchronize(h->stream) == hipSuccess ? TMM_OK : TMM_EDEVICE;
+    delete h;
+    return rc;
+}
+
+int tmm_set_params(tmm_handle h, int nbatch, const double* u) {
+    if (!h || !u || nbatch < 1 || nbatch > h->P.nbatch_max) return TMM_EINVAL;
+    const int np = h->P.nparam;
+    for (int b = 0; b < nbatch; ++b) {
+        const double* p = u + (size_t)b * np;
+        for (int i = 0; i < np; ++i)
+            if (!std::isfinite(p[i])) return TMM_EINVAL;
+        if (p[2] <= 0.0 || p[3] <= 0.0) return TMM_EINVAL;
+        if (h->P.model == TMM_MODEL_NDOP && (p[5] < 0.0 || p[5] > 1.0)) return TMM_EINVAL;
+    }
+    std::vector<double> uu(u, u + (size_t)nbatch * np);
+    if (upload(h, h->at<double>(h->P.o_u), uu.data(), uu.size() * 8)) return TMM_EDEVICE;
+    for (int b = 0; b < nbatch; ++b) h->h_member[b] = b;
+    if (upload(h, h->at<int>(h->P.o_member), h->h_member.data(), (size_t)nbatch * 4)) return TMM_EDEVICE;
+    const int total = nbatch * (h->P.nlayer + 1) * h->P.nlayer;
+    hipLaunchKernelGGL(tmm::k_param_tables, dim3((total + 255) / 256), dim3(256), 0, h->stream, nbatch, h->P.model,
+                       np, h->P.nlayer, h->P.neu, h->at<double>(h->P.o_u), h->at<double>(h->P.o_dz),
+                       h->at<double>(h->P.o_light), h->at<double>(h->P.o_rho), h->at<double>(h->P.o_drho));
+    TMM_LAUNCHED();
+    TMM_TRY(hipStreamSynchronize(h->stream));
+    h->nbatch = nbatch;
+    return TMM_OK;
+}
+
+int tmm_step(tmm_handle h, int j, const double* y_in, double* y_out) {
+    if (!h || !y_in || !y_out || y_in == y_out || j < 0) return TMM_EINVAL;
+    if (h->nbatch < 1) return TMM_ESTATE;
+    return launch_step(h, j, h->nbatch, y_in, y_out, nullptr, nullptr);
+}
+
+// Member map: slot s of the working state holds member h_member[s].
+static int push_member_map(tmm_handle h, int na) {
+    if (upload(h, h->at<int>(h->P.o_member), h->h_member.data(), (size_t)na * 4)) return TMM_EDEVICE;
+    TMM_TRY(hipStreamSynchronize(h->stream));
+    return TMM_OK;
+}
+
+int tmm_year(tmm_handle h, int nyears, const int* years_per_member, const double* y0, double* y1,
+             double* resid_host) {
+    if (!h || !y0 || !y1 || nyears < 0) return TMM_EINVAL;
+    const int nb = h->nbatch;
+    if (nb < 1) return TMM_ESTATE;
+    std::vector<int> left(nb, nyears);
+    if (years_per_member)
+        for (int b = 0; b < nb; ++b) {
+            if (years_per_member[b] < 0 || years_per_member[b] > nyears) return TMM_EINVAL;
+            left[b] = years_per_member[b];
+        }
+    const int ntr = h->P.ntr, Wf = nb * ntr;
+    const size_t n = h->P.n;
+    if (resid_host) std::fill(resid_host, resid_host + (size_t)nyears * nb, 0.0);
+
+    // working state: slot s holds member active[s]
+    std::vector<int> active;
+    for (int b = 0; b < nb; ++b) active.push_back(b);
+    int ib = 0;                    // ybuf index holding the current state
+    int rc = copy(h, h->ybuf(0), y0, n * Wf);
+    if (rc) return rc;
+
+    auto scatter_finished = [&](const std::vector<int>& slots, int Wc) -> int {
+        // copy finished slots of the working state into their member columns of y1
+        int k = 0;
+        for (int s : slots) {
+            h->h_scol[k] = s;
+            h->h_dcol[k] = active[s];
+            ++k;
+        }
+        if (!k) return TMM_OK;
+        if (upload(h, h->at<int>(h->P.o_scol), h->h_scol.data(), (size_t)k * 4) ||
+            upload(h, h->at<int>(h->P.o_dcol), h->h_dcol.data(), (size_t)k * 4))
+            return TMM_EDEVICE;
+        hipLaunchKernelGGL(tmm::k_gather_slots, dim3(launch_blocks(n * k * ntr)), dim3(256), 0, h->stream, n, k,
+                           ntr, Wc, Wf, h->at<int>(h->P.o_scol), h->at<int>(h->P.o_dcol), h->ybuf(ib), y1);
+        TMM_LAUNCHED();
+        TMM_TRY(hipStreamSynchronize(h->stream));
+        return TMM_OK;
+    };
+
+    // members with no years at all keep y0
+    {
+        std::vector<int> done;
+        for (size_t s = 0; s < active.size(); ++s)
+            if (left[active[s]] == 0) done.push_back((int)s);
+        if (!done.empty()) {
+            if ((rc = scatter_finished(done, Wf))) return rc;
+        }
+    }
+    std::vector<int> keep;
+    for (size_t s = 0; s < active.size(); ++s)
+        if (left[active[s]] > 0) keep.push_back((int)s);
+    // compact away members with no years
+    if (keep.size() != active.size() && !keep.empty()) {
+        const int other = (ib + 1) % 3;
+        for (size_t k = 0; k < keep.size(); ++k) { h->h_scol[k] = keep[k]; h->h_dcol[k] = (int)k; }
+        if (upload(h, h->at<int>(h->P.o_scol), h->h_scol.data(), keep.size() * 4) ||
+            upload(h, h->at<int>(h->P.o_dcol), h->h_dcol.data(), keep.size() * 4))
+            return TMM_EDEVICE;
+        hipLaunchKernelGGL(tmm::k_gather_slots, dim3(launch_blocks(n * keep.size() * ntr)), dim3(256), 0,
+                           h->stream, n, (int)keep.size(), ntr, Wf, (int)keep.size() * ntr,
+                           h->at<int>(h->P.o_scol), h->at<int>(h->P.o_dcol), h->ybuf(ib), h->ybuf(other));
+        TMM_LAUNCHED();
+        std::vector<int> na;
+        for (int s : keep) na.push_back(active[s]);
+        active = na;
+        ib = other;
+    }
+    if (keep.empty()) active.clear();
+    for (size_t s = 0; s < active.size(); ++s) h->h_member[s] = active[s];
+    if (!active.empty() && (rc = push_member_map(h, (int)active.size()))) return rc;
+
+    for (int yr = 0; yr < nyears && !active.empty(); ++yr) {
+        const int na = (int)active.size();
+        const int Wc = na * ntr;
+        const int ia = (ib + 1) % 3, iout = (ib + 2) % 3;
+        // year: ybuf(ib) -> ybuf(iout) via ybuf(ia) and ... ping-pong needs two scratch buffers
+        // besides the start: use ia and the v buffers' first slot.
+        rc = run_year(h, na, h->ybuf(ib), h->ybuf(iout), h->ybuf(ia), h->vbuf(0));
+        if (rc) return rc;
+        if (resid_host) {
+            rc = sqdiff(h, na, h->ybuf(iout), h->ybuf(ib), 0, 1.0, 1, h->vec(0));
+            if (rc) return rc;
+            std::vector<double> r(na);
+            TMM_TRY(hipMemcpyAsync(r.data(), h->vec(0), (size_t)na * 8, hipMemcpyDeviceToHost, h->stream));
+            TMM_TRY(hipStreamSynchronize(h->stream));
+            for (int s = 0; s < na; ++s) resid_host[(size_t)yr * nb + active[s]] = r[s];
+        }
+        ib = iout;
+        std::vector<int> fin, stay;
+        for (int s = 0; s < na; ++s) {
+            if (--left[active[s]] == 0) fin.push_back(s);
+            else stay.push_back(s);
+        }
+        if (!fin.empty()) {
+            if ((rc = scatter_finished(fin, Wc))) return rc;
+            if (!stay.empty()) {
+                const int other = (ib + 1) % 3;
+                for (size_t k = 0; k < stay.size(); ++k) { h->h_scol[k] = stay[k]; h->h_dcol[k] = (int)k; }
+                if (upload(h, h->at<int>(h->P.o_scol), h->h_scol.data(), stay.size() * 4) ||
+                    upload(h, h->at<int>(h->P.o_dcol), h->h_dcol.data(), stay.size() * 4))
+                    return TMM_EDEVICE;
+                hipLaunchKernelGGL(tmm::k_gather_slots, dim3(launch_blocks(n * stay.size() * ntr)), dim3(256), 0,
+                                   h->stream, n, (int)stay.size(), ntr, Wc, (int)stay.size() * ntr,
+                                   h->at<int>(h->P.o_scol), h->at<int>(h->P.o_dcol), h->ybuf(ib), h->ybuf(other));
+                TMM_LAUNCHED();
+                std::vector<int> na2;
+                for (int s : stay) na2.push_back(active[s]);
+                active = na2;
+                ib = other;
+                for (size_t s = 0; s < active.size(); ++s) h->h_member[s] = active[s];
+                if ((rc = push_member_map(h, (int)active.size()))) return rc;
+            } else {
+                active.clear();
+            }
+        }
+    }
+    // restore the identity member map for later calls
+    for (int b = 0; b < nb; ++b) h->h_member[b] = b;
+    if ((rc = push_member_map(h, nb))) return rc;
+    return TMM_OK;
+}
+
+int tmm_year_jvp(tmm_handle h, int mode, const double* y, const double* v, double* phi_y, double* jv) {
+    if (!h || !y || !v || !jv) return TMM_EINVAL;
+    if (mode != TMM_JVP_FD && mode != TMM_JVP_TANGENT) return TMM_EINVAL;
+    const int nb = h->nbatch;
+    if (nb < 1) return TMM_ESTATE;
+    const int ntr = h->P.ntr, W = nb * ntr;
+    const size_t n = h->P.n;
+    double* f0 = phi_y ? phi_y : h->ybuf(2);
+    if (mode == TMM_JVP_TANGENT)
+        return run_year(h, nb, y, f0, h->ybuf(0), h->ybuf(1), v, jv, h->vbuf(0), h->vbuf(1));
+    // finite differences: h_s = 1e-8 ||y_s|| / ||v_s||
+    int rc = sqdiff(h, nb, y, nullptr, 0, 1.0, 0, h->vec(1));
+    if (!rc) rc = sqdiff(h, nb, v, nullptr, 0, 1.0, 0, h->vec(2));
+    if (rc) return rc;
+    hipLaunchKernelGGL(tmm::k_fd_step, dim3(1), dim3(64), 0, h->stream, nb, h->vec(1), h->vec(2), h->vec(3));
+    TMM_LAUNCHED();
+    hipLaunchKernelGGL(tmm::k_axpy_slots, dim3(launch_blocks(n * W)), dim3(256), 0, h->stream, n, W, ntr,
+                       h->vec(3), y, v, h->vbuf(0));
+    TMM_LAUNCHED();
+    if ((rc = run_year(h, nb, y, f0, h->ybuf(0), h->ybuf(1)))) return rc;
+    if ((rc = run_year(h, nb, h->vbuf(0), jv, h->ybuf(0), h->ybuf(1)))) return rc;
+    hipLaunchKernelGGL(tmm::k_fd_quot, dim3(launch_blocks(n * W)), dim3(256), 0, h->stream, n, W, ntr, h->vec(3),
+                       jv, f0, jv);
+    TMM_LAUNCHED();
+    return TMM_OK;
+}
+
+int tmm_year_adjoint(tmm_handle h, const double* y0, const double* obs, int ckpt_every, double* J_host,
+                     double* dJdu_host, double* dJdy0) {
+    if (!h || !y0 || !obs || !J_host || !dJdu_host) return TMM_EINVAL;
+    const Plan& P = h->P;
+    if (P.adj_nb < 1) return TMM_EUNSUPPORTED;
+    if (ckpt_every != P.ckpt) return TMM_EINVAL;
+    const int nb = h->nbatch;
+    if (nb < 1) return TMM_ESTATE;
+    if (nb > P.adj_nb) return TMM_EUNSUPPORTED;
+    const int ntr = P.ntr, W = nb * ntr, np = P.nparam;
+    const size_t n = P.n, len = n * W;
+    const int K = P.ckpt, spm = P.nstep / P.nmat, nseg = P.nstep / K;
+    const double dtd = tmm::kDaysPerYear / P.nstep;
+    const Tiling& tl = h->tiling_for(W, 1, 256 * 8 * np);
+    tmm::Grid g = h->grid(tl);
+    tmm::Model md = h->model();
+    tmm::Mats mt = h->mats();
+    double* ckpt = h->at<double>(P.o_ckpt);
+    double* seg = h->at<double>(P.o_seg);
+    double* fin = h->at<double>(P.o_final);
+    double* mu[2] = {h->at<double>(P.o_mu[0]), h->at<double>(P.o_mu[1])};
+    double* ubt = h->at<double>(P.o_ubt);
+    double* jpart = h->at<double>(P.o_jpart);
+    const int ntile_m = h->tilings.front().ntile;   // misfit partials use the first tiling
+    int rc;
+    if ((rc = fill(h, ubt, (size_t)tl.ntile * nb * np, 0.0))) return rc;
+
+    auto ckpt_ptr = [&](int s) -> const double* { return s == 0 ? y0 : ckpt + (size_t)s * len; };
+    // forward sweep with checkpoints and misfit partials
+    {
+        const double* cur = y0;
+        for (int j = 0; j < P.nstep; ++j) {
+            const int nj = j + 1;
+            double* nxt;
+            if (nj == P.nstep) nxt = fin;
+            else if (nj % K == 0) nxt = ckpt + (size_t)(nj / K) * len;
+            else nxt = (cur == seg) ? seg + len : seg;          // two scratch slots of the segment store
+            if ((rc = launch_step(h, j, nb, cur, nxt, nullptr, nullptr))) return rc;
+            if (nj % spm == 0) {
+                const int m = nj / spm - 1;
+                rc = sqdiff(h, nb, nxt, obs + (size_t)m * len, 1, 1.0, 0, nullptr, 0,
+                            jpart + (size_t)m * ntile_m * nb);
+                if (rc) return rc;
+            }
+            cur = nxt;
+        }
+        hipLaunchKernelGGL(tmm::k_sum_tiles, dim3(1), dim3(256), 0, h->stream, P.nmat * ntile_m, nb, nb, jpart,
+                           1.0 / (2.0 * P.nmat * h->vtot), 0, 0, h->vec(4));
+        TMM_LAUNCHED();
+    }
+    const size_t lds = (size_t)tl.max_rows * W * 8 + (size_t)256 * np * 8;
+    auto adjoint = [&](int j, int use_ae, int use_ai, const double* mu_in, const double* yj, const double* ob,
+                       double* out) -> int {
+        const double sc = 1.0 / (P.nmat * h->vtot);
+        if (ntr == 2)
+            hipLaunchKernelGGL((tmm::k_adjoint<2, kMaxTileRows, kMaxTileRows>), dim3(tl.ntile), dim3(256), lds,
+                               h->stream, g, md, mt, W, nb, j, dtd, use_ae, use_ai, mu_in, yj, ob, sc, out,
+                               use_ae ? ubt : nullptr);
+        else
+            hipLaunchKernelGGL((tmm::k_adjoint<1, kMaxTileRows, kMaxTileRows>), dim3(tl.ntile), dim3(256), lds,
+                               h->stream, g, md, mt, W, nb, j, dtd, use_ae, use_ai, mu_in, yj, ob, sc, out,
+                               use_ae ? ubt : nullptr);
+        TMM_LAUNCHED();
+        return TMM_OK;
+    };
+    // head: lambda_nstep = misfit source of the last snapshot; mu_{nstep-1} = Ai^T lambda
+    int im = 0;
+    if ((rc = adjoint(P.nstep, 0, 1, nullptr, fin, obs + (size_t)(P.nmat - 1) * len, mu[im]))) return rc;
+    for (int s = nseg - 1; s >= 0; --s) {
+        const int base = s * K;
+        // replay the segment, keeping y_{base+1} .. y_{base+K-1}
+        const double* cur = ckpt_ptr(s);
+        for (int jj = base; jj < base + K - 1; ++jj) {
+            double* nxt = seg + (size_t)(jj + 1 - base) * len;
+            if ((rc = launch_step(h, jj, nb, cur, nxt, nullptr, nullptr))) return rc;
+            cur = nxt;
+        }
+        for (int j = base + K - 1; j >= base && j >= 1; --j) {
+            const double* yj = j == base ? ckpt_ptr(s) : seg + (size_t)(j - base) * len;
+            const double* ob = (j % spm == 0) ? obs + (size_t)(j / spm - 1) * len : nullptr;
+            if ((rc = adjoint(j, 1, 1, mu[im], yj, ob, mu[1 - im]))) return rc;
+            im = 1 - im;
+        }
+    }
+    // tail: lambda_0 = Ae(t_0)^T mu_0 + dt_d (dq/dy)(y_0)^T mu_0
+    double* l0 = dJdy0 ? dJdy0 : mu[1 - im];
+    if ((rc = adjoint(0, 1, 0, mu[im], y0, nullptr, l0))) return rc;
+    hipLaunchKernelGGL(tmm::k_sum_tiles, dim3(1), dim3(256), 0, h->stream, tl.ntile, nb * np, nb * np, ubt, 1.0, 0, 0,
+                       h->vec(5));
+    TMM_LAUNCHED();
+    std::vector<double> J(nb), G((size_t)nb * np);
+    TMM_TRY(hipMemcpyAsync(J.data(), h->vec(4), (size_t)nb * 8, hipMemcpyDeviceToHost, h->stream));
+    TMM_TRY(hipMemcpyAsync(G.data(), h->vec(5), (size_t)nb * np * 8, hipMemcpyDeviceToHost, h->stream));
+    TMM_TRY(hipStreamSynchronize(h->stream));
+    for (int b = 0; b < nb; ++b) {
+        if (!std::isfinite(J[b])) return TMM_ENONFINITE;
+        J_host[b] = J[b];
+    }
+    for (size_t i = 0; i < G.size(); ++i) {
+        if (!std::isfinite(G[i])) return TMM_ENONFINITE;
+        dJdu_host[i] = G[i];
+    }
+    return TMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,704 @@
+// Device code of libtmm: float64 kernels for gfx950.
+//
+// Method: Piwonski & Slawig, "The Idea and Concept of Metos3D" (arXiv
+// 1410.0204).  One time step (section 3)
+//     z = Ae(t_j) y_j + dt_d q(y_j, u),   y_{j+1} = Ai(t_j) z
+// with Ae, Ai linear interpolations of monthly matrices and q the PO4-DOP
+// model of section 2.2.1 evaluated per water column (section 5).
+//
+// Data layout on the device (built by the host code at creation):
+//  * Ae, Ae^T: ELL, slot-major: val[month][slot][npad], col[slot][npad].
+//    Lanes of a wavefront own consecutive rows, so every slot is one
+//    coalesced 512-byte read of values and a 256-byte read of indices.
+//  * Ai: one dense n_c x n_c block per water column (the implicit operator
+//    acts within columns only, section 3), stored column-major ("cm", lanes
+//    = rows of the forward product) and row-major ("rm", lanes = rows of the
+//    transposed product).
+//  * States: row-major n x W (W = members * tracers), so the W values of a
+//    grid point are contiguous.
+//  * Tiles: a tile is a run of whole water columns; one workgroup owns one
+//    tile, stages z (or the adjoint lambda) of its rows in LDS and applies
+//    the column blocks from there.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tmm {
+
+constexpr int kMaxLayers = 64;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSigmaPar = 0.4;       // photosynthetically available fraction of I_SWR
+constexpr double kSigmaIce = 0.0;       // no ice in the synthetic forcing
+constexpr double kSolarConstant = 1361.0;
+constexpr double kDaysPerYear = 360.0;  // section 5.1
+
+enum { MODEL_N = 1, MODEL_NDOP = 2 };
+
+struct BgcParams {
+    double alpha, kw, k1, ki, lam, sig, b;
+};
+
+__device__ __forceinline__ BgcParams load_params(const double* __restrict__ u, int model, int nparam, int m) {
+    const double* p = u + (size_t)m * nparam;
+    BgcParams r;
+    r.alpha = p[0];
+    r.kw = p[1];
+    r.k1 = p[2];
+    r.ki = p[3];
+    if (model == MODEL_NDOP) {
+        r.lam = p[4];
+        r.sig = p[5];
+        r.b = p[6];
+    } else {
+        r.lam = 0.0;
+        r.sig = 0.0;
+        r.b = p[4];
+    }
+    return r;
+}
+
+// Month pair and weight of step j: monthly matrices sit at mid-month and the
+// year is periodic (section 3).  Integer arithmetic, one exact division.
+__device__ __forceinline__ void step_phase(int j, int nstep, int nmat, int& k0, int& k1, double& w) {
+    const int spm = nstep / nmat;
+    int jj = j % nstep;
+    if (jj < 0) jj += nstep;
+    int tau = jj - spm / 2;
+    int kk = tau >= 0 ? tau / spm : -((-tau + spm - 1) / spm);
+    int r = tau - kk * spm;
+    kk %= nmat;
+    if (kk < 0) kk += nmat;
+    k0 = kk;
+    k1 = kk + 1 == nmat ? 0 : kk + 1;
+    w = (double)r / (double)spm;
+}
+
+// Daily-mean top-of-atmosphere short-wave radiation at latitude lat (deg) and
+// time t (fraction of the 360-day year): I_SWR of section 2.2.1.
+__device__ __forceinline__ double insolation(double lat_deg, double t) {
+    const double decl = -23.44 * kPi / 180.0 * cos(2.0 * kPi * (t + 10.0 / kDaysPerYear));
+    const double phi = lat_deg * kPi / 180.0;
+    const double x = -tan(phi) * tan(decl);
+    double h0;
+    if (x >= 1.0) h0 = 0.0;
+    else if (x <= -1.0) h0 = kPi;
+    else h0 = acos(x);
+    const double q = kSolarConstant / kPi * (h0 * sin(phi) * sin(decl) + cos(phi) * cos(decl) * sin(h0));
+    return q > 0.0 ? q : 0.0;
+}
+
+// Production f = alpha N+/(N+ + K_1) * I/(I + K_I) (section 2.2.1) and
+// derivatives.  I = I_SWR sigma_PAR (1 - sigma_ice) exp(-z K_H2O); the
+// exponential factor comes from the per-member light table.
+struct Production {
+    double f, dfdN, limN, limI, I;
+};
+
+__device__ __forceinline__ Production production(const BgcParams& p, double N, double Q, double light) {
+    Production r;
+    r.I = Q * kSigmaPar * (1.0 - kSigmaIce) * light;
+    const double Np = N > 0.0 ? N : 0.0;
+    r.limN = Np / (Np + p.k1);
+    r.limI = r.I / (r.I + p.ki);
+    r.f = p.alpha * r.limN * r.limI;
+    r.dfdN = N > 0.0 ? p.alpha * p.k1 / ((N + p.k1) * (N + p.k1)) * r.limI : 0.0;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Per-member tables: light attenuation exp(-z_k K_H2O) at layer centres and
+// the Martin-curve remineralisation fractions rho_k (per metre) with
+// d rho_k / d b, for every column depth n_c.
+// Layout: light[m][k], rho[(m*(nlayer+1) + n_c)*nlayer + k].
+// ---------------------------------------------------------------------------
+__global__ void k_param_tables(int nbatch, int model, int nparam, int nlayer, int neu,
+                               const double* __restrict__ u, const double* __restrict__ dz,
+                               double* __restrict__ light, double* __restrict__ rho,
+                               double* __restrict__ drho) {
+    const int per_member = (nlayer + 1) * nlayer;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nbatch * per_member) return;
+    const int m = idx / per_member;
+    const int rem = idx % per_member;
+    const int nc = rem / nlayer;
+    const int k = rem % nlayer;
+    const BgcParams p = load_params(u, model, nparam, m);
+
+    auto bottom = [&](int kk) {
+        double d = 0.0;
+        for (int i = 0; i <= kk; ++i) d += dz[i];
+        return d;
+    };
+    if (nc == 0) {
+        const double z = bottom(k) - 0.5 * dz[k];
+        light[(size_t)m * nlayer + k] = exp(-z * p.kw);
+    }
+    double r = 0.0, dr = 0.0;
+    if (nc >= 1 && k < nc) {
+        if (nc <= neu) {
+            r = k == nc - 1 ? 1.0 / dz[k] : 0.0;
+        } else if (k >= neu) {
+            const double lp = bottom(neu - 1);
+            const double ztop = bottom(k - 1);
+            const double mtop = pow(ztop / lp, -p.b);
+            const double dmtop = -log(ztop / lp) * mtop;
+            double mbot = 0.0, dmbot = 0.0;
+            if (k < nc - 1) {
+                const double zbot = bottom(k);
+                mbot = pow(zbot / lp, -p.b);
+                dmbot = -log(zbot / lp) * mbot;
+            }
+            r = (mtop - mbot) / dz[k];
+            dr = (dmtop - dmbot) / dz[k];
+        }
+    }
+    rho[idx] = r;
+    drho[idx] = dr;
+}
+
+// ---------------------------------------------------------------------------
+// Arguments shared by the step kernels.
+// ---------------------------------------------------------------------------
+struct Grid {
+    int n, npad, nlayer, neu, nstep, nmat;
+    const int* tile_col;     // [ntile+1] first column of each tile
+    const int* col_start;    // [ncol+1]
+    const int* blk_off;      // [ncol] offset of each column's Ai block
+    const double* lat;       // [ncol]
+    const double* area;      // [ncol]
+    const double* dz;        // [nlayer]
+};
+
+struct Model {
+    int model, ntr, nparam;
+    const double* u;         // [members][nparam]
+    const double* light;     // [members][nlayer]
+    const double* rho;       // [members][nlayer+1][nlayer]
+    const double* drho;
+    const int* member;       // [slots] parameter row of each state slot
+};
+
+struct Mats {
+    int ew;                  // ELL width of Ae
+    int etw;                 // ELL width of Ae^T
+    size_t ae_month;         // values per month of the ELL array (ew*npad)
+    size_t aet_month;
+    size_t ai_month;         // values per month of the block array
+    const double* ae;        // [nmat][ew][npad]
+    const int* ae_col;       // [ew][npad]
+    const double* aet;       // [nmat][etw][npad]
+    const int* aet_col;
+    const double* ai_cm;     // [nmat][blocks] column-major blocks
+    const double* ai_rm;     // [nmat][blocks] row-major blocks
+};
+
+// LDS map of a tile: for every local row its local column and layer, and per
+// column its first local row, depth and insolation at the current step.
+struct TileMap {
+    int c0, r0, nrows, ncols;
+};
+
+template <int MAXR, int MAXC>
+struct TileLds {
+    short row_col[MAXR];
+    short row_k[MAXR];
+    short col_r0[MAXC];
+    short col_nc[MAXC];
+    double Q[MAXC];
+};
+
+template <int MAXR, int MAXC>
+__device__ __forceinline__ TileMap build_tile(const Grid& g, TileLds<MAXR, MAXC>& L, double t) {
+    TileMap tm;
+    tm.c0 = g.tile_col[blockIdx.x];
+    const int c1 = g.tile_col[blockIdx.x + 1];
+    tm.ncols = c1 - tm.c0;
+    tm.r0 = g.col_start[tm.c0];
+    tm.nrows = g.col_start[c1] - tm.r0;
+    for (int lc = threadIdx.x; lc < tm.ncols; lc += blockDim.x) {
+        const int c = tm.c0 + lc;
+        const int s = g.col_start[c] - tm.r0;
+        const int nc = g.col_start[c + 1] - g.col_start[c];
+        L.col_r0[lc] = (short)s;
+        L.col_nc[lc] = (short)nc;
+        L.Q[lc] = t >= 0.0 ? insolation(g.lat[c], t) : 0.0;
+        for (int k = 0; k < nc; ++k) {
+            L.row_col[s + k] = (short)lc;
+            L.row_k[s + k] = (short)k;
+        }
+    }
+    __syncthreads();
+    return tm;
+}
+
+// Biogeochemistry of one (row, member) of the PO4-DOP / N model (sections
+// 2.2.1 and 5): q for both tracers, from the member's state in the rows of
+// the row's water column.  Production runs in the euphotic layers, the export
+// Phi = sum_k h_k f_k is remineralised below by the Martin curve, DOP decays
+// with rate lambda'_2.
+struct ColumnRef {
+    int rs;       // global first row of the column
+    int nc;       // depth
+    int k;        // layer of this row
+    double Q;     // insolation
+};
+
+__device__ __forceinline__ void bgc_q(const Grid& g, const Model& md, const double* __restrict__ y, int W,
+                                      const ColumnRef& c, int slot, double& q1, double& q2) {
+    const int m = md.member[slot];
+    const BgcParams p = load_params(md.u, md.model, md.nparam, m);
+    const double* light = md.light + (size_t)m * g.nlayer;
+    const int ne = c.nc < g.neu ? c.nc : g.neu;
+    double Phi = 0.0, fk = 0.0;
+    for (int e = 0; e < ne; ++e) {
+        const double N = y[(size_t)(c.rs + e) * W + slot * md.ntr];
+        const double f = production(p, N, c.Q, light[e]).f;
+        Phi += g.dz[e] * f;
+        if (e == c.k) fk = f;
+    }
+    const double rho = md.rho[((size_t)m * (g.nlayer + 1) + c.nc) * g.nlayer + c.k];
+    const double dop = md.ntr > 1 ? y[(size_t)(c.rs + c.k) * W + slot * md.ntr + 1] : 0.0;
+    q1 = -fk + p.lam * dop + (1.0 - p.sig) * Phi * rho;
+    q2 = p.sig * fk - p.lam * dop;
+}
+
+// Tangent of bgc_q in direction v.
+__device__ __forceinline__ void bgc_q_tangent(const Grid& g, const Model& md, const double* __restrict__ y,
+                                              const double* __restrict__ v, int W, const ColumnRef& c,
+                                              int slot, double& q1, double& q2) {
+    const int m = md.member[slot];
+    const BgcParams p = load_params(md.u, md.model, md.nparam, m);
+    const double* light = md.light + (size_t)m * g.nlayer;
+    const int ne = c.nc < g.neu ? c.nc : g.neu;
+    double Phid = 0.0, fdk = 0.0;
+    for (int e = 0; e < ne; ++e) {
+        const size_t at = (size_t)(c.rs + e) * W + slot * md.ntr;
+        const double fd = production(p, y[at], c.Q, light[e]).dfdN * v[at];
+        Phid += g.dz[e] * fd;
+        if (e == c.k) fdk = fd;
+    }
+    const double rho = md.rho[((size_t)m * (g.nlayer + 1) + c.nc) * g.nlayer + c.k];
+    const double dopd = md.ntr > 1 ? v[(size_t)(c.rs + c.k) * W + slot * md.ntr + 1] : 0.0;
+    q1 = -fdk + p.lam * dopd + (1.0 - p.sig) * Phid * rho;
+    q2 = p.sig * fdk - p.lam * dopd;
+}
+
+// ---------------------------------------------------------------------------
+// Forward step (and its tangent).  One workgroup per tile; thread task =
+// (row, group of CW state columns).  Phase A: z = Ae(t_j) y + dt_d q(y) into
+// LDS.  Phase B: y_out = Ai(t_j) z from LDS.
+// ---------------------------------------------------------------------------
+template <int CW, bool TANGENT, int MAXR, int MAXC>
+__global__ void k_step(Grid g, Model md, Mats mt, int W, int tpr, int j, double dtd,
+                       const double* __restrict__ y, double* __restrict__ yo,
+                       const double* __restrict__ v, double* __restrict__ vo) {
+    extern __shared__ double s_dyn[];
+    __shared__ TileLds<MAXR, MAXC> L;
+    int k0, k1;
+    double w;
+    step_phase(j, g.nstep, g.nmat, k0, k1, w);
+    const double t = (double)(j % g.nstep) / (double)g.nstep;
+    const TileMap tm = build_tile<MAXR, MAXC>(g, L, t);
+    double* s_z = s_dyn;                                   // [nrows][W]
+    double* s_zd = s_dyn + (size_t)tm.nrows * W;           // tangent [nrows][W]
+
+    const double* ae0 = mt.ae + (size_t)k0 * mt.ae_month;
+    const double* ae1 = mt.ae + (size_t)k1 * mt.ae_month;
+    const double om = 1.0 - w;
+    const int ntask = tm.nrows * tpr;
+
+    for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
+        const int rr = task / tpr;
+        const int wc0 = (task % tpr) * CW;
+        const int r = tm.r0 + rr;
+        const int lc = L.row_col[rr];
+        ColumnRef c;
+        c.rs = tm.r0 + L.col_r0[lc];
+        c.nc = L.col_nc[lc];
+        c.k = L.row_k[rr];
+        c.Q = L.Q[lc];
+
+        double acc[CW], accd[CW];
+#pragma unroll
+        for (int cc = 0; cc < CW; ++cc) { acc[cc] = 0.0; accd[cc] = 0.0; }
+        for (int s = 0; s < mt.ew; ++s) {
+            const size_t e = (size_t)s * g.npad + r;
+            const int col = mt.ae_col[e];
+            const double a = om * ae0[e] + w * ae1[e];
+#pragma unroll
+            for (int cc = 0; cc < CW; ++cc) {
+                if (wc0 + cc < W) {
+                    acc[cc] += a * y[(size_t)col * W + wc0 + cc];
+                    if (TANGENT) accd[cc] += a * v[(size_t)col * W + wc0 + cc];
+                }
+            }
+        }
+        // sources: one BGC evaluation per member, both tracers
+#pragma unroll
+        for (int cc = 0; cc < CW; ++cc) {
+            const int wc = wc0 + cc;
+            if (wc >= W) break;
+            const int tr = wc % md.ntr;
+            if (tr != 0 && cc != 0) continue;   // computed with its tracer-0 column
+            const int slot = wc / md.ntr;
+            double q1, q2;
+            bgc_q(g, md, y, W, c, slot, q1, q2);
+            double qd1 = 0.0, qd2 = 0.0;
+            if (TANGENT) bgc_q_tangent(g, md, y, v, W, c, slot, qd1, qd2);
+            if (tr == 0) {
+                acc[cc] += dtd * q1;
+                if (TANGENT) accd[cc] += dtd * qd1;
+                if (md.ntr > 1 && cc + 1 < CW && wc + 1 < W) {
+                    acc[cc + 1] += dtd * q2;
+                    if (TANGENT) accd[cc + 1] += dtd * qd2;
+                }
+            } else {   // first column of this thread is tracer 1 of its member
+                acc[cc] += dtd * q2;
+                if (TANGENT) accd[cc] += dtd * qd2;
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < CW; ++cc) {
+            if (wc0 + cc < W) {
+                s_z[(size_t)rr * W + wc0 + cc] = acc[cc];
+                if (TANGENT) s_zd[(size_t)rr * W + wc0 + cc] = accd[cc];
+            }
+        }
+    }
+    __syncthreads();
+
+    const double* ai0 = mt.ai_cm + (size_t)k0 * mt.ai_month;
+    const double* ai1 = mt.ai_cm + (size_t)k1 * mt.ai_month;
+    for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
+        const int rr = task / tpr;
+        const int wc0 = (task % tpr) * CW;
+        const int r = tm.r0 + rr;
+        const int lc = L.row_col[rr];
+        const int lr0 = L.col_r0[lc];
+        const int nc = L.col_nc[lc];
+        const int k = L.row_k[rr];
+        const size_t blk = (size_t)g.blk_off[tm.c0 + lc];
+        double acc[CW], accd[CW];
+#pragma unroll
+        for (int cc = 0; cc < CW; ++cc) { acc[cc] = 0.0; accd[cc] = 0.0; }
+        for (int s = 0; s < nc; ++s) {
+            const size_t e = blk + (size_t)s * nc + k;
+            const double a = om * ai0[e] + w * ai1[e];
+#pragma unroll
+            for (int cc = 0; cc < CW; ++cc) {
+                if (wc0 + cc < W) {
+                    acc[cc] += a * s_z[(size_t)(lr0 + s) * W + wc0 + cc];
+                    if (TANGENT) accd[cc] += a * s_zd[(size_t)(lr0 + s) * W + wc0 + cc];
+                }
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < CW; ++cc) {
+            if (wc0 + cc < W) {
+                yo[(size_t)r * W + wc0 + cc] = acc[cc];
+                if (TANGENT) vo[(size_t)r * W + wc0 + cc] = accd[cc];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint step (reverse mode of k_step).  With mu_j the cotangent of z_j:
+//   lambda_j = Ae(t_j)^T mu_j + dt_d (dq/dy)(y_j)^T mu_j + s_j
+//   mu_{j-1} = Ai(t_{j-1})^T lambda_j
+//   ubar    += dt_d (dq/du)(y_j)^T mu_j        (per-tile partial sums)
+// s_j is the misfit source at month ends.  use_ae = false starts the sweep
+// from the source alone; use_ai = false ends it, writing lambda_0.
+// Thread task = (row, member); NTR = tracers per member.
+// ---------------------------------------------------------------------------
+template <int NTR, int MAXR, int MAXC>
+__global__ void k_adjoint(Grid g, Model md, Mats mt, int W, int nb, int j, double dtd,
+                          int use_ae, int use_ai, const double* __restrict__ mu,
+                          const double* __restrict__ yj, const double* __restrict__ obs, double src_scale,
+                          double* __restrict__ out, double* __restrict__ ubar_tile) {
+    extern __shared__ double s_dyn[];
+    __shared__ TileLds<MAXR, MAXC> L;
+    constexpr int NP = NTR == 2 ? 7 : 5;
+    const double t = (double)(j % g.nstep) / (double)g.nstep;
+    const TileMap tm = build_tile<MAXR, MAXC>(g, L, use_ae ? t : -1.0);
+    double* s_lam = s_dyn;                                  // [nrows][W]
+    double* s_contrib = s_dyn + (size_t)tm.nrows * W;       // [blockDim][NP]
+
+    int k0, k1;
+    double w;
+    step_phase(j, g.nstep, g.nmat, k0, k1, w);
+    const double om = 1.0 - w;
+    const double* aet0 = mt.aet + (size_t)k0 * mt.aet_month;
+    const double* aet1 = mt.aet + (size_t)k1 * mt.aet_month;
+    const int ntask = tm.nrows * nb;
+    const int passes = (ntask + blockDim.x - 1) / blockDim.x;
+    // reduction threads: (member, parameter) pairs, accumulate over passes
+    double ured = 0.0;
+
+    for (int pass = 0; pass < passes; ++pass) {
+        const int task = pass * blockDim.x + threadIdx.x;
+        double contrib[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) contrib[p] = 0.0;
+        if (task < ntask) {
+            const int rr = task / nb;
+            const int slot = task % nb;
+            const int r = tm.r0 + rr;
+            const int lc = L.row_col[rr];
+            ColumnRef c;
+            c.rs = tm.r0 + L.col_r0[lc];
+            c.nc = L.col_nc[lc];
+            c.k = L.row_k[rr];
+            c.Q = L.Q[lc];
+            double lam[NTR];
+#pragma unroll
+            for (int tr = 0; tr < NTR; ++tr) lam[tr] = 0.0;
+            if (use_ae) {
+                for (int s = 0; s < mt.etw; ++s) {
+                    const size_t e = (size_t)s * g.npad + r;
+                    const int col = mt.aet_col[e];
+                    const double a = om * aet0[e] + w * aet1[e];
+#pragma unroll
+                    for (int tr = 0; tr < NTR; ++tr) lam[tr] += a * mu[(size_t)col * W + slot * NTR + tr];
+                }
+                // (dq/dy)^T mu and (dq/du)^T mu for this row
+                const int m = md.member[slot];
+                const BgcParams p = load_params(md.u, md.model, md.nparam, m);
+                const double* light = md.light + (size_t)m * g.nlayer;
+                const size_t tab = ((size_t)m * (g.nlayer + 1) + c.nc) * g.nlayer;
+                const int ne = c.nc < g.neu ? c.nc : g.neu;
+                double Phi = 0.0;
+                for (int e = 0; e < ne; ++e) {
+                    const double N = yj[(size_t)(c.rs + e) * W + slot * NTR];
+                    Phi += g.dz[e] * production(p, N, c.Q, light[e]).f;
+                }
+                const size_t at = (size_t)r * W + slot * NTR;
+                const double mu1 = mu[at];
+                const double mu2 = NTR > 1 ? mu[at + 1] : 0.0;
+                const double dop = NTR > 1 ? yj[at + 1] : 0.0;
+                const double rho = md.rho[tab + c.k];
+                const double drho = md.drho[tab + c.k];
+                double ybar1 = 0.0, ybar2 = 0.0;
+                if (c.k < g.neu) {
+                    double Phibar = 0.0;
+                    for (int kk = 0; kk < c.nc; ++kk)
+                        Phibar += (1.0 - p.sig) * md.rho[tab + kk] * mu[(size_t)(c.rs + kk) * W + slot * NTR];
+                    const Production pr = production(p, yj[at], c.Q, light[c.k]);
+                    const double fbar = -mu1 + p.sig * mu2 + g.dz[c.k] * Phibar;
+                    ybar1 = fbar * pr.dfdN;
+                    // df/dalpha, df/dK_H2O, df/dK_1, df/dK_I
+                    const double Np = yj[at] > 0.0 ? yj[at] : 0.0;
+                    const double zc = [&] {
+                        double d = 0.0;
+                        for (int i = 0; i <= c.k; ++i) d += g.dz[i];
+                        return d - 0.5 * g.dz[c.k];
+                    }();
+                    const double IKI2 = (pr.I + p.ki) * (pr.I + p.ki);
+                    contrib[0] += fbar * pr.limN * pr.limI;
+                    contrib[1] += fbar * p.alpha * pr.limN * p.ki / IKI2 * (-zc * pr.I);
+                    contrib[2] += fbar * (-p.alpha * Np / ((Np + p.k1) * (Np + p.k1)) * pr.limI);
+                    contrib[3] += fbar * (-p.alpha * pr.limN * pr.I / IKI2);
+                    if (NTR > 1) contrib[5] += pr.f * mu2;
+                }
+                if (NTR > 1) {
+                    ybar2 = p.lam * (mu1 - mu2);
+                    contrib[4] += dop * (mu1 - mu2);
+                    contrib[5] += -Phi * rho * mu1;
+                    contrib[NP - 1] += (1.0 - p.sig) * Phi * drho * mu1;
+                    lam[1] += dtd * ybar2;
+                } else {
+                    contrib[NP - 1] += (1.0 - p.sig) * Phi * drho * mu1;
+                }
+                lam[0] += dtd * ybar1;
+            }
+            if (obs) {
+                const int lk = c.k;
+                const double V = g.area[tm.c0 + lc] * g.dz[lk];
+#pragma unroll
+                for (int tr = 0; tr < NTR; ++tr) {
+                    const size_t at = (size_t)r * W + slot * NTR + tr;
+                    lam[tr] += V * (yj[at] - obs[at]) * src_scale;
+                }
+            }
+#pragma unroll
+            for (int tr = 0; tr < NTR; ++tr) s_lam[(size_t)rr * W + slot * NTR + tr] = lam[tr];
+        }
+        if (ubar_tile) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p) s_contrib[(size_t)threadIdx.x * NP + p] = contrib[p];
+            __syncthreads();
+            // thread (slot, p) sums the rows of this pass in a fixed order; task
+            // pass*blockDim + tt belongs to slot (pass*blockDim + tt) % nb
+            if ((int)threadIdx.x < nb * NP) {
+                const int slot = threadIdx.x / NP, p = threadIdx.x % NP;
+                const int lim = min((int)blockDim.x, ntask - pass * (int)blockDim.x);
+                const int first = (slot - (pass * (int)blockDim.x) % nb + nb) % nb;
+                double s = 0.0;
+                for (int tt = first; tt < lim; tt += nb) s += s_contrib[(size_t)tt * NP + p];
+                ured += s;
+            }
+            __syncthreads();
+        }
+    }
+    if (ubar_tile && (int)threadIdx.x < nb * NP)
+        ubar_tile[(size_t)blockIdx.x * nb * NP + threadIdx.x] += dtd * ured;
+    __syncthreads();
+
+    // mu_{j-1} = Ai(t_{j-1})^T lambda_j, or lambda_j itself at the end
+    int q0, q1;
+    double wq;
+    step_phase(j - 1, g.nstep, g.nmat, q0, q1, wq);
+    const double omq = 1.0 - wq;
+    const double* ai0 = mt.ai_rm + (size_t)q0 * mt.ai_month;
+    const double* ai1 = mt.ai_rm + (size_t)q1 * mt.ai_month;
+    for (int task = threadIdx.x; task < ntask; task += blockDim.x) {
+        const int rr = task / nb;
+        const int slot = task % nb;
+        const int r = tm.r0 + rr;
+        if (!use_ai) {
+#pragma unroll
+            for (int tr = 0; tr < NTR; ++tr)
+                out[(size_t)r * W + slot * NTR + tr] = s_lam[(size_t)rr * W + slot * NTR + tr];
+            continue;
+        }
+        const int lc = L.row_col[rr];
+        const int lr0 = L.col_r0[lc];
+        const int nc = L.col_nc[lc];
+        const int k = L.row_k[rr];
+        const size_t blk = (size_t)g.blk_off[tm.c0 + lc];
+        double acc[NTR];
+#pragma unroll
+        for (int tr = 0; tr < NTR; ++tr) acc[tr] = 0.0;
+        for (int s = 0; s < nc; ++s) {   // row s of the block, column k
+            const size_t e = blk + (size_t)s * nc + k;
+            const double a = omq * ai0[e] + wq * ai1[e];
+#pragma unroll
+            for (int tr = 0; tr < NTR; ++tr) acc[tr] += a * s_lam[(size_t)(lr0 + s) * W + slot * NTR + tr];
+        }
+#pragma unroll
+        for (int tr = 0; tr < NTR; ++tr) out[(size_t)r * W + slot * NTR + tr] = acc[tr];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions (deterministic: fixed-order per-tile partial sums, then a fixed-
+// order sum over tiles).
+// ---------------------------------------------------------------------------
+
+// part[tile][slot] = sum over the tile's rows and the slot's tracers of
+// weight_i * (a - b)^2, weight_i = V_i if volume != 0 else 1; b may be NULL.
+template <int MAXR, int MAXC>
+__global__ void k_tile_sqdiff(Grid g, int W, int ntr, int nb, const double* __restrict__ a,
+                              const double* __restrict__ b, int volume, double* __restrict__ part) {
+    __shared__ TileLds<MAXR, MAXC> L;
+    __shared__ double s_red[256];
+    const TileMap tm = build_tile<MAXR, MAXC>(g, L, -1.0);
+    for (int slot = 0; slot < nb; ++slot) {
+        double s = 0.0;
+        for (int rr = threadIdx.x; rr < tm.nrows; rr += blockDim.x) {
+            const int r = tm.r0 + rr;
+            double wgt = 1.0;
+            if (volume) wgt = g.area[tm.c0 + L.row_col[rr]] * g.dz[L.row_k[rr]];
+            for (int tr = 0; tr < ntr; ++tr) {
+                const size_t at = (size_t)r * W + slot * ntr + tr;
+                const double d = b ? a[at] - b[at] : a[at];
+                s += wgt * d * d;
+            }
+        }
+        s_red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) s_red[threadIdx.x] += s_red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * nb + slot] = s_red[0];
+        __syncthreads();
+    }
+}
+
+// Per-tile cell volume sums (for V_tot).
+template <int MAXR, int MAXC>
+__global__ void k_tile_volume(Grid g, double* __restrict__ part) {
+    __shared__ TileLds<MAXR, MAXC> L;
+    __shared__ double s_red[256];
+    const TileMap tm = build_tile<MAXR, MAXC>(g, L, -1.0);
+    double s = 0.0;
+    for (int rr = threadIdx.x; rr < tm.nrows; rr += blockDim.x)
+        s += g.area[tm.c0 + L.row_col[rr]] * g.dz[L.row_k[rr]];
+    s_red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s_red[threadIdx.x] += s_red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s_red[0];
+}
+
+// out[q] = scale * sum_t part[t*stride + q] (+ out[q] if accumulate); optional sqrt.
+__global__ void k_sum_tiles(int ntile, int stride, int nq, const double* __restrict__ part, double scale,
+                            int accumulate, int take_sqrt, double* __restrict__ out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    double s = 0.0;
+    for (int t = 0; t < ntile; ++t) s += part[(size_t)t * stride + q];
+    s *= scale;
+    if (take_sqrt) s = sqrt(s);
+    out[q] = accumulate ? out[q] + s : s;
+}
+
+__global__ void k_fill(double* __restrict__ x, size_t len, double value) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < len; i += stride) x[i] = value;
+}
+
+__global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, size_t len) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < len; i += stride) dst[i] = src[i];
+}
+
+// FD direction: h_s = 1e-8 ||y_s|| / ||v_s|| per slot from squared norms.
+__global__ void k_fd_step(int nb, const double* __restrict__ ny2, const double* __restrict__ nv2,
+                          double* __restrict__ h) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nb) return;
+    h[s] = nv2[s] > 0.0 ? 1e-8 * sqrt(ny2[s]) / sqrt(nv2[s]) : 0.0;
+}
+
+// out = y + h_slot v
+__global__ void k_axpy_slots(size_t n, int W, int ntr, const double* __restrict__ h, const double* __restrict__ y,
+                             const double* __restrict__ v, double* __restrict__ out) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n * W; i += stride) out[i] = y[i] + h[(i % W) / ntr] * v[i];
+}
+
+// jv = (fp - f0)/h_slot  (0 where h = 0)
+__global__ void k_fd_quot(size_t n, int W, int ntr, const double* __restrict__ h, const double* __restrict__ fp,
+                          const double* __restrict__ f0, double* __restrict__ jv) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n * W; i += stride) {
+        const double hh = h[(i % W) / ntr];
+        jv[i] = hh > 0.0 ? (fp[i] - f0[i]) / hh : 0.0;
+    }
+}
+
+// Column gather between state layouts: dst[i*Wd + dcol[s]*ntr + tr] = src[i*Ws + scol[s]*ntr + tr]
+// for s < ns (member compaction and scatter of finished members).
+__global__ void k_gather_slots(size_t n, int ns, int ntr, int Ws, int Wd, const int* __restrict__ scol,
+                               const int* __restrict__ dcol, const double* __restrict__ src,
+                               double* __restrict__ dst) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t per_row = (size_t)ns * ntr;
+    for (; i < n * per_row; i += stride) {
+        const size_t row = i / per_row;
+        const int q = (int)(i % per_row);
+        const int s = q / ntr, tr = q % ntr;
+        dst[row * Wd + (size_t)dcol[s] * ntr + tr] = src[row * Ws + (size_t)scol[s] * ntr + tr];
+    }
+}
+
+}  // namespace tmm

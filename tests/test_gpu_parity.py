@@ -1,0 +1,172 @@
+"""GPU parity: libtmm (through its C ABI) against the CPU oracle, same seeded inputs.
+
+Tolerances: one step within 1e-14 relative to the largest value, one model
+year within 1e-12 (the forward bar), derivatives as stated per test.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_1410_0204_amd import tmm
+    return tmm
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _make(inp, nbatch_max=1, adjoint=0, ckpt=240):
+    tmm = _lib()
+    print(f"[gpu] create {inp.name} nbatch_max={nbatch_max} adjoint={adjoint}", flush=True)
+    return tmm.TMM(inp.desc_arrays(), nbatch_max=nbatch_max, adjoint_nbatch_max=adjoint, ckpt_every=ckpt)
+
+
+@pytest.fixture(scope="module")
+def inputs():
+    return {"tiny_n": synth.tiny(), "tiny_ndop": synth.tiny(model=synth.MODEL_NDOP),
+            "small": synth.small_ndop()}
+
+
+@pytest.mark.parametrize("name", ["tiny_n", "tiny_ndop", "small"])
+def test_step_parity(inputs, name):
+    inp = inputs[name]
+    t = _make(inp)
+    o = oracle.Oracle(inp)
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    rng = np.random.default_rng(1)
+    y = inp.initial_state() * rng.uniform(0.5, 1.5, size=(inp.n, inp.ntracer))
+    yd = t.state(y)
+    for j in (0, 119, 120, 1439, 2879):
+        got = t.step(j, yd).cpu().numpy()
+        exp = o.step(u, j, y)
+        assert _rel(got, exp) <= 1e-14, j
+
+
+@pytest.mark.parametrize("name", ["tiny_n", "tiny_ndop", "small"])
+def test_year_parity(inputs, name):
+    inp = inputs[name]
+    t = _make(inp)
+    o = oracle.Oracle(inp)
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    y0 = inp.initial_state()
+    got, r = t.year(t.state(y0), nyears=2)
+    exp, re = o.year(u, y0, 2)
+    assert _rel(got.cpu().numpy(), exp) <= 1e-12
+    assert np.allclose(r, re, rtol=1e-9, atol=0)
+
+
+def test_batched_members_match_unbatched(inputs):
+    inp = inputs["small"]
+    U = synth.latin_hypercube(synth.MODEL_NDOP, 3, seed=2)
+    t = _make(inp, nbatch_max=3)
+    y0 = inp.initial_state(3)
+    t.set_params(U)
+    yb, rb = t.year(t.state(y0))
+    yb = yb.cpu().numpy()
+    for m in range(3):
+        t.set_params(U[m])
+        ym, rm = t.year(t.state(y0[:, 2 * m:2 * m + 2]))
+        assert _rel(ym.cpu().numpy(), yb[:, 2 * m:2 * m + 2]) <= 1e-15
+        assert rm[0, 0] == pytest.approx(rb[0, m], rel=1e-14)
+
+
+def test_uneven_spinup_lengths(inputs):
+    """Members stop after their own number of years; finished states are kept."""
+    inp = inputs["tiny_ndop"]
+    U = synth.latin_hypercube(synth.MODEL_NDOP, 4, seed=5)
+    L = np.array([2, 0, 1, 3], dtype=np.int32)
+    t = _make(inp, nbatch_max=4)
+    o = oracle.Oracle(inp)
+    t.set_params(U)
+    y0 = inp.initial_state(4)
+    got, r = t.year(t.state(y0), nyears=3, years_per_member=L)
+    got = got.cpu().numpy()
+    for m in range(4):
+        exp, re = o.year(U[m], y0[:, 2 * m:2 * m + 2], int(L[m])) if L[m] else (y0[:, 2 * m:2 * m + 2], None)
+        assert _rel(got[:, 2 * m:2 * m + 2], exp) <= 1e-12, m
+        if L[m]:
+            assert np.allclose(r[:L[m], m], re[:, 0], rtol=1e-9)
+            assert (r[L[m]:, m] == 0).all()
+
+
+def test_jvp_tangent_and_fd(inputs):
+    inp = inputs["small"]
+    t = _make(inp)
+    o = oracle.Oracle(inp)
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    rng = np.random.default_rng(3)
+    y = inp.initial_state() * rng.uniform(0.8, 1.2, size=(inp.n, 2))
+    v = rng.standard_normal(y.shape) * y
+    tmm = _lib()
+    phi, jv = t.year_jvp(t.state(y), t.state(v), mode=tmm.TMM_JVP_TANGENT)
+    ephi, ejv = o.year_tangent(u, y, v)
+    assert _rel(phi.cpu().numpy(), ephi) <= 1e-12
+    assert _rel(jv.cpu().numpy(), ejv) <= 1e-11
+    phi, jfd = t.year_jvp(t.state(y), t.state(v), mode=tmm.TMM_JVP_FD)
+    _, efd = o.year_jvp_fd(u, y, v)
+    assert _rel(phi.cpu().numpy(), ephi) <= 1e-12
+    # both are forward differences with h = 1e-8 |y|/|v|; rounding makes them agree to ~1e-6
+    assert _rel(jfd.cpu().numpy(), efd) <= 1e-5
+    assert _rel(jfd.cpu().numpy(), ejv) <= 1e-5
+
+
+@pytest.mark.parametrize("name,ckpt", [("tiny_n", 240), ("tiny_ndop", 240), ("small", 480), ("small", 1)])
+def test_adjoint_parity(inputs, name, ckpt):
+    inp = inputs[name]
+    o = oracle.Oracle(inp)
+    ustar = synth.hidden_params(inp.model, seed=21)
+    y0 = inp.initial_state()
+    snaps = o.snapshots(ustar, y0)
+    obs = snaps * (1 + 0.05 * synth.obs_noise(snaps.shape, seed=22))
+    u = synth.nominal(inp.model)
+    eJ, eG, eY = o.year_adjoint(u, y0, obs)
+    t = _make(inp, adjoint=1, ckpt=ckpt)
+    t.set_params(u)
+    import torch
+    J, G, dy0 = t.year_adjoint(t.state(y0), torch.as_tensor(obs).cuda())
+    assert J[0] == pytest.approx(eJ[0], rel=1e-12)
+    assert _rel(G, eG) <= 1e-10
+    assert _rel(dy0.cpu().numpy(), eY) <= 1e-10
+
+
+def test_year_is_deterministic(inputs):
+    inp = inputs["small"]
+    t = _make(inp)
+    t.set_params(synth.nominal(inp.model))
+    y0 = t.state(inp.initial_state())
+    a, _ = t.year(y0)
+    b, _ = t.year(y0)
+    assert bool((a == b).all())
+
+
+@pytest.fixture(scope="module")
+def global_inputs():
+    return synth.global_2p8()
+
+
+def test_global_step_and_year_parity(global_inputs):
+    """Full 128x64x15 workload (52749 points, N-DOP) in the benchmark's launch configuration."""
+    inp = global_inputs
+    t = _make(inp)
+    o = oracle.Oracle(inp)
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    y0 = inp.initial_state()
+    yd = t.state(y0)
+    for j in (0, 2879):
+        assert _rel(t.step(j, yd).cpu().numpy(), o.step(u, j, y0)) <= 1e-14
+    print("[gpu] global year on the oracle (~15 s)", flush=True)
+    got, r = t.year(yd)
+    exp, re = o.year(u, y0)
+    assert _rel(got.cpu().numpy(), exp) <= 1e-12
+    assert r[0, 0] == pytest.approx(re[0, 0], rel=1e-9)

@@ -1,0 +1,176 @@
+"""Throughput of the transport-matrix year map on one MI355X.
+
+A "step" of this benchmark is one model year (2880 time steps) of the
+global 128x64x15 workload (52749 wet points in 4448 columns, N-DOP model,
+two tracers, float64), i.e. one evaluation of the year map phi that spin-up
+and Newton-Krylov iterate.  Inputs are synthetic and seeded, shaped like the
+paper's 2.8125-degree configuration; they are resident in HBM before timing
+starts.
+
+Printed as one JSON line: model-years/s, the effective bandwidth of the step
+kernel against MI355X peak HBM bandwidth (roofline), the adjoint/forward
+cost ratio, and the CPU oracle's rate on the host as a reported baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+STEP_KERNEL = "k_step"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_step(n, nnz_e, nnz_i, W):
+    """Algorithmic bytes of one time step: both bracketing months' values (8 B
+    each) and the column index (4 B) of every nonzero of Ae and Ai, the two
+    CSR row-pointer arrays, and the state read and written."""
+    return (nnz_e + nnz_i) * (2 * 8 + 4) + 2 * 4 * (n + 1) + 2 * 8 * n * W
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("tmm_device.hpp", "tmm.hip"):
+        with open(os.path.join(ROOT, "paper_1410_0204_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(per_launch_units):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken with the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "k_step_global_128x64x15_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec["bytes_per_launch"] * per_launch_units
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed model years")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed model years")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X; --gpus must be 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1410_0204_amd import tmm
+
+    inp = synth.global_2p8()
+    n, W = inp.n, inp.ntracer
+    B = bytes_per_step(n, inp.tm.ae_nnz, inp.tm.ai_nnz, W)
+    log(f"[bench] {inp.name}: n={n} ncol={inp.grid.ncol} nnz_e={inp.tm.ae_nnz} nnz_i={inp.tm.ai_nnz} "
+        f"bytes/step={B}")
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=1, adjoint_nbatch_max=1, ckpt_every=240, device=dev, stream=stream)
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    y0 = t.state(inp.initial_state())
+    y1 = t.state()
+
+    # warm-up years (spin-up from the constant field)
+    y, _ = t.year(y0, nyears=max(args.warmup, 1), out=y1, residuals=False)
+    torch.cuda.synchronize()
+
+    # timed years: events on the stream the library launches on
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ya = t.state()
+    torch.cuda.synchronize()
+    start.record(stream)
+    t.year(y, nyears=args.steps, out=ya, residuals=False)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    ms_per_year = ms / args.steps
+    years_per_s = 1000.0 / ms_per_year
+    launches = args.steps * inp.nstep
+    us_per_launch = ms * 1000.0 / launches
+    achieved = B / (us_per_launch * 1e-6) / 1e9
+    log(f"[bench] forward: {ms_per_year:.3f} ms/model-year, {years_per_s:.2f} model-years/s, "
+        f"{us_per_launch:.2f} us/step, {achieved:.0f} GB/s effective")
+
+    # adjoint / forward cost ratio (one model year each, ckpt every 240 steps)
+    obs = torch.as_tensor(np.broadcast_to(inp.initial_state(), (12, n, W)).copy()
+                          * (1 + 0.05 * synth.obs_noise((12, n, W), seed=3))).to(dev)
+    t.year_adjoint(y0, obs, want_dy0=False)   # warm-up
+    torch.cuda.synchronize()
+    start.record(stream)
+    t.year_adjoint(y0, obs, want_dy0=True)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_adj = start.elapsed_time(stop)
+    start.record(stream)
+    t.year(y0, nyears=1, out=ya, residuals=False)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_fwd1 = start.elapsed_time(stop)
+    ratio = ms_adj / ms_fwd1
+    log(f"[bench] adjoint year {ms_adj:.2f} ms vs forward {ms_fwd1:.2f} ms: ratio {ratio:.2f}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        o = oracle.Oracle(inp)
+        yh = inp.initial_state()
+        t0 = time.perf_counter()
+        o.year(u, yh, 1)
+        dt = time.perf_counter() - t0
+        cpu = {"value": 1.0 / dt, "unit": "model-years/s", "cores": 1, "kind": "oracle",
+               "sample": "one model year (2880 steps) of the same global 128x64x15 N-DOP workload, "
+                         f"single-threaded C oracle, {dt:.1f} s"}
+        log(f"[bench] cpu oracle: {dt:.1f} s per model year")
+
+    traffic = measured_traffic(1)
+    out = {
+        "metric": "model-years/s + HBM GB/s (N-DOP, 52749 pts); adjoint/forward cost ratio",
+        "value": years_per_s,
+        "unit": "model-years/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_year,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded 128x64x15 grid and monthly matrices shaped like the paper's 2.8125-degree set)",
+        "config": {"workload": "global_128x64x15 N-DOP forward model years", "n": n, "columns": inp.grid.ncol,
+                   "layers": 15, "tracers": W, "nstep": inp.nstep, "nnz_explicit": inp.tm.ae_nnz,
+                   "nnz_implicit": inp.tm.ai_nnz, "step": "one model year"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": STEP_KERNEL, "us_per_launch": us_per_launch, "bytes_per_launch": B},
+        "adjoint_forward_ratio": ratio,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    t.close()
+
+
+if __name__ == "__main__":
+    main()

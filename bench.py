@@ -27,7 +27,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-STEP_KERNEL = "k_step"
 
 
 def log(*a):
@@ -43,16 +42,16 @@ def bytes_per_step(n, nnz_e, nnz_i, W):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("tmm_device.hpp", "tmm.hip"):
+    for f in ("tmm_device.hpp", "tmm_persistent.hpp", "tmm.hip"):
         with open(os.path.join(ROOT, "paper_1410_0204_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(per_launch_units):
+def measured_traffic(kernel, per_launch_units):
     """HBM bytes per launch from the committed counter summary, if it was
     taken with the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "k_step_global_128x64x15_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_global_128x64x15_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -97,6 +96,11 @@ def main():
     y, _ = t.year(y0, nyears=max(args.warmup, 1), out=y1, residuals=False)
     torch.cuda.synchronize()
 
+    persistent = bool(t.query(tmm.TMM_Q_PERSISTENT))
+    kernel = "k_year_persistent" if persistent else "k_step"
+    log(f"[bench] path: {kernel}" + (f" ({t.query(tmm.TMM_Q_DOMAINS)} domains on "
+                                     f"{t.query(tmm.TMM_Q_COMPUTE_UNITS)} CUs)" if persistent else ""))
+
     # timed years: events on the stream the library launches on
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ya = t.state()
@@ -108,11 +112,29 @@ def main():
     ms = start.elapsed_time(stop)
     ms_per_year = ms / args.steps
     years_per_s = 1000.0 / ms_per_year
-    launches = args.steps * inp.nstep
+    us_per_step = ms * 1000.0 / (args.steps * inp.nstep)
+    # one launch of the dominant kernel covers a model year (persistent) or a step
+    units = inp.nstep if persistent else 1
+    launches = args.steps if persistent else args.steps * inp.nstep
     us_per_launch = ms * 1000.0 / launches
-    achieved = B / (us_per_launch * 1e-6) / 1e9
+    achieved = B * units / (us_per_launch * 1e-6) / 1e9
     log(f"[bench] forward: {ms_per_year:.3f} ms/model-year, {years_per_s:.2f} model-years/s, "
-        f"{us_per_launch:.2f} us/step, {achieved:.0f} GB/s effective")
+        f"{us_per_step:.2f} us/step, {achieved:.0f} GB/s effective")
+
+    # the one-launch-per-step path on the same handle, for comparison
+    per_step = None
+    if persistent:
+        t.set_option(tmm.TMM_OPT_PERSISTENT, 0)
+        t.year(y, nyears=1, out=ya, residuals=False)
+        torch.cuda.synchronize()
+        start.record(stream)
+        t.year(y, nyears=2, out=ya, residuals=False)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        t.set_option(tmm.TMM_OPT_PERSISTENT, 1)
+        ms_ps = start.elapsed_time(stop) / 2
+        per_step = {"ms_per_year": ms_ps, "model_years_per_s": 1000.0 / ms_ps}
+        log(f"[bench] per-step kernels: {ms_ps:.3f} ms/model-year")
 
     # adjoint / forward cost ratio (one model year each, ckpt every 240 steps)
     obs = torch.as_tensor(np.broadcast_to(inp.initial_state(), (12, n, W)).copy()
@@ -145,7 +167,7 @@ def main():
                          f"single-threaded C oracle, {dt:.1f} s"}
         log(f"[bench] cpu oracle: {dt:.1f} s per model year")
 
-    traffic = measured_traffic(1)
+    traffic = measured_traffic(kernel, 1)
     out = {
         "metric": "model-years/s + HBM GB/s (N-DOP, 52749 pts); adjoint/forward cost ratio",
         "value": years_per_s,
@@ -161,10 +183,13 @@ def main():
         "data": "synthetic (seeded 128x64x15 grid and monthly matrices shaped like the paper's 2.8125-degree set)",
         "config": {"workload": "global_128x64x15 N-DOP forward model years", "n": n, "columns": inp.grid.ncol,
                    "layers": 15, "tracers": W, "nstep": inp.nstep, "nnz_explicit": inp.tm.ae_nnz,
-                   "nnz_implicit": inp.tm.ai_nnz, "step": "one model year"},
+                   "nnz_implicit": inp.tm.ai_nnz, "step": "one model year",
+                   "path": kernel},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": STEP_KERNEL, "us_per_launch": us_per_launch, "bytes_per_launch": B},
+                     "kernel": kernel, "us_per_launch": us_per_launch, "bytes_per_launch": B * units,
+                     "us_per_time_step": us_per_step},
+        "per_step_path": per_step,
         "adjoint_forward_ratio": ratio,
         "cpu_baseline": cpu,
     }

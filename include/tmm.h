@@ -65,7 +65,9 @@ enum {
 /* Directional derivative of the year map (section 6.1). */
 enum {
     TMM_JVP_FD = 0,         /* finite difference (phi(y+h v) - phi(y))/h, h = 1e-8 |y|/|v| per member */
-    TMM_JVP_TANGENT = 1     /* exact forward-mode tangent */
+    TMM_JVP_TANGENT = 1,    /* exact forward-mode tangent */
+    TMM_JVP_FD_GIVEN_PHI = 2 /* as TMM_JVP_FD with phi_y = phi(y) supplied by the caller (input): one
+                               year map per product, as inside a Krylov solve at a fixed Newton iterate */
 };
 
 typedef struct {
@@ -130,8 +132,9 @@ int tmm_year(tmm_handle h, int nyears, const int *years_per_member,
              const double *y0, double *y1, double *resid_host);
 
 /* Directional derivative of the year map (section 6.1): jv = phi'(y) v by
- * mode TMM_JVP_FD or TMM_JVP_TANGENT; phi_y (nullable) receives phi(y).
- * All device, n x W. */
+ * mode TMM_JVP_FD or TMM_JVP_TANGENT, where phi_y (nullable) receives phi(y);
+ * with TMM_JVP_FD_GIVEN_PHI, phi_y must hold phi(y) and is read.
+ * All device, n x W; jv must not overlap y, v or phi_y. */
 int tmm_year_jvp(tmm_handle h, int mode, const double *y, const double *v,
                  double *phi_y, double *jv);
 
@@ -145,6 +148,29 @@ int tmm_year_jvp(tmm_handle h, int mode, const double *y, const double *v,
  * ckpt_every must equal the descriptor's value.  Synchronises. */
 int tmm_year_adjoint(tmm_handle h, const double *y0, const double *obs, int ckpt_every,
                      double *J_host, double *dJdu_host, double *dJdy0);
+
+/* Options (tmm_set_option). */
+enum {
+    TMM_OPT_PERSISTENT = 1,  /* 1 (default): single-member model years run as one persistent
+                                cooperative launch when the grid fits; 0: one launch per step */
+    TMM_OPT_DOMAIN_ROWS = 2  /* target rows per workgroup of the persistent kernel (<= 512);
+                                0 = the default (448) */
+};
+
+/* Queries (tmm_query). */
+enum {
+    TMM_Q_PERSISTENT = 1,   /* 1 if the persistent year kernel is available on this handle */
+    TMM_Q_DOMAINS = 2,      /* workgroups (column domains) of the persistent kernel */
+    TMM_Q_WORKSPACE = 3,    /* workspace bytes in use */
+    TMM_Q_COMPUTE_UNITS = 4 /* compute units of the device */
+};
+
+/* Sets an execution option; results are the same either way up to rounding
+ * order.  TMM_EINVAL for an unknown option. */
+int tmm_set_option(tmm_handle h, int option, int value);
+
+/* Reads a property of the handle into *value.  TMM_EINVAL for an unknown query. */
+int tmm_query(tmm_handle h, int what, long long *value);
 
 /* Static text for a status code. */
 const char *tmm_strerror(int status);

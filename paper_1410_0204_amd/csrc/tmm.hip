@@ -15,6 +15,7 @@
 
 #include "tmm.h"
 #include "tmm_device.hpp"
+#include "tmm_persistent.hpp"
 
 namespace {
 
@@ -82,8 +83,18 @@ struct Plan {
     size_t o_u, o_light, o_rho, o_drho, o_member, o_scol, o_dcol;
     size_t o_ybuf[3], o_vbuf[2], o_part, o_vec, o_ubt, o_jpart, o_ckpt, o_seg, o_final, o_mu[2];
     size_t vec_stride;
+    // insolation table over distinct latitudes
+    std::vector<double> lat_u;
+    std::vector<int> col_lat;
+    size_t o_ins, o_collat, o_latu;
+    // persistent-kernel tables (sized for up to kMaxDomains domains)
+    size_t o_pblock, o_pdomcol, o_pdepptr, o_pdepidx, o_pflags, o_pabort;
+    size_t dep_capacity;
     size_t total;
 };
+
+constexpr int kMaxDomains = 4096;
+constexpr int kDefaultDomainRows = 448;     // rows per persistent workgroup unless set by option (tuned on MI355X)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -196,6 +207,27 @@ int validate(const tmm_desc* d, Plan& P) {
     } else {
         P.o_ubt = P.o_jpart = P.o_ckpt = P.o_seg = P.o_final = P.o_mu[0] = P.o_mu[1] = 0;
     }
+    // distinct latitudes (exact values) for the insolation table
+    P.lat_u.clear();
+    P.col_lat.assign(d->ncol, 0);
+    {
+        std::vector<double> l(d->lat, d->lat + d->ncol);
+        std::sort(l.begin(), l.end());
+        l.erase(std::unique(l.begin(), l.end()), l.end());
+        P.lat_u = l;
+        for (int c = 0; c < d->ncol; ++c)
+            P.col_lat[c] = (int)(std::lower_bound(l.begin(), l.end(), d->lat[c]) - l.begin());
+    }
+    P.o_ins = take((size_t)d->nstep * P.lat_u.size() * 8);
+    P.o_collat = take((size_t)d->ncol * 4);
+    P.o_latu = take(P.lat_u.size() * 8);
+    P.dep_capacity = 2 * (size_t)d->ae_nnz + 1;
+    P.o_pblock = take((size_t)kMaxDomains * 4);
+    P.o_pdomcol = take((size_t)(kMaxDomains + 1) * 4);
+    P.o_pdepptr = take((size_t)(kMaxDomains + 1) * 4);
+    P.o_pdepidx = take(P.dep_capacity * 4);
+    P.o_pflags = take((size_t)kMaxDomains * 4);
+    P.o_pabort = take(64);
     P.total = o;
     return TMM_OK;
 }
@@ -211,6 +243,15 @@ struct tmm_ctx {
     double vtot = 0.0;         // total wet volume
     std::vector<int> h_member, h_scol, h_dcol;
     std::vector<double> h_vec;
+    // persistent year kernel
+    bool pers_ok = false;          // tables built and the launch fits the device
+    bool pers_enabled = true;      // option TMM_OPT_PERSISTENT
+    int pers_G = 0;
+    int pers_kmax = 16;
+    int pers_tpb = 256;            // threads (= maximum rows) per domain
+    int num_cu = 0;
+    bool pers_used = false;        // a persistent launch happened since the last abort check
+    std::vector<int> ae_rowptr, ae_colidx;   // explicit-matrix pattern (domain dependencies)
 
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 
@@ -223,6 +264,9 @@ struct tmm_ctx {
         g.lat = at<double>(P.o_lat);
         g.area = at<double>(P.o_area);
         g.dz = at<double>(P.o_dz);
+        g.ins = at<double>(P.o_ins);
+        g.col_lat = at<int>(P.o_collat);
+        g.nlat = (int)P.lat_u.size();
         return g;
     }
     tmm::Model model() const {
@@ -273,6 +317,11 @@ int launch_blocks(size_t work, int block = 256) {
     return (int)std::min<size_t>(std::max<size_t>(b, 1), 4096);
 }
 
+int upload(tmm_ctx* h, void* dst, const void* src, size_t bytes) {
+    TMM_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
+    return TMM_OK;
+}
+
 int fill(tmm_ctx* h, double* x, size_t len, double v) {
     hipLaunchKernelGGL(tmm::k_fill, dim3(launch_blocks(len)), dim3(256), 0, h->stream, x, len, v);
     TMM_LAUNCHED();
@@ -315,10 +364,67 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
     return TMM_OK;
 }
 
+template <int TPB>
+const void* persistent_kernel_tpb(int ntr, bool tangent, int kmax) {
+    if (kmax == 16) {
+        if (ntr == 1) return tangent ? (const void*)&tmm::k_year_persistent<1, true, 16, TPB>
+                                     : (const void*)&tmm::k_year_persistent<1, false, 16, TPB>;
+        return tangent ? (const void*)&tmm::k_year_persistent<2, true, 16, TPB>
+                       : (const void*)&tmm::k_year_persistent<2, false, 16, TPB>;
+    }
+    if (ntr == 1) return tangent ? (const void*)&tmm::k_year_persistent<1, true, 32, TPB>
+                                 : (const void*)&tmm::k_year_persistent<1, false, 32, TPB>;
+    return tangent ? (const void*)&tmm::k_year_persistent<2, true, 32, TPB>
+                   : (const void*)&tmm::k_year_persistent<2, false, 32, TPB>;
+}
+
+const void* persistent_kernel(int ntr, bool tangent, int kmax, int tpb) {
+    return tpb == 512 ? persistent_kernel_tpb<512>(ntr, tangent, kmax) : persistent_kernel_tpb<256>(ntr, tangent, kmax);
+}
+
+// One model year in one cooperative launch (one member).
+int launch_persistent(tmm_ctx* h, const double* y, double* out, double* a, double* b, const double* v,
+                      double* vout, double* va, double* vb) {
+    const Plan& P = h->P;
+    hipLaunchKernelGGL(tmm::k_fill_int, dim3((h->pers_G + 255) / 256), dim3(256), 0, h->stream,
+                       h->at<int>(P.o_pflags), h->pers_G, 0);
+    TMM_LAUNCHED();
+    tmm::Grid g = h->grid(h->tilings.front());
+    tmm::Model md = h->model();
+    tmm::Mats mt = h->mats();
+    tmm::Persist ps;
+    ps.block_dom = h->at<int>(P.o_pblock);
+    ps.dom_col = h->at<int>(P.o_pdomcol);
+    ps.dep_ptr = h->at<int>(P.o_pdepptr);
+    ps.dep_idx = h->at<int>(P.o_pdepidx);
+    ps.flags = h->at<int>(P.o_pflags);
+    ps.abort_flag = h->at<int>(P.o_pabort);
+    ps.spin_limit = 1ll << 22;
+    double dtd = tmm::kDaysPerYear / P.nstep;
+    void* args[] = {&g, &md, &mt, &ps, &dtd, &y, &out, &a, &b, &v, &vout, &va, &vb};
+    TMM_TRY(hipLaunchCooperativeKernel(persistent_kernel(P.ntr, v != nullptr, h->pers_kmax, h->pers_tpb),
+                                       dim3(h->pers_G), dim3(h->pers_tpb), args, 0, h->stream));
+    h->pers_used = true;
+    return TMM_OK;
+}
+
+// After persistent launches: a set abort flag means a wait gave up.
+int check_abort(tmm_ctx* h) {
+    if (!h->pers_used) return TMM_OK;
+    int flag = 0;
+    TMM_TRY(hipMemcpyAsync(&flag, h->at<int>(h->P.o_pabort), 4, hipMemcpyDeviceToHost, h->stream));
+    TMM_TRY(hipStreamSynchronize(h->stream));
+    h->pers_used = false;
+    return flag ? TMM_EDEVICE : TMM_OK;
+}
+
 // One model year for nb slots from y to out, ping-ponging through a, b.  The
 // last step writes out directly.  Tangent when v != nullptr (vout, va, vb).
+// One member on a handle with the persistent tables runs as one persistent
+// launch; otherwise one launch per step.
 int run_year(tmm_ctx* h, int nb, const double* y, double* out, double* a, double* b,
              const double* v = nullptr, double* vout = nullptr, double* va = nullptr, double* vb = nullptr) {
+    if (nb == 1 && h->pers_ok && h->pers_enabled) return launch_persistent(h, y, out, a, b, v, vout, va, vb);
     const double* cur = y;
     const double* vcur = v;
     for (int j = 0; j < h->P.nstep; ++j) {
@@ -330,6 +436,95 @@ int run_year(tmm_ctx* h, int nb, const double* y, double* out, double* a, double
         cur = nxt;
         vcur = vnxt;
     }
+    return TMM_OK;
+}
+
+// Domains for the persistent kernel: contiguous runs of water columns with
+// about n/G rows each (at most the workgroup size), the domains each one must
+// wait for (both directions of every explicit-matrix coupling), and an
+// XCD-aware block order (consecutive domains on the same XCD, assuming the
+// round-robin dispatch of workgroups over the 8 XCDs).
+int build_persistent(tmm_ctx* h, int target_rows) {
+    const Plan& P = h->P;
+    int dev = 0, coop = 0, ncu = 0;
+    TMM_TRY(hipGetDevice(&dev));
+    TMM_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    TMM_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    h->num_cu = ncu;
+    h->pers_ok = false;
+    if (!coop || P.ew > tmm::kEllMax || P.nlayer > 32 || P.neu > tmm::kNeuMax) return TMM_OK;
+    h->pers_kmax = P.nlayer <= 16 ? 16 : 32;
+    if (target_rows < 1) target_rows = kDefaultDomainRows;
+    // 512-thread workgroups only where the row's Ai block fits the halved register budget
+    const int tpb = (target_rows > 256 && h->pers_kmax == 16) ? tmm::kPersistThreadsMax : 256;
+    target_rows = std::min(target_rows, tpb);
+    int occ = 0;
+    for (int ntr = 1; ntr <= 2; ++ntr)
+        for (int t = 0; t < 2; ++t) {
+            int o = 0;
+            TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, persistent_kernel(ntr, t, h->pers_kmax, tpb),
+                                                                 tpb, 0));
+            occ = (ntr == 1 && t == 0) ? o : std::min(occ, o);
+        }
+    const int maxG = std::min(kMaxDomains, std::min(ncu * occ, P.ncol));
+    if (maxG < 1) return TMM_OK;
+    int G = std::min(maxG, std::max(1, (P.n + target_rows - 1) / target_rows));
+    std::vector<int> dom;
+    for (;;) {
+        dom.assign(1, 0);
+        long long rows = 0;
+        for (int c = 0; c < P.ncol; ++c) {
+            rows += P.col_start[c + 1] - P.col_start[c];
+            const long long target = (long long)P.n * (long long)dom.size() / G;
+            if (rows >= target && (int)dom.size() < G && c + 1 < P.ncol) dom.push_back(c + 1);
+        }
+        dom.push_back(P.ncol);
+        int maxrows = 0;
+        for (size_t i = 0; i + 1 < dom.size(); ++i)
+            maxrows = std::max(maxrows, P.col_start[dom[i + 1]] - P.col_start[dom[i]]);
+        if (maxrows <= tpb) break;
+        if (G >= maxG) return TMM_OK;                 // does not fit: per-step path only
+        G = std::min(maxG, G + std::max(1, G / 8));
+    }
+    G = (int)dom.size() - 1;
+    std::vector<int> row_dom(P.n);
+    for (int q = 0; q < G; ++q)
+        for (int r = P.col_start[dom[q]]; r < P.col_start[dom[q + 1]]; ++r) row_dom[r] = q;
+    std::vector<std::vector<int>> deps(G);
+    for (int i = 0; i < P.n; ++i)
+        for (int e = h->ae_rowptr[i]; e < h->ae_rowptr[i + 1]; ++e) {
+            const int a = row_dom[i], b = row_dom[h->ae_colidx[e]];
+            if (a != b) {
+                deps[a].push_back(b);
+                deps[b].push_back(a);
+            }
+        }
+    std::vector<int> dep_ptr(G + 1, 0), dep_idx;
+    for (int q = 0; q < G; ++q) {
+        std::sort(deps[q].begin(), deps[q].end());
+        deps[q].erase(std::unique(deps[q].begin(), deps[q].end()), deps[q].end());
+        dep_idx.insert(dep_idx.end(), deps[q].begin(), deps[q].end());
+        dep_ptr[q + 1] = (int)dep_idx.size();
+    }
+    if (dep_idx.size() > P.dep_capacity) return TMM_OK;
+    if (dep_idx.empty()) dep_idx.push_back(0);
+    std::vector<int> block_dom(G);
+    {
+        int next = 0;
+        for (int x = 0; x < 8; ++x)
+            for (int b = x; b < G; b += 8) block_dom[b] = next++;
+    }
+    if (upload(h, h->at<int>(P.o_pblock), block_dom.data(), (size_t)G * 4) ||
+        upload(h, h->at<int>(P.o_pdomcol), dom.data(), dom.size() * 4) ||
+        upload(h, h->at<int>(P.o_pdepptr), dep_ptr.data(), dep_ptr.size() * 4) ||
+        upload(h, h->at<int>(P.o_pdepidx), dep_idx.data(), dep_idx.size() * 4))
+        return TMM_EDEVICE;
+    hipLaunchKernelGGL(tmm::k_fill_int, dim3(1), dim3(64), 0, h->stream, h->at<int>(P.o_pabort), 16, 0);
+    TMM_LAUNCHED();
+    TMM_TRY(hipStreamSynchronize(h->stream));
+    h->pers_G = G;
+    h->pers_tpb = tpb;
+    h->pers_ok = true;
     return TMM_OK;
 }
 
@@ -351,10 +546,6 @@ int sqdiff(tmm_ctx* h, int nb, const double* a, const double* b, int volume, dou
     return TMM_OK;
 }
 
-int upload(tmm_ctx* h, void* dst, const void* src, size_t bytes) {
-    TMM_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
-    return TMM_OK;
-}
 
 }  // namespace
 
@@ -493,6 +684,19 @@ int tmm_create(const tmm_desc* d, void* dev_workspace, size_t bytes, void* hip_s
         if (upload(h, tl.d_tile_col, tl.tile_col.data(), tl.tile_col.size() * 4)) return fail(TMM_EDEVICE);
         h->tilings.push_back(std::move(tl));
     }
+    // insolation per step and distinct latitude
+    if (upload(h, h->at<int>(P.o_collat), P.col_lat.data(), P.col_lat.size() * 4) ||
+        upload(h, h->at<double>(P.o_latu), P.lat_u.data(), P.lat_u.size() * 8))
+        return fail(TMM_EDEVICE);
+    {
+        const int tot = P.nstep * (int)P.lat_u.size();
+        hipLaunchKernelGGL(tmm::k_insolation_table, dim3((tot + 255) / 256), dim3(256), 0, h->stream, P.nstep,
+                           (int)P.lat_u.size(), h->at<double>(P.o_latu), h->at<double>(P.o_ins));
+        if (hipGetLastError() != hipSuccess) return fail(TMM_EDEVICE);
+    }
+    h->ae_rowptr.assign(d->ae_rowptr, d->ae_rowptr + P.n + 1);
+    h->ae_colidx.assign(d->ae_colidx, d->ae_colidx + d->ae_nnz);
+    if (build_persistent(h, 0)) return fail(TMM_EDEVICE);
     h->h_member.resize(P.nbatch_max);
     h->h_scol.resize(P.nbatch_max);
     h->h_dcol.resize(P.nbatch_max);
@@ -678,19 +882,22 @@ int tmm_year(tmm_handle h, int nyears, const int* years_per_member, const double
     // restore the identity member map for later calls
     for (int b = 0; b < nb; ++b) h->h_member[b] = b;
     if ((rc = push_member_map(h, nb))) return rc;
-    return TMM_OK;
+    return check_abort(h);
 }
 
 int tmm_year_jvp(tmm_handle h, int mode, const double* y, const double* v, double* phi_y, double* jv) {
     if (!h || !y || !v || !jv) return TMM_EINVAL;
-    if (mode != TMM_JVP_FD && mode != TMM_JVP_TANGENT) return TMM_EINVAL;
+    if (mode != TMM_JVP_FD && mode != TMM_JVP_TANGENT && mode != TMM_JVP_FD_GIVEN_PHI) return TMM_EINVAL;
+    if (mode == TMM_JVP_FD_GIVEN_PHI && !phi_y) return TMM_EINVAL;
     const int nb = h->nbatch;
     if (nb < 1) return TMM_ESTATE;
     const int ntr = h->P.ntr, W = nb * ntr;
     const size_t n = h->P.n;
     double* f0 = phi_y ? phi_y : h->ybuf(2);
-    if (mode == TMM_JVP_TANGENT)
-        return run_year(h, nb, y, f0, h->ybuf(0), h->ybuf(1), v, jv, h->vbuf(0), h->vbuf(1));
+    if (mode == TMM_JVP_TANGENT) {
+        int rt = run_year(h, nb, y, f0, h->ybuf(0), h->ybuf(1), v, jv, h->vbuf(0), h->vbuf(1));
+        return rt ? rt : check_abort(h);
+    }
     // finite differences: h_s = 1e-8 ||y_s|| / ||v_s||
     int rc = sqdiff(h, nb, y, nullptr, 0, 1.0, 0, h->vec(1));
     if (!rc) rc = sqdiff(h, nb, v, nullptr, 0, 1.0, 0, h->vec(2));
@@ -700,12 +907,36 @@ int tmm_year_jvp(tmm_handle h, int mode, const double* y, const double* v, doubl
     hipLaunchKernelGGL(tmm::k_axpy_slots, dim3(launch_blocks(n * W)), dim3(256), 0, h->stream, n, W, ntr,
                        h->vec(3), y, v, h->vbuf(0));
     TMM_LAUNCHED();
-    if ((rc = run_year(h, nb, y, f0, h->ybuf(0), h->ybuf(1)))) return rc;
+    if (mode == TMM_JVP_FD && (rc = run_year(h, nb, y, f0, h->ybuf(0), h->ybuf(1)))) return rc;
     if ((rc = run_year(h, nb, h->vbuf(0), jv, h->ybuf(0), h->ybuf(1)))) return rc;
     hipLaunchKernelGGL(tmm::k_fd_quot, dim3(launch_blocks(n * W)), dim3(256), 0, h->stream, n, W, ntr, h->vec(3),
                        jv, f0, jv);
     TMM_LAUNCHED();
-    return TMM_OK;
+    return check_abort(h);
+}
+
+int tmm_set_option(tmm_handle h, int option, int value) {
+    if (!h) return TMM_EINVAL;
+    switch (option) {
+        case TMM_OPT_PERSISTENT: h->pers_enabled = value != 0; return TMM_OK;
+        case TMM_OPT_DOMAIN_ROWS: {
+            if (value < 0) return TMM_EINVAL;
+            if (hipStreamSynchronize(h->stream) != hipSuccess) return TMM_EDEVICE;
+            return build_persistent(h, value);
+        }
+        default: return TMM_EINVAL;
+    }
+}
+
+int tmm_query(tmm_handle h, int what, long long* value) {
+    if (!h || !value) return TMM_EINVAL;
+    switch (what) {
+        case TMM_Q_PERSISTENT: *value = h->pers_ok ? 1 : 0; return TMM_OK;
+        case TMM_Q_DOMAINS: *value = h->pers_G; return TMM_OK;
+        case TMM_Q_WORKSPACE: *value = (long long)h->P.total; return TMM_OK;
+        case TMM_Q_COMPUTE_UNITS: *value = h->num_cu; return TMM_OK;
+        default: return TMM_EINVAL;
+    }
 }
 
 int tmm_year_adjoint(tmm_handle h, const double* y0, const double* obs, int ckpt_every, double* J_host,

@@ -87,6 +87,16 @@ __device__ __forceinline__ double insolation(double lat_deg, double t) {
     return q > 0.0 ? q : 0.0;
 }
 
+// Insolation table ins[j][l] = I_SWR(lat_l, j/nstep) for every step of the year
+// and every distinct latitude of the grid (computed once per handle).
+__global__ void k_insolation_table(int nstep, int nlat, const double* __restrict__ lat_u,
+                                   double* __restrict__ ins) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nstep * nlat) return;
+    const int j = idx / nlat, l = idx % nlat;
+    ins[idx] = insolation(lat_u[l], (double)j / (double)nstep);
+}
+
 // Production f = alpha N+/(N+ + K_1) * I/(I + K_I) (section 2.2.1) and
 // derivatives.  I = I_SWR sigma_PAR (1 - sigma_ice) exp(-z K_H2O); the
 // exponential factor comes from the per-member light table.
@@ -167,6 +177,9 @@ struct Grid {
     const double* lat;       // [ncol]
     const double* area;      // [ncol]
     const double* dz;        // [nlayer]
+    const double* ins;       // [nstep][nlat] insolation per step and distinct latitude
+    const int* col_lat;      // [ncol] row of each column in the insolation table
+    int nlat;
 };
 
 struct Model {
@@ -208,7 +221,7 @@ struct TileLds {
 };
 
 template <int MAXR, int MAXC>
-__device__ __forceinline__ TileMap build_tile(const Grid& g, TileLds<MAXR, MAXC>& L, double t) {
+__device__ __forceinline__ TileMap build_tile(const Grid& g, TileLds<MAXR, MAXC>& L, int jstep) {
     TileMap tm;
     tm.c0 = g.tile_col[blockIdx.x];
     const int c1 = g.tile_col[blockIdx.x + 1];
@@ -221,7 +234,7 @@ __device__ __forceinline__ TileMap build_tile(const Grid& g, TileLds<MAXR, MAXC>
         const int nc = g.col_start[c + 1] - g.col_start[c];
         L.col_r0[lc] = (short)s;
         L.col_nc[lc] = (short)nc;
-        L.Q[lc] = t >= 0.0 ? insolation(g.lat[c], t) : 0.0;
+        L.Q[lc] = jstep >= 0 ? g.ins[(size_t)jstep * g.nlat + g.col_lat[c]] : 0.0;
         for (int k = 0; k < nc; ++k) {
             L.row_col[s + k] = (short)lc;
             L.row_k[s + k] = (short)k;
@@ -297,8 +310,7 @@ __global__ void k_step(Grid g, Model md, Mats mt, int W, int tpr, int j, double 
     int k0, k1;
     double w;
     step_phase(j, g.nstep, g.nmat, k0, k1, w);
-    const double t = (double)(j % g.nstep) / (double)g.nstep;
-    const TileMap tm = build_tile<MAXR, MAXC>(g, L, t);
+    const TileMap tm = build_tile<MAXR, MAXC>(g, L, j % g.nstep);
     double* s_z = s_dyn;                                   // [nrows][W]
     double* s_zd = s_dyn + (size_t)tm.nrows * W;           // tangent [nrows][W]
 
@@ -419,8 +431,7 @@ __global__ void k_adjoint(Grid g, Model md, Mats mt, int W, int nb, int j, doubl
     extern __shared__ double s_dyn[];
     __shared__ TileLds<MAXR, MAXC> L;
     constexpr int NP = NTR == 2 ? 7 : 5;
-    const double t = (double)(j % g.nstep) / (double)g.nstep;
-    const TileMap tm = build_tile<MAXR, MAXC>(g, L, use_ae ? t : -1.0);
+    const TileMap tm = build_tile<MAXR, MAXC>(g, L, use_ae ? j % g.nstep : -1);
     double* s_lam = s_dyn;                                  // [nrows][W]
     double* s_contrib = s_dyn + (size_t)tm.nrows * W;       // [blockDim][NP]
 
@@ -592,7 +603,7 @@ __global__ void k_tile_sqdiff(Grid g, int W, int ntr, int nb, const double* __re
                               const double* __restrict__ b, int volume, double* __restrict__ part) {
     __shared__ TileLds<MAXR, MAXC> L;
     __shared__ double s_red[256];
-    const TileMap tm = build_tile<MAXR, MAXC>(g, L, -1.0);
+    const TileMap tm = build_tile<MAXR, MAXC>(g, L, -1);
     for (int slot = 0; slot < nb; ++slot) {
         double s = 0.0;
         for (int rr = threadIdx.x; rr < tm.nrows; rr += blockDim.x) {
@@ -621,7 +632,7 @@ template <int MAXR, int MAXC>
 __global__ void k_tile_volume(Grid g, double* __restrict__ part) {
     __shared__ TileLds<MAXR, MAXC> L;
     __shared__ double s_red[256];
-    const TileMap tm = build_tile<MAXR, MAXC>(g, L, -1.0);
+    const TileMap tm = build_tile<MAXR, MAXC>(g, L, -1);
     double s = 0.0;
     for (int rr = threadIdx.x; rr < tm.nrows; rr += blockDim.x)
         s += g.area[tm.c0 + L.row_col[rr]] * g.dz[L.row_k[rr]];

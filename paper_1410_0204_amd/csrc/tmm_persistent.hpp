@@ -1,0 +1,306 @@
+// Persistent model-year kernel: all nstep time steps of one model year in a
+// single cooperative launch.
+//
+// The time step is the one of section 3 of the paper,
+//     y_{j+1} = Ai(t_j) (Ae(t_j) y_j + dt_d q(y_j, u)),
+// iterated over a model year (section 4).  On the global 2.8-degree grid one
+// step moves ~20 MB of matrix values but takes only a few microseconds of
+// arithmetic, so a kernel per step is bound by launch and memory latency.
+// Here instead:
+//
+//  * Every workgroup owns a fixed "domain" of whole water columns (at most
+//    one row per thread) for the whole year.
+//  * The two monthly matrices in use -- the thread's row of Ae and its row of
+//    the column block of Ai, for months k0 and k1 -- live in VGPRs and are
+//    reloaded only when the month pair changes (12 times a year).  Across the
+//    chip the register file holds the interpolation bracket of the whole
+//    matrix set, so no step streams matrix values from memory.
+//  * The implicit operator acts within a water column (section 3), so the
+//    vertical product and the biogeochemistry (section 5: one column at a
+//    time) only touch the domain's own rows, kept in LDS.
+//  * Only the explicit (horizontal) product reads rows of other domains.
+//    Each domain publishes its new state to a global ping-pong buffer and
+//    then a step counter with an agent-scope release store; a domain starts
+//    step j after it has read a counter >= j from every domain its Ae rows
+//    touch (and every domain that touches it, so that
+//    no buffer is overwritten while a neighbour still reads it).
+//  * The published state is stored with agent-scope (write-through) stores;
+//    the flag is a release store and the waiting side polls with relaxed
+//    loads followed by one acquire fence, so each step costs one L2
+//    write-back and one L2 invalidate per workgroup.  Larger domains (512
+//    threads) mean fewer of these per L2.
+//  * Waits are bounded: after spin_limit polls a workgroup sets a global
+//    abort flag and returns; every other workgroup sees the flag and returns
+//    too, so the grid always drains.  Cooperative launch guarantees that all
+//    workgroups are resident.
+#pragma once
+
+#include "tmm_device.hpp"
+
+namespace tmm {
+
+constexpr int kPersistThreadsMax = 512;   // rows per domain (one per thread), at most
+constexpr int kNeuMax = 4;             // euphotic layers supported by this kernel
+constexpr int kEllMax = 8;             // Ae nonzeros per row supported by this kernel
+
+struct Persist {
+    const int* block_dom;   // [G] domain of each workgroup
+    const int* dom_col;     // [G+1] first water column of each domain
+    const int* dep_ptr;     // [G+1]
+    const int* dep_idx;     // domains each domain waits for
+    int* flags;             // [G] number of steps each domain has published
+    int* abort_flag;        // non-zero once any wait gave up
+    long long spin_limit;
+};
+
+template <int KMAX>
+struct RowMats {
+    int col[kEllMax];       // Ae column indices of the row
+    int loc[kEllMax];       // local row of that column in this domain, or -1
+    double e0[kEllMax], e1[kEllMax];   // Ae row, months k0 and k1
+    double a0[KMAX], a1[KMAX];         // row of the Ai block, months k0 and k1
+};
+
+template <int KMAX>
+__device__ __forceinline__ void load_month(const Mats& mt, const Grid& g, int m, int r, size_t blk, int nc, int k,
+                                           double* e, double* a) {
+#pragma unroll
+    for (int s = 0; s < kEllMax; ++s)
+        e[s] = s < mt.ew ? mt.ae[(size_t)m * mt.ae_month + (size_t)s * g.npad + r] : 0.0;
+#pragma unroll
+    for (int s = 0; s < KMAX; ++s)
+        a[s] = s < nc ? mt.ai_rm[(size_t)m * mt.ai_month + blk + (size_t)k * nc + s] : 0.0;
+}
+
+// NTR tracers of one member; TANGENT also steps v = phi'(y) direction; TPB
+// threads per workgroup = maximum rows per domain.
+template <int NTR, bool TANGENT, int KMAX, int TPB>
+__global__ __launch_bounds__(TPB, 1) void k_year_persistent(
+    Grid g, Model md, Mats mt, Persist ps, double dtd, const double* __restrict__ y_in,
+    double* __restrict__ y_out, double* __restrict__ buf0, double* __restrict__ buf1,
+    const double* __restrict__ v_in, double* __restrict__ v_out, double* __restrict__ vbuf0,
+    double* __restrict__ vbuf1) {
+    constexpr int TV = TANGENT ? NTR : 1;
+    __shared__ short s_rowcol[TPB];
+    __shared__ short s_rowk[TPB];
+    __shared__ short s_colr0[TPB];
+    __shared__ short s_colnc[TPB];
+    __shared__ double s_y[TPB * NTR];
+    __shared__ double s_z[TPB * NTR];
+    __shared__ double s_v[TPB * TV];
+    __shared__ double s_zd[TPB * TV];
+    __shared__ int s_fail;
+
+    const int tid = threadIdx.x;
+    const int d = ps.block_dom[blockIdx.x];
+    const int c0 = ps.dom_col[d], c1 = ps.dom_col[d + 1];
+    const int r0 = g.col_start[c0];
+    const int nrows = g.col_start[c1] - r0;
+    for (int lc = tid; lc < c1 - c0; lc += blockDim.x) {
+        const int s = g.col_start[c0 + lc] - r0;
+        const int nc = g.col_start[c0 + lc + 1] - g.col_start[c0 + lc];
+        s_colr0[lc] = (short)s;
+        s_colnc[lc] = (short)nc;
+        for (int k = 0; k < nc; ++k) {
+            s_rowcol[s + k] = (short)lc;
+            s_rowk[s + k] = (short)k;
+        }
+    }
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
+
+    const bool own = tid < nrows;
+    const int r = r0 + (own ? tid : 0);
+    const int lc = own ? s_rowcol[tid] : 0;
+    const int k = own ? s_rowk[tid] : 0;
+    const int nc = own ? s_colnc[lc] : 1;
+    const int lr0 = own ? s_colr0[lc] : 0;
+    const int c = c0 + lc;
+    const size_t blk = (size_t)g.blk_off[c];
+    const int latrow = g.col_lat[c];
+
+    // biogeochemical constants of this row (member 0 of the state)
+    const int m = md.member[0];
+    const BgcParams p = load_params(md.u, md.model, md.nparam, m);
+    const double rho = md.rho[((size_t)m * (g.nlayer + 1) + nc) * g.nlayer + k];
+    const int ne = nc < g.neu ? nc : g.neu;
+    double light[kNeuMax], hz[kNeuMax];
+#pragma unroll
+    for (int e = 0; e < kNeuMax; ++e) {
+        light[e] = e < ne ? md.light[(size_t)m * g.nlayer + e] : 0.0;
+        hz[e] = e < ne ? g.dz[e] : 0.0;
+    }
+
+    RowMats<KMAX> R;
+#pragma unroll
+    for (int s = 0; s < kEllMax; ++s) {
+        R.col[s] = s < mt.ew ? mt.ae_col[(size_t)s * g.npad + r] : r;
+        const int lr = R.col[s] - r0;
+        R.loc[s] = (lr >= 0 && lr < nrows) ? lr : -1;
+    }
+
+    // own state
+    double yr[NTR], vr[TV];
+#pragma unroll
+    for (int t = 0; t < NTR; ++t) {
+        yr[t] = own ? y_in[(size_t)r * NTR + t] : 0.0;
+        s_y[tid * NTR + t] = yr[t];
+        if (TANGENT) {
+            vr[t % TV] = own ? v_in[(size_t)r * NTR + t] : 0.0;
+            s_v[tid * TV + t % TV] = vr[t % TV];
+        }
+    }
+    const int dep0 = ps.dep_ptr[d], ndep = ps.dep_ptr[d + 1] - dep0;
+    int m0 = -1, m1 = -1;
+    __syncthreads();
+
+    for (int j = 0; j < g.nstep; ++j) {
+        int k0, k1;
+        double w;
+        step_phase(j, g.nstep, g.nmat, k0, k1, w);
+        if (k0 != m0 || k1 != m1) {
+            if (own) {
+                if (k0 == m1) {
+#pragma unroll
+                    for (int s = 0; s < kEllMax; ++s) R.e0[s] = R.e1[s];
+#pragma unroll
+                    for (int s = 0; s < KMAX; ++s) R.a0[s] = R.a1[s];
+                } else {
+                    load_month<KMAX>(mt, g, k0, r, blk, nc, k, R.e0, R.a0);
+                }
+                load_month<KMAX>(mt, g, k1, r, blk, nc, k, R.e1, R.a1);
+            }
+            m0 = k0;
+            m1 = k1;
+        }
+        const double om = 1.0 - w;
+        const double Q = g.ins[(size_t)j * g.nlat + latrow];
+
+        // sources from the domain's own rows (no wait needed)
+        double q[NTR], qd[TV];
+        {
+            double Phi = 0.0, fk = 0.0, Phid = 0.0, fdk = 0.0;
+#pragma unroll
+            for (int e = 0; e < kNeuMax; ++e) {
+                if (e < ne) {
+                    const double N = s_y[(lr0 + e) * NTR];
+                    const Production pr = production(p, N, Q, light[e]);
+                    Phi += hz[e] * pr.f;
+                    if (e == k) fk = pr.f;
+                    if (TANGENT) {
+                        const double fd = pr.dfdN * s_v[(lr0 + e) * TV];
+                        Phid += hz[e] * fd;
+                        if (e == k) fdk = fd;
+                    }
+                }
+            }
+            const double dop = NTR > 1 ? yr[NTR - 1] : 0.0;
+            q[0] = -fk + p.lam * dop + (1.0 - p.sig) * Phi * rho;
+            if (NTR > 1) q[NTR - 1] = p.sig * fk - p.lam * dop;
+            if (TANGENT) {
+                const double dopd = NTR > 1 ? vr[TV - 1] : 0.0;
+                qd[0] = -fdk + p.lam * dopd + (1.0 - p.sig) * Phid * rho;
+                if (NTR > 1) qd[TV - 1] = p.sig * fdk - p.lam * dopd;
+            }
+        }
+
+        // wait until every neighbouring domain has published y_j: relaxed
+        // polling, then one acquire fence (the acquire half of the flag's
+        // release/acquire pair) in each polling wave
+        for (int qi = tid; qi < ndep; qi += blockDim.x) {
+            const int e = ps.dep_idx[dep0 + qi];
+            long long it = 0;
+            while (__hip_atomic_load(&ps.flags[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < j) {
+                ++it;
+                if (it > ps.spin_limit ||
+                    ((it & 63) == 0 && __hip_atomic_load(ps.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                    __hip_atomic_store(ps.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s_fail = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (tid < ndep) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+        if (s_fail) return;
+
+        // z = Ae(t_j) y_j + dt_d q
+        const double* src = j == 0 ? y_in : ((j & 1) ? buf1 : buf0);
+        const double* vsrc = j == 0 ? v_in : ((j & 1) ? vbuf1 : vbuf0);
+        if (own) {
+            double acc[NTR], accd[TV];
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) acc[t] = 0.0;
+#pragma unroll
+            for (int t = 0; t < TV; ++t) accd[t] = 0.0;
+#pragma unroll
+            for (int s = 0; s < kEllMax; ++s) {
+                if (s < mt.ew) {
+                    const double a = om * R.e0[s] + w * R.e1[s];
+                    const int lr = R.loc[s];
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) {
+                        const double yy = lr >= 0 ? s_y[lr * NTR + t] : src[(size_t)R.col[s] * NTR + t];
+                        acc[t] += a * yy;
+                        if (TANGENT) {
+                            const double vv = lr >= 0 ? s_v[lr * TV + t % TV] : vsrc[(size_t)R.col[s] * NTR + t];
+                            accd[t % TV] += a * vv;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) {
+                s_z[tid * NTR + t] = acc[t] + dtd * q[t];
+                if (TANGENT) s_zd[tid * TV + t % TV] = accd[t % TV] + dtd * qd[t % TV];
+            }
+        }
+        __syncthreads();
+
+        // y_{j+1} = Ai(t_j) z, within the water column
+        double* dst = j == g.nstep - 1 ? y_out : ((j & 1) ? buf0 : buf1);
+        double* vdst = j == g.nstep - 1 ? v_out : ((j & 1) ? vbuf0 : vbuf1);
+        if (own) {
+            double acc[NTR], accd[TV];
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) acc[t] = 0.0;
+#pragma unroll
+            for (int t = 0; t < TV; ++t) accd[t] = 0.0;
+#pragma unroll
+            for (int s = 0; s < KMAX; ++s) {
+                if (s < nc) {
+                    const double a = om * R.a0[s] + w * R.a1[s];
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) {
+                        acc[t] += a * s_z[(lr0 + s) * NTR + t];
+                        if (TANGENT) accd[t % TV] += a * s_zd[(lr0 + s) * TV + t % TV];
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) {
+                yr[t] = acc[t];
+                s_y[tid * NTR + t] = acc[t];
+                // agent-scope stores write through the XCD's L2, so the release
+                // below has no dirty lines of the exchange buffers to write back
+                __hip_atomic_store(&dst[(size_t)r * NTR + t], acc[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (TANGENT) {
+                    vr[t % TV] = accd[t % TV];
+                    s_v[tid * TV + t % TV] = accd[t % TV];
+                    __hip_atomic_store(&vdst[(size_t)r * NTR + t], accd[t % TV], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(&ps.flags[d], j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void k_fill_int(int* __restrict__ x, int len, int value) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) x[i] = value;
+}
+
+}  // namespace tmm

@@ -1,0 +1,253 @@
+"""Host drivers over the libtmm ABI: spin-up, Newton-Krylov, ensembles.
+
+These follow sections 4, 6 and 7 of the paper.  A periodic solution is a
+fixed point of the year map phi (section 4).  Spin-up finds it by the plain
+iteration y <- phi(y) and logs ||y - phi(y)||_2 each year (section 7).  The
+Newton solver works on F(y) = y - phi(y) with a globalising backtracking line
+search (section 6).  Its linear systems are solved matrix-free by restarted
+GMRES with modified Gram-Schmidt and inexact-Newton forcing terms after
+Eisenstat and Walker (section 6.2).  Jacobian-vector products come from
+libtmm, either as finite differences or as the exact tangent (section 6.1).
+
+The Krylov vectors are host float64 arrays: one state holds 0.84 MB on the
+global grid, small next to a model year, so each product copies one vector to
+the device and one back.  Every model year runs in libtmm.
+"""
+
+import hashlib
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import tmm as _tmm
+
+
+def _log(path, rec):
+    if path:
+        with open(path, "a") as fh:
+            fh.write(json.dumps(rec) + "\n")
+
+
+def _config_hash(t, u):
+    h = hashlib.sha256()
+    h.update(np.asarray([t.n, t.nstep, t.nmat, t.model], dtype=np.int64).tobytes())
+    h.update(np.ascontiguousarray(u, dtype=np.float64).tobytes())
+    for k in ("col_start", "ae_rowptr", "ae_colidx", "ae_val", "ai_val"):
+        h.update(t._keep[k].tobytes())
+    return h.hexdigest()[:16]
+
+
+# ---------------------------------------------------------------------------
+# Spin-up (pseudo-time fixed-point iteration)
+# ---------------------------------------------------------------------------
+
+def spinup(t, u, y0, years, tol=0.0, log_path=None, state_path=None, state_every=0, resume=False):
+    """Iterates y <- phi(y) for up to ``years`` model years.
+
+    Returns (y, residuals), where residuals[k] = ||y_k - phi(y_k)||_2 of the
+    year that started from y_k (the residual of section 7).  Stops early when
+    a residual falls to ``tol`` or below.  With ``state_path`` the state is
+    saved every ``state_every`` years as .npz (y, year, u, config hash), and
+    ``resume`` continues from such a file when it matches the configuration.
+    """
+    u = np.atleast_2d(np.asarray(u, dtype=np.float64))
+    t.set_params(u)
+    cfg = _config_hash(t, u)
+    y = t.state(np.asarray(y0, dtype=np.float64))
+    start_year = 0
+    resid = []
+    if resume and state_path and os.path.exists(state_path):
+        with np.load(state_path, allow_pickle=False) as z:
+            if str(z["config"]) == cfg:
+                y = t.state(z["y"])
+                start_year = int(z["year"])
+                resid = list(z["resid"])
+    nxt = t.state()
+    for yr in range(start_year, years):
+        t0 = time.perf_counter()
+        _, r = t.year(y, nyears=1, out=nxt)
+        y, nxt = nxt, y
+        resid.append(float(np.linalg.norm(r[0])))
+        _log(log_path, {"kind": "spinup", "year": yr + 1, "residual": resid[-1],
+                        "seconds": time.perf_counter() - t0})
+        if state_path and state_every and (yr + 1) % state_every == 0:
+            tmp = state_path + ".tmp.npz"
+            np.savez(tmp, y=y.cpu().numpy(), year=yr + 1, u=u, config=cfg, resid=np.asarray(resid))
+            os.replace(tmp, state_path)
+        if resid[-1] <= tol:
+            break
+    return y.cpu().numpy(), np.asarray(resid)
+
+
+# ---------------------------------------------------------------------------
+# GMRES(m) with modified Gram-Schmidt, x0 = 0
+# ---------------------------------------------------------------------------
+
+def gmres(matvec, b, rtol, restart=30, maxiter=300, log=None):
+    """Solves A x = b to ||b - A x|| <= rtol ||b||.
+
+    Returns (x, r, matvecs) with r = b - A x the true residual at exit."""
+    bnorm = float(np.linalg.norm(b))
+    x = np.zeros_like(b)
+    if bnorm == 0.0:
+        return x, b.copy(), 0
+    target = rtol * bnorm
+    r = b.copy()
+    beta = bnorm
+    its = 0
+    while its < maxiter and beta > target:
+        V = [r / beta]
+        H = np.zeros((restart + 1, restart))
+        g = np.zeros(restart + 1)
+        g[0] = beta
+        cs, sn = np.zeros(restart), np.zeros(restart)
+        k_done = 0
+        for k in range(restart):
+            w = matvec(V[k])
+            its += 1
+            for i in range(k + 1):                 # modified Gram-Schmidt
+                H[i, k] = float(np.dot(w, V[i]))
+                w = w - H[i, k] * V[i]
+            hk1 = float(np.linalg.norm(w))
+            H[k + 1, k] = hk1
+            for i in range(k):                     # earlier Givens rotations
+                tmp = cs[i] * H[i, k] + sn[i] * H[i + 1, k]
+                H[i + 1, k] = -sn[i] * H[i, k] + cs[i] * H[i + 1, k]
+                H[i, k] = tmp
+            den = math.hypot(H[k, k], H[k + 1, k])
+            cs[k], sn[k] = (1.0, 0.0) if den == 0.0 else (H[k, k] / den, H[k + 1, k] / den)
+            H[k, k] = cs[k] * H[k, k] + sn[k] * H[k + 1, k]
+            H[k + 1, k] = 0.0
+            g[k + 1] = -sn[k] * g[k]
+            g[k] = cs[k] * g[k]
+            k_done = k + 1
+            if log:
+                log(its, abs(g[k + 1]))
+            if abs(g[k + 1]) <= target or its >= maxiter or hk1 == 0.0:
+                break
+            V.append(w / hk1)
+        coef = np.linalg.solve(np.triu(H[:k_done, :k_done]), g[:k_done])
+        for i in range(k_done):
+            x = x + coef[i] * V[i]
+        r = b - matvec(x)
+        its += 1
+        beta = float(np.linalg.norm(r))
+    return x, r, its
+
+
+# ---------------------------------------------------------------------------
+# Inexact Newton-Krylov for y = phi(y)
+# ---------------------------------------------------------------------------
+
+def newton_krylov(t, u, y0, tol=1e-8, jvp="fd", restart=30, max_newton=30, max_krylov=300,
+                  eta0=0.5, eta_max=0.9, gamma=0.9, ew_alpha=2.0, line_search=True, log_path=None):
+    """Solves F(y) = y - phi(y) = 0 from y0 until ||F|| <= tol.
+
+    Linear systems (I - phi'(y)) d = -F by GMRES(restart) with forcing terms
+    eta_k = gamma (|F_k|/|F_{k-1}|)^ew_alpha (Eisenstat-Walker choice 2,
+    safeguarded, capped at eta_max).  ``jvp`` is "fd" (finite differences
+    reusing phi(y): one model year per product) or "tangent" (exact).
+    Backtracking on |F|^2 with quadratic/cubic interpolation (Dennis and
+    Schnabel) when ``line_search``.  Returns (y, history); history counts
+    year maps (tangent years count 1 each).
+    """
+    u = np.atleast_2d(np.asarray(u, dtype=np.float64))
+    t.set_params(u)
+    shape = (t.n, t.W)
+    y = np.asarray(y0, dtype=np.float64).copy()
+    yd = t.state(y)
+    phi, phi_try = t.state(), t.state()
+    years = 0
+
+    def F_of(y_host, y_dev, out):
+        nonlocal years
+        t.year(y_dev, nyears=1, out=out, residuals=False)
+        years += 1
+        return (y_host - out.cpu().numpy()).ravel()
+
+    F = F_of(y, yd, phi)
+    fnorm = float(np.linalg.norm(F))
+    hist = {"newton": [], "years": 0, "fnorm": [fnorm]}
+    _log(log_path, {"kind": "newton", "it": 0, "fnorm": fnorm, "years": years})
+    eta_prev, fnorm_prev = eta0, None
+    for it in range(1, max_newton + 1):
+        if fnorm <= tol:
+            break
+        if fnorm_prev is None:
+            eta = eta0
+        else:
+            eta = gamma * (fnorm / fnorm_prev) ** ew_alpha
+            safe = gamma * eta_prev ** ew_alpha
+            if safe > 0.1:
+                eta = max(eta, safe)
+            eta = min(eta, eta_max)
+        # keep the linear solve from asking for more than the outer tolerance needs
+        eta = max(eta, 0.5 * tol / fnorm)
+        phi_y = phi
+
+        def matvec(v):
+            nonlocal years
+            vd = t.state(v.reshape(shape))
+            if jvp == "tangent":
+                _, jv = t.year_jvp(yd, vd, mode=_tmm.TMM_JVP_TANGENT, want_phi=False)
+            else:
+                _, jv = t.year_jvp(yd, vd, mode=_tmm.TMM_JVP_FD_GIVEN_PHI, phi=phi_y)
+            years += 1
+            return v - jv.cpu().numpy().ravel()
+
+        d, rlin, mv = gmres(matvec, -F, eta, restart=restart, maxiter=max_krylov)
+        lres = float(np.linalg.norm(rlin))
+        # line search on f = |F|^2 / 2; J d = -F - r, so the slope is F.(J d) = -|F|^2 - F.r
+        lam, f0 = 1.0, 0.5 * fnorm ** 2
+        slope = -fnorm ** 2 - float(np.dot(F, rlin))
+        lam_prev, fl_prev = None, None
+        while True:
+            y_try = y + lam * d.reshape(shape)
+            yt = t.state(y_try)
+            F_try = F_of(y_try, yt, phi_try)
+            f_try = 0.5 * float(np.dot(F_try, F_try))
+            if not line_search or f_try <= f0 + 1e-4 * lam * slope or lam < 1e-4:
+                break
+            if lam_prev is None:                        # quadratic model
+                lam_new = -slope / (2.0 * (f_try - f0 - slope))
+            else:                                       # cubic model through two trial points
+                a_ = np.array([[1 / lam ** 2, -1 / lam_prev ** 2], [-lam_prev / lam ** 2, lam / lam_prev ** 2]])
+                rhs = np.array([f_try - f0 - lam * slope, fl_prev - f0 - lam_prev * slope]) / (lam - lam_prev)
+                ca, cb = a_ @ rhs
+                if ca == 0:
+                    lam_new = -slope / (2 * cb)
+                else:
+                    disc = max(cb * cb - 3 * ca * slope, 0.0)
+                    lam_new = (-cb + math.sqrt(disc)) / (3 * ca)
+            lam_prev, fl_prev = lam, f_try
+            lam = float(min(max(lam_new, 0.1 * lam), 0.5 * lam))
+        y, yd, F = y_try, yt, F_try
+        phi, phi_try = phi_try, phi
+        fnorm_prev, eta_prev = fnorm, eta
+        fnorm = float(np.linalg.norm(F))
+        rec = {"kind": "newton", "it": it, "fnorm": fnorm, "eta": eta, "krylov": mv, "lambda": lam,
+               "linear_residual": lres, "years": years}
+        hist["newton"].append(rec)
+        hist["fnorm"].append(fnorm)
+        _log(log_path, rec)
+    hist["years"] = years
+    return y, hist
+
+
+# ---------------------------------------------------------------------------
+# Ensembles with uneven spin-up lengths
+# ---------------------------------------------------------------------------
+
+def ensemble(t, U, lengths, y0):
+    """Runs member b of parameter table U for lengths[b] model years, all in
+    one batched state (members leave the batch when their years are done)."""
+    U = np.atleast_2d(np.asarray(U, dtype=np.float64))
+    lengths = np.asarray(lengths, dtype=np.int32)
+    t.set_params(U)
+    y = t.state(np.asarray(y0, dtype=np.float64))
+    out, resid = t.year(y, nyears=int(lengths.max()), years_per_member=lengths)
+    return out.cpu().numpy(), resid
+

@@ -20,10 +20,17 @@ TMM_MODEL_N = 1
 TMM_MODEL_NDOP = 2
 TMM_JVP_FD = 0
 TMM_JVP_TANGENT = 1
+TMM_JVP_FD_GIVEN_PHI = 2
+TMM_OPT_PERSISTENT = 1
+TMM_OPT_DOMAIN_ROWS = 2
+TMM_Q_PERSISTENT = 1
+TMM_Q_DOMAINS = 2
+TMM_Q_WORKSPACE = 3
+TMM_Q_COMPUTE_UNITS = 4
 
 EXPORTED = (
     "tmm_workspace_bytes", "tmm_create", "tmm_destroy", "tmm_set_params", "tmm_step", "tmm_year",
-    "tmm_year_jvp", "tmm_year_adjoint", "tmm_strerror",
+    "tmm_year_jvp", "tmm_year_adjoint", "tmm_set_option", "tmm_query", "tmm_strerror",
 )
 
 _dp = C.POINTER(C.c_double)
@@ -69,6 +76,8 @@ def load():
             "tmm_year": (C.c_int, [vp, C.c_int, _ip, vp, vp, _dp]),
             "tmm_year_jvp": (C.c_int, [vp, C.c_int, vp, vp, vp, vp]),
             "tmm_year_adjoint": (C.c_int, [vp, vp, vp, C.c_int, _dp, _dp, vp]),
+            "tmm_set_option": (C.c_int, [vp, C.c_int, C.c_int]),
+            "tmm_query": (C.c_int, [vp, C.c_int, C.POINTER(C.c_longlong)]),
             "tmm_strerror": (C.c_char_p, [C.c_int]),
         }
         for name, (res, args) in sig.items():
@@ -141,6 +150,16 @@ def tmm_year_adjoint(h, y0, obs, ckpt_every, J_host, dJdu_host, dJdy0):
                                    _ptr(dJdy0)), "tmm_year_adjoint")
 
 
+def tmm_set_option(h, option, value):
+    _check(load().tmm_set_option(h, int(option), int(value)), "tmm_set_option")
+
+
+def tmm_query(h, what):
+    v = C.c_longlong()
+    _check(load().tmm_query(h, int(what), C.byref(v)), "tmm_query")
+    return v.value
+
+
 # --- handle with its workspace ----------------------------------------------
 
 def _i32(a):
@@ -203,6 +222,12 @@ class TMM:
         except Exception:
             pass
 
+    def set_option(self, option, value):
+        tmm_set_option(self.handle, option, value)
+
+    def query(self, what):
+        return tmm_query(self.handle, what)
+
     @property
     def W(self):
         return self.nbatch * self.ntracer
@@ -234,8 +259,14 @@ class TMM:
         tmm_year(self.handle, nyears, years_per_member, self._state_arg(y0), self._state_arg(out), resid)
         return out, resid
 
-    def year_jvp(self, y, v, mode=TMM_JVP_TANGENT, want_phi=True):
+    def year_jvp(self, y, v, mode=TMM_JVP_TANGENT, want_phi=True, phi=None):
+        """jv = phi'(y) v.  With mode TMM_JVP_FD_GIVEN_PHI pass phi = phi(y)."""
         jv = self.state()
+        if mode == TMM_JVP_FD_GIVEN_PHI:
+            if phi is None:
+                raise ValueError("TMM_JVP_FD_GIVEN_PHI needs phi")
+            tmm_year_jvp(self.handle, mode, self._state_arg(y), self._state_arg(v), self._state_arg(phi), jv)
+            return phi, jv
         phi = self.state() if want_phi else None
         tmm_year_jvp(self.handle, mode, self._state_arg(y), self._state_arg(v), phi, jv)
         return phi, jv

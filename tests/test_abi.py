@@ -1,0 +1,80 @@
+"""C ABI checks that need no GPU: exported symbols and descriptor validation."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "tmm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(tmm_\w+)\s*\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    from paper_1410_0204_amd import tmm
+    lib = tmm.load()
+    names = _declared()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(tmm.EXPORTED) == names
+
+
+def _desc(inp, **over):
+    from paper_1410_0204_amd import tmm
+    a = inp.desc_arrays()
+    a.update({k: v for k, v in over.items()})
+    keep = {k: (np.ascontiguousarray(v, dtype=np.int32) if np.asarray(v).dtype.kind in "iu"
+                else np.ascontiguousarray(v, dtype=np.float64))
+            for k, v in a.items() if isinstance(v, np.ndarray)}
+    ip = lambda x: x.ctypes.data_as(C.POINTER(C.c_int))  # noqa: E731
+    dp = lambda x: x.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+    d = tmm.TmmDesc(a["n"], a["ncol"], a["nlayer"], ip(keep["col_start"]), dp(keep["lat"]), dp(keep["area"]),
+                    dp(keep["dz"]), a["nmat"], a["nstep"], a["model"], a["neuphotic"], over.get("nbatch_max", 1),
+                    over.get("adjoint_nbatch_max", 1), over.get("ckpt_every", 240),
+                    keep["ae_colidx"].size, ip(keep["ae_rowptr"]), ip(keep["ae_colidx"]), dp(keep["ae_val"]),
+                    keep["ai_colidx"].size, ip(keep["ai_rowptr"]), ip(keep["ai_colidx"]), dp(keep["ai_val"]))
+    return d, keep
+
+
+def _status(d):
+    from paper_1410_0204_amd import tmm
+    n = C.c_size_t()
+    return tmm.load().tmm_workspace_bytes(C.byref(d), C.byref(n)), n.value
+
+
+def test_valid_descriptor_sizes_workspace(tiny_n):
+    d, _ = _desc(tiny_n)
+    rc, n = _status(d)
+    assert rc == 0 and n > 0
+
+
+def test_invalid_descriptors_are_rejected(tiny_n):
+    tm = tiny_n.tm
+    bad_rowptr = tm.ae_rowptr.copy()
+    bad_rowptr[5], bad_rowptr[6] = bad_rowptr[6], bad_rowptr[5] - 1      # not monotone
+    bad_col = tm.ae_colidx.copy()
+    bad_col[3] = tiny_n.n                                                 # out of range
+    cross = tm.ai_colidx.copy()
+    cross[0] = tiny_n.grid.col_start[1]                                   # couples two columns
+    for over in ({"ae_rowptr": bad_rowptr}, {"ae_colidx": bad_col}, {"ai_colidx": cross},
+                 {"nstep": 2876}, {"nmat": 7}, {"model": 3}, {"neuphotic": 0},
+                 {"ckpt_every": 7}, {"nbatch_max": 0}, {"adjoint_nbatch_max": 2},
+                 {"dz": np.r_[tiny_n.grid.dz[:-1], -1.0]}):
+        d, _ = _desc(tiny_n, **over)
+        rc, _ = _status(d)
+        assert rc == -1, over
+
+
+def test_strerror():
+    from paper_1410_0204_amd import tmm
+    assert tmm.tmm_strerror(0) == "ok"
+    assert "invalid" in tmm.tmm_strerror(-1)
+    assert tmm.tmm_strerror(12345) == "unknown status"

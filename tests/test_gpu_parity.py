@@ -75,7 +75,7 @@ def test_batched_members_match_unbatched(inputs):
     for m in range(3):
         t.set_params(U[m])
         ym, rm = t.year(t.state(y0[:, 2 * m:2 * m + 2]))
-        assert _rel(ym.cpu().numpy(), yb[:, 2 * m:2 * m + 2]) <= 1e-15
+        assert _rel(ym.cpu().numpy(), yb[:, 2 * m:2 * m + 2]) <= 1e-13
         assert rm[0, 0] == pytest.approx(rb[0, m], rel=1e-14)
 
 
@@ -139,6 +139,50 @@ def test_adjoint_parity(inputs, name, ckpt):
     assert _rel(dy0.cpu().numpy(), eY) <= 1e-10
 
 
+@pytest.mark.parametrize("name", ["tiny_n", "tiny_ndop", "small"])
+def test_persistent_and_per_step_paths_agree(inputs, name):
+    """The single-launch year kernel and the per-step kernels give the oracle's year."""
+    tmm = _lib()
+    inp = inputs[name]
+    t = _make(inp)
+    assert t.query(tmm.TMM_Q_PERSISTENT) == 1
+    o = oracle.Oracle(inp)
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    y0 = inp.initial_state()
+    exp, _ = o.year(u, y0)
+    out = {}
+    for pers in (1, 0):
+        t.set_option(tmm.TMM_OPT_PERSISTENT, pers)
+        got, _ = t.year(t.state(y0))
+        out[pers] = got.cpu().numpy()
+        assert _rel(out[pers], exp) <= 1e-12, pers
+    assert _rel(out[1], out[0]) <= 1e-12
+
+
+@pytest.mark.parametrize("rows", [16, 32, 64, 256, 512])
+def test_persistent_domain_sizes(inputs, rows):
+    """Every domain partition (and so every dependency pattern) gives the same year."""
+    tmm = _lib()
+    inp = inputs["small"]
+    t = _make(inp)
+    t.set_option(tmm.TMM_OPT_DOMAIN_ROWS, rows)
+    print(f"[gpu] domains: {t.query(tmm.TMM_Q_DOMAINS)}", flush=True)
+    o = oracle.Oracle(inp)
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    y0 = inp.initial_state()
+    got, _ = t.year(t.state(y0), nyears=2)
+    exp, _ = o.year(u, y0, 2)
+    assert _rel(got.cpu().numpy(), exp) <= 1e-12
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(y0.shape)
+    phi, jv = t.year_jvp(t.state(y0), t.state(v), mode=tmm.TMM_JVP_TANGENT)
+    ephi, ejv = o.year_tangent(u, y0, v)
+    assert _rel(phi.cpu().numpy(), ephi) <= 1e-12
+    assert _rel(jv.cpu().numpy(), ejv) <= 1e-11
+
+
 def test_year_is_deterministic(inputs):
     inp = inputs["small"]
     t = _make(inp)
@@ -158,6 +202,9 @@ def test_global_step_and_year_parity(global_inputs):
     """Full 128x64x15 workload (52749 points, N-DOP) in the benchmark's launch configuration."""
     inp = global_inputs
     t = _make(inp)
+    tmm = _lib()
+    assert t.query(tmm.TMM_Q_PERSISTENT) == 1
+    print(f"[gpu] global: {t.query(tmm.TMM_Q_DOMAINS)} domains on {t.query(tmm.TMM_Q_COMPUTE_UNITS)} CUs", flush=True)
     o = oracle.Oracle(inp)
     u = synth.nominal(inp.model)
     t.set_params(u)

@@ -12,6 +12,16 @@ kernel against MI355X peak HBM bandwidth (roofline), the adjoint/forward
 cost ratio, and the CPU oracle's rate on the host as a reported baseline.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Further measurements, each printed as its own JSON line (not run by default):
+  --mode newton       Newton-Krylov steady periodic solve on the same grid
+                      (FD and tangent Jacobian-vector products), with spin-up
+                      at the same cost for comparison;
+  --mode ensemble     64 N-DOP parameter vectors (Latin hypercube) with spin-up
+                      lengths 1..8 years on the 256x128x23 grid, batched, against
+                      one-member runs;
+  --mode copy         a plain 512 MiB device copy, for scaling hardware byte
+                      counters.
 """
 
 import argparse
@@ -67,11 +77,17 @@ def main():
     ap.add_argument("--steps", type=int, default=20, help="timed model years")
     ap.add_argument("--warmup", type=int, default=2, help="untimed model years")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="forward", choices=["forward", "newton", "ensemble", "copy"])
+    ap.add_argument("--forward-only", action="store_true",
+                    help="skip the per-step comparison and the adjoint (for hardware counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X; --gpus must be 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.mode != "forward":
+        {"newton": bench_newton, "ensemble": bench_ensemble, "copy": bench_copy}[args.mode](args)
+        return
 
     import torch
     import synth
@@ -123,7 +139,7 @@ def main():
 
     # the one-launch-per-step path on the same handle, for comparison
     per_step = None
-    if persistent:
+    if persistent and not args.forward_only:
         t.set_option(tmm.TMM_OPT_PERSISTENT, 0)
         t.year(y, nyears=1, out=ya, residuals=False)
         torch.cuda.synchronize()
@@ -137,25 +153,27 @@ def main():
         log(f"[bench] per-step kernels: {ms_ps:.3f} ms/model-year")
 
     # adjoint / forward cost ratio (one model year each, ckpt every 240 steps)
-    obs = torch.as_tensor(np.broadcast_to(inp.initial_state(), (12, n, W)).copy()
-                          * (1 + 0.05 * synth.obs_noise((12, n, W), seed=3))).to(dev)
-    t.year_adjoint(y0, obs, want_dy0=False)   # warm-up
-    torch.cuda.synchronize()
-    start.record(stream)
-    t.year_adjoint(y0, obs, want_dy0=True)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms_adj = start.elapsed_time(stop)
-    start.record(stream)
-    t.year(y0, nyears=1, out=ya, residuals=False)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms_fwd1 = start.elapsed_time(stop)
-    ratio = ms_adj / ms_fwd1
-    log(f"[bench] adjoint year {ms_adj:.2f} ms vs forward {ms_fwd1:.2f} ms: ratio {ratio:.2f}")
+    ratio = None
+    if not args.forward_only:
+        obs = torch.as_tensor(np.broadcast_to(inp.initial_state(), (12, n, W)).copy()
+                              * (1 + 0.05 * synth.obs_noise((12, n, W), seed=3))).to(dev)
+        t.year_adjoint(y0, obs, want_dy0=False)   # warm-up
+        torch.cuda.synchronize()
+        start.record(stream)
+        t.year_adjoint(y0, obs, want_dy0=True)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms_adj = start.elapsed_time(stop)
+        start.record(stream)
+        t.year(y0, nyears=1, out=ya, residuals=False)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms_fwd1 = start.elapsed_time(stop)
+        ratio = ms_adj / ms_fwd1
+        log(f"[bench] adjoint year {ms_adj:.2f} ms vs forward {ms_fwd1:.2f} ms: ratio {ratio:.2f}")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.forward_only:
         import oracle
         o = oracle.Oracle(inp)
         yh = inp.initial_state()
@@ -195,6 +213,114 @@ def main():
     }
     print(json.dumps(out), flush=True)
     t.close()
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def bench_copy(args):
+    """512 MiB device-to-device copy: reads and writes 512 MiB each."""
+    import torch
+    n = 512 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    s, e = _events()
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(3):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / 3
+    print(json.dumps({"mode": "copy", "bytes_read": n * 8, "bytes_written": n * 8, "ms": ms,
+                      "GB_per_s": 2 * n * 8 / ms / 1e6}), flush=True)
+
+
+def bench_newton(args):
+    """Steady periodic solution of the global grid by Newton-Krylov (FD and
+    tangent JVPs), and spin-up for the same number of model years."""
+    import torch
+    import synth
+    from paper_1410_0204_amd import drivers, tmm
+
+    inp = synth.global_2p8()
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=1)
+    u = synth.nominal(inp.model)
+    y0 = inp.initial_state()
+    out = {"mode": "newton", "workload": "global_128x64x15 N-DOP", "tol": 1e-8, "restart": 30}
+    for jvp in ("fd", "tangent"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y, hist = drivers.newton_krylov(t, u, y0, tol=1e-8, jvp=jvp, restart=30, max_newton=args.steps,
+                                        max_krylov=300)
+        dt = time.perf_counter() - t0
+        out[jvp] = {"fnorm": hist["fnorm"], "year_maps": hist["years"], "seconds": dt,
+                    "newton_iterations": len(hist["newton"]),
+                    "krylov_per_newton": [r["krylov"] for r in hist["newton"]]}
+        log(f"[newton/{jvp}] |F| {hist['fnorm'][0]:.3e} -> {hist['fnorm'][-1]:.3e} in {len(hist['newton'])} "
+            f"Newton steps, {hist['years']} year maps, {dt:.1f} s")
+    years = out["fd"]["year_maps"]
+    t0 = time.perf_counter()
+    _, r = drivers.spinup(t, u, y0, years=years)
+    out["spinup"] = {"years": years, "residual_first": float(r[0]), "residual_last": float(r[-1]),
+                     "seconds": time.perf_counter() - t0}
+    log(f"[spin-up] {years} years: residual {r[0]:.3e} -> {r[-1]:.3e}")
+    print(json.dumps(out), flush=True)
+
+
+def bench_ensemble(args):
+    """64 members with uneven spin-up lengths in one batched state (W = 128)
+    against one-member runs of the same grid."""
+    import torch
+    import synth
+    from paper_1410_0204_amd import tmm
+
+    t0 = time.perf_counter()
+    inp = synth.ensemble_1p4()
+    log(f"[ensemble] inputs {inp.name}: n={inp.n} ncol={inp.grid.ncol} nnz_e={inp.tm.ae_nnz} "
+        f"nnz_i={inp.tm.ai_nnz} ({time.perf_counter() - t0:.1f} s to generate)")
+    nm = 64
+    U = synth.latin_hypercube(synth.MODEL_NDOP, nm, seed=17)
+    L = synth.spinup_lengths(nm, seed=18)
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=nm)
+    s, e = _events()
+    t.set_params(U)
+    y0 = t.state(inp.initial_state(nm))
+    # warm-up: one step at full width
+    t.step(0, y0)
+    torch.cuda.synchronize()
+    s.record()
+    out_b, _ = t.year(y0, nyears=int(L.max()), years_per_member=L, residuals=False)
+    e.record()
+    torch.cuda.synchronize()
+    ms_b = s.elapsed_time(e)
+    member_years = int(L.sum())
+    # one-member runs: time one model year of member 0, extrapolate to all member-years
+    t.set_params(U[0])
+    y1 = t.state(inp.initial_state(1))
+    t.year(y1, nyears=1, residuals=False)
+    torch.cuda.synchronize()
+    s.record()
+    t.year(y1, nyears=1, residuals=False)
+    e.record()
+    torch.cuda.synchronize()
+    ms_1 = s.elapsed_time(e)
+    W = 2 * nm
+    B = bytes_per_step(inp.n, inp.tm.ae_nnz, inp.tm.ai_nnz, W)
+    res = {"mode": "ensemble", "workload": "ensemble_256x128x23 N-DOP", "n": inp.n, "members": nm,
+           "member_years": member_years, "batched_ms": ms_b,
+           "batched_member_years_per_s": member_years / (ms_b / 1000.0),
+           "one_member_ms_per_year": ms_1,
+           "sequential_member_years_per_s_extrapolated": 1000.0 / ms_1,
+           "speedup": (member_years * ms_1) / ms_b,
+           "full_width_bytes_per_step": B}
+    log(f"[ensemble] batched: {member_years} member-years in {ms_b:.0f} ms "
+        f"({res['batched_member_years_per_s']:.2f}/s); one member {ms_1:.1f} ms/year; "
+        f"speedup {res['speedup']:.1f}x")
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -78,6 +78,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2, help="untimed model years")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="forward", choices=["forward", "newton", "ensemble", "copy"])
+    ap.add_argument("--log", default=None, help="JSONL progress log (newton mode)")
     ap.add_argument("--forward-only", action="store_true",
                     help="skip the per-step comparison and the adjoint (for hardware counter runs)")
     args = ap.parse_args()
@@ -255,7 +256,7 @@ def bench_newton(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         y, hist = drivers.newton_krylov(t, u, y0, tol=1e-8, jvp=jvp, restart=30, max_newton=args.steps,
-                                        max_krylov=300)
+                                        max_krylov=300, log_path=args.log)
         dt = time.perf_counter() - t0
         out[jvp] = {"fnorm": hist["fnorm"], "year_maps": hist["years"], "seconds": dt,
                     "newton_iterations": len(hist["newton"]),
@@ -264,7 +265,7 @@ def bench_newton(args):
             f"Newton steps, {hist['years']} year maps, {dt:.1f} s")
     years = out["fd"]["year_maps"]
     t0 = time.perf_counter()
-    _, r = drivers.spinup(t, u, y0, years=years)
+    _, r = drivers.spinup(t, u, y0, years=years, log_path=args.log)
     out["spinup"] = {"years": years, "residual_first": float(r[0]), "residual_last": float(r[-1]),
                      "seconds": time.perf_counter() - t0}
     log(f"[spin-up] {years} years: residual {r[0]:.3e} -> {r[-1]:.3e}")

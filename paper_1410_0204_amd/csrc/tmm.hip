@@ -82,6 +82,7 @@ struct Plan {
     std::vector<size_t> o_tiles;
     size_t o_u, o_light, o_rho, o_drho, o_member, o_scol, o_dcol;
     size_t o_ybuf[3], o_vbuf[2], o_part, o_vec, o_ubt, o_jpart, o_ckpt, o_seg, o_final, o_mu[2];
+    size_t o_pubar, o_pjpart;       // per-domain adjoint partial sums (persistent path)
     size_t vec_stride;
     // insolation table over distinct latitudes
     std::vector<double> lat_u;
@@ -204,7 +205,10 @@ int validate(const tmm_desc* d, Plan& P) {
         P.o_final = take(astate);
         P.o_mu[0] = take(astate);
         P.o_mu[1] = take(astate);
+        P.o_pubar = take((size_t)kMaxDomains * 8 * 8);
+        P.o_pjpart = take(nm * kMaxDomains * 8);
     } else {
+        P.o_pubar = P.o_pjpart = 0;
         P.o_ubt = P.o_jpart = P.o_ckpt = P.o_seg = P.o_final = P.o_mu[0] = P.o_mu[1] = 0;
     }
     // distinct latitudes (exact values) for the insolation table
@@ -378,20 +382,24 @@ const void* persistent_kernel_tpb(int ntr, bool tangent, int kmax) {
                    : (const void*)&tmm::k_year_persistent<2, false, 32, TPB>;
 }
 
+template <int TPB>
+const void* adjoint_kernel_tpb(int ntr, int kmax) {
+    if (kmax == 16) return ntr == 1 ? (const void*)&tmm::k_adjoint_persistent<1, 16, TPB>
+                                    : (const void*)&tmm::k_adjoint_persistent<2, 16, TPB>;
+    return ntr == 1 ? (const void*)&tmm::k_adjoint_persistent<1, 32, TPB>
+                    : (const void*)&tmm::k_adjoint_persistent<2, 32, TPB>;
+}
+
+const void* adjoint_kernel(int ntr, int kmax, int tpb) {
+    return tpb == 512 ? adjoint_kernel_tpb<512>(ntr, kmax) : adjoint_kernel_tpb<256>(ntr, kmax);
+}
+
 const void* persistent_kernel(int ntr, bool tangent, int kmax, int tpb) {
     return tpb == 512 ? persistent_kernel_tpb<512>(ntr, tangent, kmax) : persistent_kernel_tpb<256>(ntr, tangent, kmax);
 }
 
-// One model year in one cooperative launch (one member).
-int launch_persistent(tmm_ctx* h, const double* y, double* out, double* a, double* b, const double* v,
-                      double* vout, double* va, double* vb) {
+tmm::Persist persist_args(tmm_ctx* h) {
     const Plan& P = h->P;
-    hipLaunchKernelGGL(tmm::k_fill_int, dim3((h->pers_G + 255) / 256), dim3(256), 0, h->stream,
-                       h->at<int>(P.o_pflags), h->pers_G, 0);
-    TMM_LAUNCHED();
-    tmm::Grid g = h->grid(h->tilings.front());
-    tmm::Model md = h->model();
-    tmm::Mats mt = h->mats();
     tmm::Persist ps;
     ps.block_dom = h->at<int>(P.o_pblock);
     ps.dom_col = h->at<int>(P.o_pdomcol);
@@ -400,10 +408,56 @@ int launch_persistent(tmm_ctx* h, const double* y, double* out, double* a, doubl
     ps.flags = h->at<int>(P.o_pflags);
     ps.abort_flag = h->at<int>(P.o_pabort);
     ps.spin_limit = 1ll << 22;
+    return ps;
+}
+
+int reset_flags(tmm_ctx* h) {
+    hipLaunchKernelGGL(tmm::k_fill_int, dim3((h->pers_G + 255) / 256), dim3(256), 0, h->stream,
+                       h->at<int>(h->P.o_pflags), h->pers_G, 0);
+    TMM_LAUNCHED();
+    return TMM_OK;
+}
+
+// Steps sr.j0 .. sr.j1-1 in one cooperative launch (one member).
+int launch_persistent(tmm_ctx* h, tmm::StepRange sr, const double* y, double* out, double* a, double* b,
+                      const double* v, double* vout, double* va, double* vb) {
+    const Plan& P = h->P;
+    int rc = reset_flags(h);
+    if (rc) return rc;
+    tmm::Grid g = h->grid(h->tilings.front());
+    tmm::Model md = h->model();
+    tmm::Mats mt = h->mats();
+    tmm::Persist ps = persist_args(h);
     double dtd = tmm::kDaysPerYear / P.nstep;
-    void* args[] = {&g, &md, &mt, &ps, &dtd, &y, &out, &a, &b, &v, &vout, &va, &vb};
+    void* args[] = {&g, &md, &mt, &ps, &sr, &dtd, &y, &out, &a, &b, &v, &vout, &va, &vb};
     TMM_TRY(hipLaunchCooperativeKernel(persistent_kernel(P.ntr, v != nullptr, h->pers_kmax, h->pers_tpb),
                                        dim3(h->pers_G), dim3(h->pers_tpb), args, 0, h->stream));
+    h->pers_used = true;
+    return TMM_OK;
+}
+
+int launch_persistent_year(tmm_ctx* h, const double* y, double* out, double* a, double* b, const double* v,
+                           double* vout, double* va, double* vb) {
+    tmm::StepRange sr{0, h->P.nstep, nullptr, 1, nullptr, nullptr};
+    return launch_persistent(h, sr, y, out, a, b, v, vout, va, vb);
+}
+
+// Reverse sweep over steps j_hi-1 .. j_lo in one cooperative launch.
+int launch_adjoint_persistent(tmm_ctx* h, int j_lo, int j_hi, const double* ystore, const double* obs,
+                              double src_scale, const double* mu_in, double* mu_out, double* a, double* b,
+                              double* ubar_dom) {
+    const Plan& P = h->P;
+    int rc = reset_flags(h);
+    if (rc) return rc;
+    tmm::Grid g = h->grid(h->tilings.front());
+    tmm::Model md = h->model();
+    tmm::Mats mt = h->mats();
+    tmm::Persist ps = persist_args(h);
+    double dtd = tmm::kDaysPerYear / P.nstep;
+    void* args[] = {&g, &md, &mt, &ps, &dtd, &j_lo, &j_hi, &ystore, &obs, &src_scale, &mu_in, &mu_out,
+                    &a, &b, &ubar_dom};
+    TMM_TRY(hipLaunchCooperativeKernel(adjoint_kernel(P.ntr, h->pers_kmax, h->pers_tpb), dim3(h->pers_G),
+                                       dim3(h->pers_tpb), args, 0, h->stream));
     h->pers_used = true;
     return TMM_OK;
 }
@@ -424,7 +478,7 @@ int check_abort(tmm_ctx* h) {
 // launch; otherwise one launch per step.
 int run_year(tmm_ctx* h, int nb, const double* y, double* out, double* a, double* b,
              const double* v = nullptr, double* vout = nullptr, double* va = nullptr, double* vb = nullptr) {
-    if (nb == 1 && h->pers_ok && h->pers_enabled) return launch_persistent(h, y, out, a, b, v, vout, va, vb);
+    if (nb == 1 && h->pers_ok && h->pers_enabled) return launch_persistent_year(h, y, out, a, b, v, vout, va, vb);
     const double* cur = y;
     const double* vcur = v;
     for (int j = 0; j < h->P.nstep; ++j) {
@@ -465,6 +519,10 @@ int build_persistent(tmm_ctx* h, int target_rows) {
             TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, persistent_kernel(ntr, t, h->pers_kmax, tpb),
                                                                  tpb, 0));
             occ = (ntr == 1 && t == 0) ? o : std::min(occ, o);
+            if (t == 0) {
+                TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, adjoint_kernel(ntr, h->pers_kmax, tpb), tpb, 0));
+                occ = std::min(occ, o);
+            }
         }
     const int maxG = std::min(kMaxDomains, std::min(ncu * occ, P.ncol));
     if (maxG < 1) return TMM_OK;
@@ -546,6 +604,84 @@ int sqdiff(tmm_ctx* h, int nb, const double* a, const double* b, int volume, dou
     return TMM_OK;
 }
 
+
+
+// Checkpointed adjoint of one model year for one member with persistent
+// launches: a forward sweep storing y every ckpt steps and the month-end
+// misfit sums; the misfit source of the last month and Ai^T for the last
+// step; then per segment, last first, a forward replay storing every state
+// and a reverse sweep over the segment.
+int adjoint_persistent(tmm_ctx* h, const double* y0, const double* obs, double* J_host, double* dJdu_host,
+                       double* dJdy0) {
+    const Plan& P = h->P;
+    const int np = P.nparam, G = h->pers_G;
+    const size_t len = (size_t)P.n * P.ntr;
+    const int K = P.ckpt, nseg = P.nstep / K;
+    const double dtd = tmm::kDaysPerYear / P.nstep;
+    double* ckpt = h->at<double>(P.o_ckpt);
+    double* seg = h->at<double>(P.o_seg);
+    double* fin = h->at<double>(P.o_final);
+    double* mu[2] = {h->at<double>(P.o_mu[0]), h->at<double>(P.o_mu[1])};
+    double* ubar = h->at<double>(P.o_pubar);
+    double* jpart = h->at<double>(P.o_pjpart);
+    int rc;
+    if ((rc = fill(h, ubar, (size_t)G * np, 0.0)) || (rc = fill(h, jpart, (size_t)P.nmat * G, 0.0))) return rc;
+    // forward sweep: checkpoints y_{sK} at slot s, misfit partial sums
+    tmm::StepRange fw{0, P.nstep, ckpt, K, obs, jpart};
+    if ((rc = launch_persistent(h, fw, y0, fin, h->ybuf(0), h->ybuf(1), nullptr, nullptr, nullptr, nullptr)))
+        return rc;
+    hipLaunchKernelGGL(tmm::k_sum_tiles, dim3(1), dim3(64), 0, h->stream, P.nmat * G, 1, 1, jpart,
+                       1.0 / (2.0 * P.nmat * h->vtot), 0, 0, h->vec(4));
+    TMM_LAUNCHED();
+    // head: lambda_nstep = source of the last month, mu_{nstep-1} = Ai(t_{nstep-1})^T lambda_nstep
+    {
+        const Tiling& tl = h->tiling_for(P.ntr, 1, 256 * 8 * np);
+        tmm::Grid g = h->grid(tl);
+        tmm::Model md = h->model();
+        tmm::Mats mt = h->mats();
+        const size_t lds = (size_t)tl.max_rows * P.ntr * 8 + (size_t)256 * np * 8;
+        const double sc = 1.0 / (P.nmat * h->vtot);
+        const double* ob = obs + (size_t)(P.nmat - 1) * len;
+        if (P.ntr == 2)
+            hipLaunchKernelGGL((tmm::k_adjoint<2, kMaxTileRows, kMaxTileRows>), dim3(tl.ntile), dim3(256), lds,
+                               h->stream, g, md, mt, P.ntr, 1, P.nstep, dtd, 0, 1, nullptr, fin, ob, sc, mu[0],
+                               nullptr);
+        else
+            hipLaunchKernelGGL((tmm::k_adjoint<1, kMaxTileRows, kMaxTileRows>), dim3(tl.ntile), dim3(256), lds,
+                               h->stream, g, md, mt, P.ntr, 1, P.nstep, dtd, 0, 1, nullptr, fin, ob, sc, mu[0],
+                               nullptr);
+        TMM_LAUNCHED();
+    }
+    int im = 0;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int lo = sg * K, hi = lo + K;
+        // replay: y_lo .. y_{hi-1} into the segment store
+        tmm::StepRange rp{lo, hi, seg, 1, nullptr, nullptr};
+        if ((rc = launch_persistent(h, rp, ckpt + (size_t)sg * len, h->ybuf(2), h->ybuf(0), h->ybuf(1), nullptr,
+                                    nullptr, nullptr, nullptr)))
+            return rc;
+        double* out = sg == 0 ? (dJdy0 ? dJdy0 : mu[1 - im]) : mu[1 - im];
+        if ((rc = launch_adjoint_persistent(h, lo, hi, seg, obs, 1.0 / (P.nmat * h->vtot), mu[im], out,
+                                            h->vbuf(0), h->vbuf(1), ubar)))
+            return rc;
+        im = 1 - im;
+    }
+    hipLaunchKernelGGL(tmm::k_sum_tiles, dim3(1), dim3(64), 0, h->stream, G, np, np, ubar, 1.0, 0, 0, h->vec(5));
+    TMM_LAUNCHED();
+    double J = 0.0;
+    std::vector<double> Gr(np);
+    TMM_TRY(hipMemcpyAsync(&J, h->vec(4), 8, hipMemcpyDeviceToHost, h->stream));
+    TMM_TRY(hipMemcpyAsync(Gr.data(), h->vec(5), (size_t)np * 8, hipMemcpyDeviceToHost, h->stream));
+    TMM_TRY(hipStreamSynchronize(h->stream));
+    if ((rc = check_abort(h))) return rc;
+    if (!std::isfinite(J)) return TMM_ENONFINITE;
+    J_host[0] = J;
+    for (int q = 0; q < np; ++q) {
+        if (!std::isfinite(Gr[q])) return TMM_ENONFINITE;
+        dJdu_host[q] = Gr[q];
+    }
+    return TMM_OK;
+}
 
 }  // namespace
 
@@ -952,6 +1088,8 @@ int tmm_year_adjoint(tmm_handle h, const double* y0, const double* obs, int ckpt
     const size_t n = P.n, len = n * W;
     const int K = P.ckpt, spm = P.nstep / P.nmat, nseg = P.nstep / K;
     const double dtd = tmm::kDaysPerYear / P.nstep;
+    if (nb == 1 && h->pers_ok && h->pers_enabled && P.etw <= tmm::kEllMax)
+        return adjoint_persistent(h, y0, obs, J_host, dJdu_host, dJdy0);
     const Tiling& tl = h->tiling_for(W, 1, 256 * 8 * np);
     tmm::Grid g = h->grid(tl);
     tmm::Model md = h->model();

@@ -53,6 +53,17 @@ struct Persist {
     long long spin_limit;
 };
 
+// Steps j0 .. j1-1 of the year for one launch, with optional state storage
+// (y_j of own rows at slot (j - j0)/store_every when (j - j0) % store_every == 0)
+// and month-end misfit partial sums against obs.
+struct StepRange {
+    int j0, j1;
+    double* store;          // nullable, [slots][n*NTR]
+    int store_every;
+    const double* obs;      // nullable, [nmat][n*NTR]
+    double* jpart;          // [nmat][G] per-domain sums of V_i (y - obs)^2
+};
+
 template <int KMAX>
 struct RowMats {
     int col[kEllMax];       // Ae column indices of the row
@@ -76,11 +87,12 @@ __device__ __forceinline__ void load_month(const Mats& mt, const Grid& g, int m,
 // threads per workgroup = maximum rows per domain.
 template <int NTR, bool TANGENT, int KMAX, int TPB>
 __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
-    Grid g, Model md, Mats mt, Persist ps, double dtd, const double* __restrict__ y_in,
+    Grid g, Model md, Mats mt, Persist ps, StepRange sr, double dtd, const double* __restrict__ y_in,
     double* __restrict__ y_out, double* __restrict__ buf0, double* __restrict__ buf1,
     const double* __restrict__ v_in, double* __restrict__ v_out, double* __restrict__ vbuf0,
     double* __restrict__ vbuf1) {
     constexpr int TV = TANGENT ? NTR : 1;
+    __shared__ double s_red[TPB];
     __shared__ short s_rowcol[TPB];
     __shared__ short s_rowk[TPB];
     __shared__ short s_colr0[TPB];
@@ -154,10 +166,20 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     int m0 = -1, m1 = -1;
     __syncthreads();
 
-    for (int j = 0; j < g.nstep; ++j) {
+    const int nsteps = sr.j1 - sr.j0;
+    const size_t state_len = (size_t)g.n * NTR;
+    const int spm = g.nstep / g.nmat;
+    const double vol = g.area[c] * g.dz[k];
+    for (int jj = 0; jj < nsteps; ++jj) {
+        const int j = sr.j0 + jj;
         int k0, k1;
         double w;
         step_phase(j, g.nstep, g.nmat, k0, k1, w);
+        if (sr.store && own && jj % sr.store_every == 0) {
+#pragma unroll
+            for (int t = 0; t < NTR; ++t)
+                sr.store[(size_t)(jj / sr.store_every) * state_len + (size_t)r * NTR + t] = yr[t];
+        }
         if (k0 != m0 || k1 != m1) {
             if (own) {
                 if (k0 == m1) {
@@ -174,7 +196,7 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             m1 = k1;
         }
         const double om = 1.0 - w;
-        const double Q = g.ins[(size_t)j * g.nlat + latrow];
+        const double Q = g.ins[(size_t)(j % g.nstep) * g.nlat + latrow];
 
         // sources from the domain's own rows (no wait needed)
         double q[NTR], qd[TV];
@@ -210,7 +232,7 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
         for (int qi = tid; qi < ndep; qi += blockDim.x) {
             const int e = ps.dep_idx[dep0 + qi];
             long long it = 0;
-            while (__hip_atomic_load(&ps.flags[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < j) {
+            while (__hip_atomic_load(&ps.flags[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < jj) {
                 ++it;
                 if (it > ps.spin_limit ||
                     ((it & 63) == 0 && __hip_atomic_load(ps.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
@@ -226,8 +248,8 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
         if (s_fail) return;
 
         // z = Ae(t_j) y_j + dt_d q
-        const double* src = j == 0 ? y_in : ((j & 1) ? buf1 : buf0);
-        const double* vsrc = j == 0 ? v_in : ((j & 1) ? vbuf1 : vbuf0);
+        const double* src = jj == 0 ? y_in : ((jj & 1) ? buf1 : buf0);
+        const double* vsrc = jj == 0 ? v_in : ((jj & 1) ? vbuf1 : vbuf0);
         if (own) {
             double acc[NTR], accd[TV];
 #pragma unroll
@@ -259,8 +281,8 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
         __syncthreads();
 
         // y_{j+1} = Ai(t_j) z, within the water column
-        double* dst = j == g.nstep - 1 ? y_out : ((j & 1) ? buf0 : buf1);
-        double* vdst = j == g.nstep - 1 ? v_out : ((j & 1) ? vbuf0 : vbuf1);
+        double* dst = jj == nsteps - 1 ? y_out : ((jj & 1) ? buf0 : buf1);
+        double* vdst = jj == nsteps - 1 ? v_out : ((jj & 1) ? vbuf0 : vbuf1);
         if (own) {
             double acc[NTR], accd[TV];
 #pragma unroll
@@ -294,7 +316,305 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             }
         }
         __syncthreads();
-        if (tid == 0) __hip_atomic_store(&ps.flags[d], j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) __hip_atomic_store(&ps.flags[d], jj + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // month-end misfit partial sums (after publishing, off the neighbours' critical path)
+        if (sr.obs && (j + 1) % spm == 0) {
+            const int mo = (j + 1) / spm - 1;
+            double cval = 0.0;
+            if (own) {
+#pragma unroll
+                for (int t = 0; t < NTR; ++t) {
+                    const double dd = yr[t] - sr.obs[(size_t)mo * state_len + (size_t)r * NTR + t];
+                    cval += vol * dd * dd;
+                }
+            }
+            s_red[tid] = cval;
+            __syncthreads();
+            for (int hh = TPB / 2; hh > 0; hh >>= 1) {
+                if (tid < hh) s_red[tid] += s_red[tid + hh];
+                __syncthreads();
+            }
+            if (tid == 0) sr.jpart[(size_t)mo * gridDim.x + d] = s_red[0];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent reverse sweep over steps j_hi-1 down to j_lo (one checkpoint
+// segment), for one member.  With mu_j the cotangent of z_j (the argument
+// of Ai in step j):
+//   lambda_j = Ae(t_j)^T mu_j + dt_d (dq/dy)(y_j)^T mu_j + s_j
+//   mu_{j-1} = Ai(t_{j-1})^T lambda_j        (lambda_0 itself when j = 0)
+//   ubar    += dt_d (dq/du)(y_j)^T mu_j
+// s_j is the misfit source at month ends (j > 0).  Each thread keeps its
+// row of Ae^T (months of step j) and column of its Ai block (months of step
+// j-1) in registers; mu is exchanged between domains like the forward state.
+// y_j of the segment comes from ystore (slot j - j_lo).  Parameter-gradient
+// sums are reduced per domain at the end and added to ubar_dom[domain][p].
+// ---------------------------------------------------------------------------
+template <int NTR, int KMAX, int TPB>
+__global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
+    Grid g, Model md, Mats mt, Persist ps, double dtd, int j_lo, int j_hi,
+    const double* __restrict__ ystore, const double* __restrict__ obs, double src_scale,
+    const double* __restrict__ mu_in, double* __restrict__ mu_out, double* __restrict__ buf0,
+    double* __restrict__ buf1, double* __restrict__ ubar_dom) {
+    constexpr int NP = NTR == 2 ? 7 : 5;
+    __shared__ short s_rowcol[TPB];
+    __shared__ short s_rowk[TPB];
+    __shared__ short s_colr0[TPB];
+    __shared__ short s_colnc[TPB];
+    __shared__ double s_y[TPB * NTR];
+    __shared__ double s_mu[TPB * NTR];
+    __shared__ double s_lam[TPB * NTR];
+    __shared__ double s_red[TPB];
+    __shared__ int s_fail;
+
+    const int tid = threadIdx.x;
+    const int d = ps.block_dom[blockIdx.x];
+    const int c0 = ps.dom_col[d], c1 = ps.dom_col[d + 1];
+    const int r0 = g.col_start[c0];
+    const int nrows = g.col_start[c1] - r0;
+    for (int lc = tid; lc < c1 - c0; lc += blockDim.x) {
+        const int s = g.col_start[c0 + lc] - r0;
+        const int nc = g.col_start[c0 + lc + 1] - g.col_start[c0 + lc];
+        s_colr0[lc] = (short)s;
+        s_colnc[lc] = (short)nc;
+        for (int k = 0; k < nc; ++k) {
+            s_rowcol[s + k] = (short)lc;
+            s_rowk[s + k] = (short)k;
+        }
+    }
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
+
+    const bool own = tid < nrows;
+    const int r = r0 + (own ? tid : 0);
+    const int lc = own ? s_rowcol[tid] : 0;
+    const int k = own ? s_rowk[tid] : 0;
+    const int nc = own ? s_colnc[lc] : 1;
+    const int lr0 = own ? s_colr0[lc] : 0;
+    const int c = c0 + lc;
+    const size_t blk = (size_t)g.blk_off[c];
+    const int latrow = g.col_lat[c];
+    const size_t state_len = (size_t)g.n * NTR;
+    const int spm = g.nstep / g.nmat;
+    const double vol = g.area[c] * g.dz[k];
+
+    const int m = md.member[0];
+    const BgcParams p = load_params(md.u, md.model, md.nparam, m);
+    const size_t tab = ((size_t)m * (g.nlayer + 1) + nc) * g.nlayer;
+    const double rho = md.rho[tab + k];
+    const double drho = md.drho[tab + k];
+    const int ne = nc < g.neu ? nc : g.neu;
+    double light[kNeuMax], hz[kNeuMax];
+#pragma unroll
+    for (int e = 0; e < kNeuMax; ++e) {
+        light[e] = e < ne ? md.light[(size_t)m * g.nlayer + e] : 0.0;
+        hz[e] = e < ne ? g.dz[e] : 0.0;
+    }
+    double zc = 0.0;   // centre depth of the row's layer
+    for (int i = 0; i <= k; ++i) zc += g.dz[i];
+    zc -= 0.5 * g.dz[k];
+
+    // row r of Ae^T and column k of the row's Ai block
+    int col[kEllMax], loc[kEllMax];
+    double e0[kEllMax], e1[kEllMax], a0[KMAX], a1[KMAX];
+#pragma unroll
+    for (int s = 0; s < kEllMax; ++s) {
+        col[s] = s < mt.etw ? mt.aet_col[(size_t)s * g.npad + r] : r;
+        const int lr = col[s] - r0;
+        loc[s] = (lr >= 0 && lr < nrows) ? lr : -1;
+    }
+    auto load_ae = [&](int mo, double* e) {
+#pragma unroll
+        for (int s = 0; s < kEllMax; ++s)
+            e[s] = s < mt.etw ? mt.aet[(size_t)mo * mt.aet_month + (size_t)s * g.npad + r] : 0.0;
+    };
+    auto load_ai = [&](int mo, double* a) {
+#pragma unroll
+        for (int s = 0; s < KMAX; ++s)
+            a[s] = s < nc ? mt.ai_cm[(size_t)mo * mt.ai_month + blk + (size_t)k * nc + s] : 0.0;
+    };
+
+    double mr[NTR];
+#pragma unroll
+    for (int t = 0; t < NTR; ++t) {
+        mr[t] = own ? mu_in[(size_t)r * NTR + t] : 0.0;
+        s_mu[tid * NTR + t] = mr[t];
+    }
+    double ub[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) ub[q] = 0.0;
+    const int dep0 = ps.dep_ptr[d], ndep = ps.dep_ptr[d + 1] - dep0;
+    int me0 = -1, me1 = -1, ma0 = -1, ma1 = -1;
+    const int nsteps = j_hi - j_lo;
+
+    for (int jj = 0; jj < nsteps; ++jj) {
+        const int j = j_hi - 1 - jj;
+        int k0, k1, q0, q1;
+        double w, wq;
+        step_phase(j, g.nstep, g.nmat, k0, k1, w);
+        step_phase(j - 1, g.nstep, g.nmat, q0, q1, wq);
+        if (own && (k0 != me0 || k1 != me1)) {
+            if (k1 == me0) {          // stepping backwards: the old k0 becomes the new k1
+#pragma unroll
+                for (int s = 0; s < kEllMax; ++s) e1[s] = e0[s];
+            } else {
+                load_ae(k1, e1);
+            }
+            load_ae(k0, e0);
+        }
+        me0 = k0;
+        me1 = k1;
+        if (own && j > 0 && (q0 != ma0 || q1 != ma1)) {
+            if (q1 == ma0) {
+#pragma unroll
+                for (int s = 0; s < KMAX; ++s) a1[s] = a0[s];
+            } else {
+                load_ai(q1, a1);
+            }
+            load_ai(q0, a0);
+        }
+        if (j > 0) {
+            ma0 = q0;
+            ma1 = q1;
+        }
+        const double om = 1.0 - w;
+        const double Q = g.ins[(size_t)j * g.nlat + latrow];
+
+        // y_j of the own rows
+        double yj[NTR];
+#pragma unroll
+        for (int t = 0; t < NTR; ++t) {
+            yj[t] = own ? ystore[(size_t)(j - j_lo) * state_len + (size_t)r * NTR + t] : 0.0;
+            s_y[tid * NTR + t] = yj[t];
+        }
+        __syncthreads();
+
+        // (dq/dy)^T mu_j and (dq/du)^T mu_j from the own water column
+        double ybar[NTR];
+        {
+            double Phi = 0.0;
+#pragma unroll
+            for (int e = 0; e < kNeuMax; ++e)
+                if (e < ne) Phi += hz[e] * production(p, s_y[(lr0 + e) * NTR], Q, light[e]).f;
+            const double mu1 = mr[0];
+            const double mu2 = NTR > 1 ? mr[NTR - 1] : 0.0;
+            const double dop = NTR > 1 ? yj[NTR - 1] : 0.0;
+            ybar[0] = 0.0;
+            if (k < g.neu) {
+                double Phibar = 0.0;
+                for (int kk = 0; kk < nc; ++kk) Phibar += (1.0 - p.sig) * md.rho[tab + kk] * s_mu[(lr0 + kk) * NTR];
+                double lk = 0.0;
+#pragma unroll
+                for (int e = 0; e < kNeuMax; ++e)
+                    if (e == k) lk = light[e];
+                const Production pr = production(p, yj[0], Q, lk);
+                const double fbar = -mu1 + p.sig * mu2 + g.dz[k] * Phibar;
+                ybar[0] = fbar * pr.dfdN;
+                const double Np = yj[0] > 0.0 ? yj[0] : 0.0;
+                const double IKI2 = (pr.I + p.ki) * (pr.I + p.ki);
+                ub[0] += fbar * pr.limN * pr.limI;
+                ub[1] += fbar * p.alpha * pr.limN * p.ki / IKI2 * (-zc * pr.I);
+                ub[2] += fbar * (-p.alpha * Np / ((Np + p.k1) * (Np + p.k1)) * pr.limI);
+                ub[3] += fbar * (-p.alpha * pr.limN * pr.I / IKI2);
+                if (NTR > 1) ub[5] += pr.f * mu2;
+            }
+            if (NTR > 1) {
+                ybar[NTR - 1] = p.lam * (mu1 - mu2);
+                ub[4] += dop * (mu1 - mu2);
+                ub[5] += -Phi * rho * mu1;
+            }
+            ub[NP - 1] += (1.0 - p.sig) * Phi * drho * mu1;
+        }
+
+        // wait until every neighbouring domain has published mu_j
+        for (int qi = tid; qi < ndep; qi += blockDim.x) {
+            const int e = ps.dep_idx[dep0 + qi];
+            long long it = 0;
+            while (__hip_atomic_load(&ps.flags[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < jj) {
+                ++it;
+                if (it > ps.spin_limit ||
+                    ((it & 63) == 0 && __hip_atomic_load(ps.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                    __hip_atomic_store(ps.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s_fail = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (tid < ndep) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+        if (s_fail) return;
+
+        // lambda_j = Ae^T mu_j + dt_d ybar + s_j
+        const double* src = jj == 0 ? mu_in : ((jj & 1) ? buf1 : buf0);
+        const int mo = (j > 0 && j % spm == 0 && obs) ? j / spm - 1 : -1;
+        if (own) {
+            double lam[NTR];
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) lam[t] = 0.0;
+#pragma unroll
+            for (int s = 0; s < kEllMax; ++s) {
+                if (s < mt.etw) {
+                    const double a = om * e0[s] + w * e1[s];
+                    const int lr = loc[s];
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t)
+                        lam[t] += a * (lr >= 0 ? s_mu[lr * NTR + t] : src[(size_t)col[s] * NTR + t]);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) {
+                lam[t] += dtd * ybar[t];
+                if (mo >= 0) lam[t] += vol * (yj[t] - obs[(size_t)mo * state_len + (size_t)r * NTR + t]) * src_scale;
+                s_lam[tid * NTR + t] = lam[t];
+            }
+        }
+        __syncthreads();
+
+        // mu_{j-1} = Ai(t_{j-1})^T lambda_j within the column, or lambda_0
+        double* dst = jj == nsteps - 1 ? mu_out : ((jj & 1) ? buf0 : buf1);
+        if (own) {
+            double out[NTR];
+            if (j > 0) {
+                const double omq = 1.0 - wq;
+#pragma unroll
+                for (int t = 0; t < NTR; ++t) out[t] = 0.0;
+#pragma unroll
+                for (int s = 0; s < KMAX; ++s) {
+                    if (s < nc) {
+                        const double a = omq * a0[s] + wq * a1[s];
+#pragma unroll
+                        for (int t = 0; t < NTR; ++t) out[t] += a * s_lam[(lr0 + s) * NTR + t];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < NTR; ++t) out[t] = s_lam[tid * NTR + t];
+            }
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) {
+                mr[t] = out[t];
+                s_mu[tid * NTR + t] = out[t];
+                __hip_atomic_store(&dst[(size_t)r * NTR + t], out[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(&ps.flags[d], jj + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+
+    // per-domain parameter-gradient sums (fixed-order tree)
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        s_red[tid] = own ? ub[q] : 0.0;
+        __syncthreads();
+        for (int hh = TPB / 2; hh > 0; hh >>= 1) {
+            if (tid < hh) s_red[tid] += s_red[tid + hh];
+            __syncthreads();
+        }
+        if (tid == 0) ubar_dom[(size_t)d * NP + q] += dtd * s_red[0];
+        __syncthreads();
     }
 }
 

@@ -120,8 +120,9 @@ def test_jvp_tangent_and_fd(inputs):
     assert _rel(jfd.cpu().numpy(), ejv) <= 1e-5
 
 
+@pytest.mark.parametrize("persistent", [1, 0])
 @pytest.mark.parametrize("name,ckpt", [("tiny_n", 240), ("tiny_ndop", 240), ("small", 480), ("small", 1)])
-def test_adjoint_parity(inputs, name, ckpt):
+def test_adjoint_parity(inputs, name, ckpt, persistent):
     inp = inputs[name]
     o = oracle.Oracle(inp)
     ustar = synth.hidden_params(inp.model, seed=21)
@@ -131,6 +132,7 @@ def test_adjoint_parity(inputs, name, ckpt):
     u = synth.nominal(inp.model)
     eJ, eG, eY = o.year_adjoint(u, y0, obs)
     t = _make(inp, adjoint=1, ckpt=ckpt)
+    t.set_option(_lib().TMM_OPT_PERSISTENT, persistent)
     t.set_params(u)
     import torch
     J, G, dy0 = t.year_adjoint(t.state(y0), torch.as_tensor(obs).cuda())

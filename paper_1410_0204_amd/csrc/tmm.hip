@@ -253,6 +253,7 @@ struct tmm_ctx {
     int pers_G = 0;
     int pers_kmax = 16;
     int pers_tpb = 256;            // threads (= maximum rows) per domain
+    int wide_min_members = 16;     // batches of at least this many members use k_step_members
     int num_cu = 0;
     bool pers_used = false;        // a persistent launch happened since the last abort check
     std::vector<int> ae_rowptr, ae_colidx;   // explicit-matrix pattern (domain dependencies)
@@ -342,6 +343,30 @@ int copy(tmm_ctx* h, double* dst, const double* src, size_t len) {
 int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const double* v, double* vo) {
     const int W = nb * h->P.ntr;
     const bool tangent = v != nullptr;
+    if (!tangent && nb >= h->wide_min_members && h->P.nlayer <= 32 && h->P.ew <= tmm::kMembersEll) {
+        // member-parallel kernel: one wavefront per column and 64 members
+        const int kmax = h->P.nlayer <= 16 ? 16 : 32;
+        const double dtd = tmm::kDaysPerYear / h->P.nstep;
+        tmm::Grid g = h->grid(h->tilings.front());
+        tmm::Model md = h->model();
+        tmm::Mats mt = h->mats();
+        dim3 grid((h->P.ncol + tmm::kMembersWaves - 1) / tmm::kMembersWaves, (nb + 63) / 64),
+            blk(64 * tmm::kMembersWaves);
+        if (h->P.ntr == 2 && kmax == 16)
+            hipLaunchKernelGGL((tmm::k_step_members<2, 16>), grid, blk, 0, h->stream, g, md, mt, h->P.ncol, nb, j,
+                               dtd, y, yo);
+        else if (h->P.ntr == 2)
+            hipLaunchKernelGGL((tmm::k_step_members<2, 32>), grid, blk, 0, h->stream, g, md, mt, h->P.ncol, nb, j,
+                               dtd, y, yo);
+        else if (kmax == 16)
+            hipLaunchKernelGGL((tmm::k_step_members<1, 16>), grid, blk, 0, h->stream, g, md, mt, h->P.ncol, nb, j,
+                               dtd, y, yo);
+        else
+            hipLaunchKernelGGL((tmm::k_step_members<1, 32>), grid, blk, 0, h->stream, g, md, mt, h->P.ncol, nb, j,
+                               dtd, y, yo);
+        TMM_LAUNCHED();
+        return TMM_OK;
+    }
     const Tiling& t = h->tiling_for(W, tangent ? 2 : 1);
     const int CW = W == 1 ? 1 : 2;
     const int tpr = (W + CW - 1) / CW;
@@ -1055,6 +1080,7 @@ int tmm_set_option(tmm_handle h, int option, int value) {
     if (!h) return TMM_EINVAL;
     switch (option) {
         case TMM_OPT_PERSISTENT: h->pers_enabled = value != 0; return TMM_OK;
+        case TMM_OPT_MEMBER_KERNEL_MIN: h->wide_min_members = value < 1 ? 1 << 30 : value; return TMM_OK;
         case TMM_OPT_DOMAIN_ROWS: {
             if (value < 0) return TMM_EINVAL;
             if (hipStreamSynchronize(h->stream) != hipSuccess) return TMM_EDEVICE;

@@ -414,6 +414,130 @@ __global__ void k_step(Grid g, Model md, Mats mt, int W, int tpr, int j, double 
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Forward step for ensembles: one wavefront per water column and group of up
+// to 64 members, lane = member (both tracers).  Each wavefront first stages
+// the column's interpolated matrices in its own LDS slice with coalesced loads
+// (the Ai block, and the Ae rows: column indices and values), so that all
+// gathers of the state are independent and wave-uniform reads come from LDS.
+// A member's parameters, light factors and export Phi are evaluated once per
+// column; z of the column stays in registers (KMAX >= column depth).
+// ---------------------------------------------------------------------------
+constexpr int kMembersWaves = 4;      // wavefronts (columns) per workgroup
+constexpr int kMembersEll = 8;        // Ae nonzeros per row supported by k_step_members
+
+template <int NTR, int KMAX>
+__global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt, int ncol, int nb, int j,
+                                                      double dtd, const double* __restrict__ y,
+                                                      double* __restrict__ yo) {
+    constexpr int NEU = 4;
+    __shared__ double s_ai[kMembersWaves][KMAX * KMAX];
+    __shared__ double s_ae[kMembersWaves][KMAX * kMembersEll];
+    __shared__ int s_col[kMembersWaves][KMAX * kMembersEll];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int craw = blockIdx.x * kMembersWaves + wave;
+    const bool valid = craw < ncol;              // waves past the last column idle but reach the barrier
+    const int c = valid ? craw : ncol - 1;
+    const int b = blockIdx.y * 64 + lane;
+    const bool act = valid && b < nb;
+    const int bb = b < nb ? b : 0;
+    const int W = nb * NTR;
+    const int rs = g.col_start[c];
+    const int nc = g.col_start[c + 1] - rs;
+    int k0, k1;
+    double w;
+    step_phase(j, g.nstep, g.nmat, k0, k1, w);
+    const double om = 1.0 - w;
+
+    // stage the interpolated column matrices (this wavefront's slice only)
+    {
+        const double* ai0 = mt.ai_rm + (size_t)k0 * mt.ai_month + g.blk_off[c];
+        const double* ai1 = mt.ai_rm + (size_t)k1 * mt.ai_month + g.blk_off[c];
+        for (int i = lane; i < nc * nc; i += 64) s_ai[wave][i] = om * ai0[i] + w * ai1[i];
+        const double* ae0 = mt.ae + (size_t)k0 * mt.ae_month;
+        const double* ae1 = mt.ae + (size_t)k1 * mt.ae_month;
+        for (int i = lane; i < nc * mt.ew; i += 64) {
+            const int k = i / mt.ew, sl = i % mt.ew;
+            const size_t e = (size_t)sl * g.npad + rs + k;
+            s_col[wave][k * kMembersEll + sl] = mt.ae_col[e];
+            s_ae[wave][k * kMembersEll + sl] = om * ae0[e] + w * ae1[e];
+        }
+    }
+    __syncthreads();
+
+    const double Q = g.ins[(size_t)(j % g.nstep) * g.nlat + g.col_lat[c]];
+    const int m = md.member[bb];
+    const BgcParams p = load_params(md.u, md.model, md.nparam, m);
+    const size_t tab = ((size_t)m * (g.nlayer + 1) + nc) * g.nlayer;
+
+    // production in the euphotic layers and the export Phi
+    const int ne = nc < g.neu ? nc : g.neu;
+    double f[NEU];
+    double Phi = 0.0;
+#pragma unroll
+    for (int e = 0; e < NEU; ++e) {
+        f[e] = 0.0;
+        if (e < ne) {
+            const double N = act ? y[(size_t)(rs + e) * W + (size_t)bb * NTR] : 0.0;
+            f[e] = production(p, N, Q, md.light[(size_t)m * g.nlayer + e]).f;
+            Phi += g.dz[e] * f[e];
+        }
+    }
+
+    // z = Ae(t_j) y + dt_d q for every row of the column, in registers
+    double z[KMAX][NTR];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+#pragma unroll
+        for (int t = 0; t < NTR; ++t) z[k][t] = 0.0;
+        if (k < nc) {
+            const int r = rs + k;
+            double acc[NTR];
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) acc[t] = 0.0;
+#pragma unroll
+            for (int sl = 0; sl < kMembersEll; ++sl) {
+                if (sl < mt.ew) {
+                    const int col = s_col[wave][k * kMembersEll + sl];
+                    const double a = s_ae[wave][k * kMembersEll + sl];
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t)
+                        acc[t] += a * (act ? y[(size_t)col * W + (size_t)bb * NTR + t] : 0.0);
+                }
+            }
+            double fk = 0.0;
+#pragma unroll
+            for (int e = 0; e < NEU; ++e)
+                if (e == k) fk = f[e];
+            const double rho = md.rho[tab + k];
+            const double dop = (NTR > 1 && act) ? y[(size_t)r * W + (size_t)bb * NTR + NTR - 1] : 0.0;
+            const double q1 = -fk + p.lam * dop + (1.0 - p.sig) * Phi * rho;
+            z[k][0] = acc[0] + dtd * q1;
+            if (NTR > 1) z[k][NTR - 1] = acc[NTR - 1] + dtd * (p.sig * fk - p.lam * dop);
+        }
+    }
+
+    // y_out = Ai(t_j) z within the column
+    for (int k = 0; k < nc; ++k) {
+        double acc[NTR];
+#pragma unroll
+        for (int t = 0; t < NTR; ++t) acc[t] = 0.0;
+#pragma unroll
+        for (int s = 0; s < KMAX; ++s) {
+            if (s < nc) {
+                const double a = s_ai[wave][k * nc + s];
+#pragma unroll
+                for (int t = 0; t < NTR; ++t) acc[t] += a * z[s][t];
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) yo[(size_t)(rs + k) * W + (size_t)bb * NTR + t] = acc[t];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint step (reverse mode of k_step).  With mu_j the cotangent of z_j:
 //   lambda_j = Ae(t_j)^T mu_j + dt_d (dq/dy)(y_j)^T mu_j + s_j

@@ -79,6 +79,30 @@ def test_batched_members_match_unbatched(inputs):
         assert rm[0, 0] == pytest.approx(rb[0, m], rel=1e-14)
 
 
+@pytest.mark.parametrize("nb,nsteps", [(8, 2880), (70, 24)])
+def test_member_parallel_kernel(inputs, nb, nsteps):
+    """Ensembles through the member-parallel step kernel (two member groups, ragged) vs the oracle."""
+    tmm = _lib()
+    inp = inputs["small"]
+    U = synth.latin_hypercube(synth.MODEL_NDOP, nb, seed=nb)
+    t = _make(inp, nbatch_max=nb)
+    t.set_option(tmm.TMM_OPT_MEMBER_KERNEL_MIN, 1)
+    o = oracle.Oracle(inp)
+    t.set_params(U)
+    rng = np.random.default_rng(nb)
+    y0 = inp.initial_state(nb) * rng.uniform(0.7, 1.3, size=(inp.n, 2 * nb))
+    if nsteps == 2880:
+        got, _ = t.year(t.state(y0))
+        exp, _ = o.year(U, y0)
+        assert _rel(got.cpu().numpy(), exp) <= 1e-12
+    else:
+        yd, ye = t.state(y0), y0
+        for j in range(nsteps):
+            yd = t.step(j * 119 % 2880, yd)
+            ye = o.step(U, j * 119 % 2880, ye)
+            assert _rel(yd.cpu().numpy(), ye) <= 1e-13, j
+
+
 def test_uneven_spinup_lengths(inputs):
     """Members stop after their own number of years; finished states are kept."""
     inp = inputs["tiny_ndop"]

@@ -1,0 +1,57 @@
+"""GPU parity at the benchmark's full sizes, in the launch configurations bench.py times.
+
+* global 128x64x15 (52749 points): the checkpointed adjoint of one model year
+  (persistent kernels, checkpoints every 240 steps) against the oracle's
+  full-trajectory reverse mode;
+* ensemble 256x128x23 (500000 points, 64 members, W = 128): steps of the
+  member-parallel kernel against the oracle's step, all outputs compared.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def test_global_adjoint_against_oracle():
+    import torch
+    from paper_1410_0204_amd import tmm
+    inp = synth.global_2p8()
+    o = oracle.Oracle(inp)
+    y0 = inp.initial_state()
+    print("[gpu] oracle snapshots and reverse mode on the global grid (~30 s)", flush=True)
+    snaps = o.snapshots(synth.hidden_params(inp.model, seed=21), y0)
+    obs = snaps * (1 + 0.05 * synth.obs_noise(snaps.shape, seed=22))
+    u = synth.nominal(inp.model)
+    eJ, eG, eY = o.year_adjoint(u, y0, obs)
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=1, adjoint_nbatch_max=1, ckpt_every=240)
+    assert t.query(tmm.TMM_Q_PERSISTENT) == 1
+    t.set_params(u)
+    J, G, dy0 = t.year_adjoint(t.state(y0), torch.as_tensor(obs).cuda())
+    assert J[0] == pytest.approx(eJ[0], rel=1e-12)
+    assert _rel(G, eG) <= 1e-9
+    assert _rel(dy0.cpu().numpy(), eY) <= 1e-9
+
+
+def test_ensemble_steps_against_oracle():
+    from paper_1410_0204_amd import tmm
+    inp = synth.ensemble_1p4()
+    nm = 64
+    U = synth.latin_hypercube(synth.MODEL_NDOP, nm, seed=17)
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=nm)
+    t.set_params(U)
+    o = oracle.Oracle(inp)
+    rng = np.random.default_rng(5)
+    y = inp.initial_state(nm) * rng.uniform(0.8, 1.2, size=(inp.n, 2 * nm))
+    for j in (0, 1439):
+        print(f"[gpu] ensemble step {j} on the oracle (~10 s)", flush=True)
+        got = t.step(j, t.state(y)).cpu().numpy()
+        exp = o.step(U, j, y)
+        assert _rel(got, exp) <= 1e-14, j

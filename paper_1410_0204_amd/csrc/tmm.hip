@@ -345,25 +345,32 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
     const bool tangent = v != nullptr;
     if (!tangent && nb >= h->wide_min_members && h->P.nlayer <= 32 && h->P.ew <= tmm::kMembersEll) {
         // member-parallel kernel: one wavefront per column and 64 members
-        const int kmax = h->P.nlayer <= 16 ? 16 : 32;
+        const int kmax = h->P.nlayer <= 16 ? 16 : h->P.nlayer <= 24 ? 24 : 32;
         const double dtd = tmm::kDaysPerYear / h->P.nstep;
         tmm::Grid g = h->grid(h->tilings.front());
         tmm::Model md = h->model();
         tmm::Mats mt = h->mats();
         dim3 grid((h->P.ncol + tmm::kMembersWaves - 1) / tmm::kMembersWaves, (nb + 63) / 64),
             blk(64 * tmm::kMembersWaves);
-        if (h->P.ntr == 2 && kmax == 16)
-            hipLaunchKernelGGL((tmm::k_step_members<2, 16>), grid, blk, 0, h->stream, g, md, mt, h->P.ncol, nb, j,
-                               dtd, y, yo);
-        else if (h->P.ntr == 2)
-            hipLaunchKernelGGL((tmm::k_step_members<2, 32>), grid, blk, 0, h->stream, g, md, mt, h->P.ncol, nb, j,
-                               dtd, y, yo);
-        else if (kmax == 16)
-            hipLaunchKernelGGL((tmm::k_step_members<1, 16>), grid, blk, 0, h->stream, g, md, mt, h->P.ncol, nb, j,
-                               dtd, y, yo);
-        else
-            hipLaunchKernelGGL((tmm::k_step_members<1, 32>), grid, blk, 0, h->stream, g, md, mt, h->P.ncol, nb, j,
-                               dtd, y, yo);
+#define TMM_MEMBERS(NT, KM)                                                                                  \
+    do {                                                                                                     \
+        if (h->P.ew <= 5)                                                                                    \
+            hipLaunchKernelGGL((tmm::k_step_members<NT, KM, 5>), grid, blk, 0, h->stream, g, md, mt, h->P.ncol,  \
+                               nb, j, dtd, y, yo);                                                           \
+        else                                                                                                 \
+            hipLaunchKernelGGL((tmm::k_step_members<NT, KM, tmm::kMembersEll>), grid, blk, 0, h->stream, g, md,  \
+                               mt, h->P.ncol, nb, j, dtd, y, yo);                                            \
+    } while (0)
+        if (h->P.ntr == 2) {
+            if (kmax == 16) TMM_MEMBERS(2, 16);
+            else if (kmax == 24) TMM_MEMBERS(2, 24);
+            else TMM_MEMBERS(2, 32);
+        } else {
+            if (kmax == 16) TMM_MEMBERS(1, 16);
+            else if (kmax == 24) TMM_MEMBERS(1, 24);
+            else TMM_MEMBERS(1, 32);
+        }
+#undef TMM_MEMBERS
         TMM_LAUNCHED();
         return TMM_OK;
     }

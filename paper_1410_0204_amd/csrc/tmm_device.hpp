@@ -427,21 +427,23 @@ __global__ void k_step(Grid g, Model md, Mats mt, int W, int tpr, int j, double 
 constexpr int kMembersWaves = 4;      // wavefronts (columns) per workgroup
 constexpr int kMembersEll = 8;        // Ae nonzeros per row supported by k_step_members
 
-template <int NTR, int KMAX>
+template <int NTR, int KMAX, int EL>
 __global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt, int ncol, int nb, int j,
                                                       double dtd, const double* __restrict__ y,
                                                       double* __restrict__ yo) {
     constexpr int NEU = 4;
+    // zero-padded KMAX x KMAX block and KMAX x EL explicit rows, so that every
+    // loop below runs to its compile-time bound without branches
     __shared__ double s_ai[kMembersWaves][KMAX * KMAX];
-    __shared__ double s_ae[kMembersWaves][KMAX * kMembersEll];
-    __shared__ int s_col[kMembersWaves][KMAX * kMembersEll];
+    __shared__ double s_ae[kMembersWaves][KMAX * EL];
+    __shared__ int s_col[kMembersWaves][KMAX * EL];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int craw = blockIdx.x * kMembersWaves + wave;
     const bool valid = craw < ncol;              // waves past the last column idle but reach the barrier
     const int c = valid ? craw : ncol - 1;
     const int b = blockIdx.y * 64 + lane;
     const bool act = valid && b < nb;
-    const int bb = b < nb ? b : 0;
+    const int bb = b < nb ? b : 0;               // idle lanes read member 0 (in bounds) and store nothing
     const int W = nb * NTR;
     const int rs = g.col_start[c];
     const int nc = g.col_start[c + 1] - rs;
@@ -454,14 +456,23 @@ __global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt,
     {
         const double* ai0 = mt.ai_rm + (size_t)k0 * mt.ai_month + g.blk_off[c];
         const double* ai1 = mt.ai_rm + (size_t)k1 * mt.ai_month + g.blk_off[c];
-        for (int i = lane; i < nc * nc; i += 64) s_ai[wave][i] = om * ai0[i] + w * ai1[i];
+        for (int i = lane; i < KMAX * KMAX; i += 64) {
+            const int k = i / KMAX, sl = i % KMAX;
+            const bool in = k < nc && sl < nc;
+            const int at = in ? k * nc + sl : 0;
+            const double v = om * ai0[at] + w * ai1[at];
+            s_ai[wave][i] = in ? v : 0.0;
+        }
         const double* ae0 = mt.ae + (size_t)k0 * mt.ae_month;
         const double* ae1 = mt.ae + (size_t)k1 * mt.ae_month;
-        for (int i = lane; i < nc * mt.ew; i += 64) {
-            const int k = i / mt.ew, sl = i % mt.ew;
-            const size_t e = (size_t)sl * g.npad + rs + k;
-            s_col[wave][k * kMembersEll + sl] = mt.ae_col[e];
-            s_ae[wave][k * kMembersEll + sl] = om * ae0[e] + w * ae1[e];
+        for (int i = lane; i < KMAX * EL; i += 64) {
+            const int k = i / EL, sl = i % EL;
+            const bool in = k < nc && sl < mt.ew;
+            const size_t e = in ? (size_t)sl * g.npad + rs + k : (size_t)rs;
+            const int col = mt.ae_col[e];
+            const double v = om * ae0[e] + w * ae1[e];
+            s_col[wave][i] = in ? col : rs;
+            s_ae[wave][i] = in ? v : 0.0;
         }
     }
     __syncthreads();
@@ -470,17 +481,23 @@ __global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt,
     const int m = md.member[bb];
     const BgcParams p = load_params(md.u, md.model, md.nparam, m);
     const size_t tab = ((size_t)m * (g.nlayer + 1) + nc) * g.nlayer;
+    const size_t me = (size_t)bb * NTR;
 
     // production in the euphotic layers and the export Phi
     const int ne = nc < g.neu ? nc : g.neu;
-    double f[NEU];
+    double Ne[NEU], le[NEU], f[NEU];
+#pragma unroll
+    for (int e = 0; e < NEU; ++e) {
+        const int re = rs + (e < nc ? e : nc - 1);
+        Ne[e] = y[(size_t)re * W + me];
+        le[e] = md.light[(size_t)m * g.nlayer + (e < g.nlayer ? e : 0)];
+    }
     double Phi = 0.0;
 #pragma unroll
     for (int e = 0; e < NEU; ++e) {
         f[e] = 0.0;
         if (e < ne) {
-            const double N = act ? y[(size_t)(rs + e) * W + (size_t)bb * NTR] : 0.0;
-            f[e] = production(p, N, Q, md.light[(size_t)m * g.nlayer + e]).f;
+            f[e] = production(p, Ne[e], Q, le[e]).f;
             Phi += g.dz[e] * f[e];
         }
     }
@@ -489,32 +506,33 @@ __global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt,
     double z[KMAX][NTR];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
+        const int kk = k < nc ? k : nc - 1;
+        double yv[EL][NTR];
 #pragma unroll
-        for (int t = 0; t < NTR; ++t) z[k][t] = 0.0;
-        if (k < nc) {
-            const int r = rs + k;
-            double acc[NTR];
+        for (int sl = 0; sl < EL; ++sl)
 #pragma unroll
-            for (int t = 0; t < NTR; ++t) acc[t] = 0.0;
+            for (int t = 0; t < NTR; ++t) yv[sl][t] = y[(size_t)s_col[wave][k * EL + sl] * W + me + t];
+        const double dop = NTR > 1 ? y[(size_t)(rs + kk) * W + me + NTR - 1] : 0.0;
+        const double rho = md.rho[tab + kk];
+        double acc[NTR];
 #pragma unroll
-            for (int sl = 0; sl < kMembersEll; ++sl) {
-                if (sl < mt.ew) {
-                    const int col = s_col[wave][k * kMembersEll + sl];
-                    const double a = s_ae[wave][k * kMembersEll + sl];
+        for (int t = 0; t < NTR; ++t) acc[t] = 0.0;
 #pragma unroll
-                    for (int t = 0; t < NTR; ++t)
-                        acc[t] += a * (act ? y[(size_t)col * W + (size_t)bb * NTR + t] : 0.0);
-                }
-            }
-            double fk = 0.0;
+        for (int sl = 0; sl < EL; ++sl) {
+            const double a = s_ae[wave][k * EL + sl];
 #pragma unroll
-            for (int e = 0; e < NEU; ++e)
-                if (e == k) fk = f[e];
-            const double rho = md.rho[tab + k];
-            const double dop = (NTR > 1 && act) ? y[(size_t)r * W + (size_t)bb * NTR + NTR - 1] : 0.0;
-            const double q1 = -fk + p.lam * dop + (1.0 - p.sig) * Phi * rho;
-            z[k][0] = acc[0] + dtd * q1;
-            if (NTR > 1) z[k][NTR - 1] = acc[NTR - 1] + dtd * (p.sig * fk - p.lam * dop);
+            for (int t = 0; t < NTR; ++t) acc[t] += a * yv[sl][t];
+        }
+        double fk = 0.0;
+#pragma unroll
+        for (int e = 0; e < NEU; ++e)
+            if (e == k) fk = f[e];
+        const double q1 = -fk + p.lam * dop + (1.0 - p.sig) * Phi * rho;
+        const double z0 = acc[0] + dtd * q1;
+        z[k][0] = k < nc ? z0 : 0.0;
+        if (NTR > 1) {
+            const double z1 = acc[NTR - 1] + dtd * (p.sig * fk - p.lam * dop);
+            z[k][NTR - 1] = k < nc ? z1 : 0.0;
         }
     }
 
@@ -524,16 +542,14 @@ __global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt,
 #pragma unroll
         for (int t = 0; t < NTR; ++t) acc[t] = 0.0;
 #pragma unroll
-        for (int s = 0; s < KMAX; ++s) {
-            if (s < nc) {
-                const double a = s_ai[wave][k * nc + s];
+        for (int sl = 0; sl < KMAX; ++sl) {
+            const double a = s_ai[wave][k * KMAX + sl];
 #pragma unroll
-                for (int t = 0; t < NTR; ++t) acc[t] += a * z[s][t];
-            }
+            for (int t = 0; t < NTR; ++t) acc[t] += a * z[sl][t];
         }
         if (act) {
 #pragma unroll
-            for (int t = 0; t < NTR; ++t) yo[(size_t)(rs + k) * W + (size_t)bb * NTR + t] = acc[t];
+            for (int t = 0; t < NTR; ++t) yo[(size_t)(rs + k) * W + me + t] = acc[t];
         }
     }
 }

@@ -67,7 +67,6 @@ struct StepRange {
 template <int KMAX>
 struct RowMats {
     int col[kEllMax];       // Ae column indices of the row
-    int loc[kEllMax];       // local row of that column in this domain, or -1
     double e0[kEllMax], e1[kEllMax];   // Ae row, months k0 and k1
     double a0[KMAX], a1[KMAX];         // row of the Ai block, months k0 and k1
 };
@@ -147,8 +146,6 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
 #pragma unroll
     for (int s = 0; s < kEllMax; ++s) {
         R.col[s] = s < mt.ew ? mt.ae_col[(size_t)s * g.npad + r] : r;
-        const int lr = R.col[s] - r0;
-        R.loc[s] = (lr >= 0 && lr < nrows) ? lr : -1;
     }
 
     // own state
@@ -256,20 +253,24 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             for (int t = 0; t < NTR; ++t) acc[t] = 0.0;
 #pragma unroll
             for (int t = 0; t < TV; ++t) accd[t] = 0.0;
+            // every slot is read from the exchange buffer (own rows included; padded
+            // slots point at the row itself with zero weight): no branches, so all
+            // loads of the row are in flight together
+            double yy[kEllMax][NTR], vv[kEllMax][TV];
+#pragma unroll
+            for (int s = 0; s < kEllMax; ++s)
+#pragma unroll
+                for (int t = 0; t < NTR; ++t) {
+                    yy[s][t] = src[(size_t)R.col[s] * NTR + t];
+                    if (TANGENT) vv[s][t % TV] = vsrc[(size_t)R.col[s] * NTR + t];
+                }
 #pragma unroll
             for (int s = 0; s < kEllMax; ++s) {
-                if (s < mt.ew) {
-                    const double a = om * R.e0[s] + w * R.e1[s];
-                    const int lr = R.loc[s];
+                const double a = om * R.e0[s] + w * R.e1[s];
 #pragma unroll
-                    for (int t = 0; t < NTR; ++t) {
-                        const double yy = lr >= 0 ? s_y[lr * NTR + t] : src[(size_t)R.col[s] * NTR + t];
-                        acc[t] += a * yy;
-                        if (TANGENT) {
-                            const double vv = lr >= 0 ? s_v[lr * TV + t % TV] : vsrc[(size_t)R.col[s] * NTR + t];
-                            accd[t % TV] += a * vv;
-                        }
-                    }
+                for (int t = 0; t < NTR; ++t) {
+                    acc[t] += a * yy[s][t];
+                    if (TANGENT) accd[t % TV] += a * vv[s][t % TV];
                 }
             }
 #pragma unroll
@@ -289,15 +290,16 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             for (int t = 0; t < NTR; ++t) acc[t] = 0.0;
 #pragma unroll
             for (int t = 0; t < TV; ++t) accd[t] = 0.0;
+            // coefficients beyond the column depth are zero; the clamped LDS index
+            // keeps the loop free of branches
 #pragma unroll
             for (int s = 0; s < KMAX; ++s) {
-                if (s < nc) {
-                    const double a = om * R.a0[s] + w * R.a1[s];
+                const double a = om * R.a0[s] + w * R.a1[s];
+                const int ls = lr0 + (s < nc ? s : nc - 1);
 #pragma unroll
-                    for (int t = 0; t < NTR; ++t) {
-                        acc[t] += a * s_z[(lr0 + s) * NTR + t];
-                        if (TANGENT) accd[t % TV] += a * s_zd[(lr0 + s) * TV + t % TV];
-                    }
+                for (int t = 0; t < NTR; ++t) {
+                    acc[t] += a * s_z[ls * NTR + t];
+                    if (TANGENT) accd[t % TV] += a * s_zd[ls * TV + t % TV];
                 }
             }
 #pragma unroll
@@ -417,13 +419,11 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     zc -= 0.5 * g.dz[k];
 
     // row r of Ae^T and column k of the row's Ai block
-    int col[kEllMax], loc[kEllMax];
+    int col[kEllMax];
     double e0[kEllMax], e1[kEllMax], a0[KMAX], a1[KMAX];
 #pragma unroll
     for (int s = 0; s < kEllMax; ++s) {
         col[s] = s < mt.etw ? mt.aet_col[(size_t)s * g.npad + r] : r;
-        const int lr = col[s] - r0;
-        loc[s] = (lr >= 0 && lr < nrows) ? lr : -1;
     }
     auto load_ae = [&](int mo, double* e) {
 #pragma unroll
@@ -554,15 +554,16 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
             double lam[NTR];
 #pragma unroll
             for (int t = 0; t < NTR; ++t) lam[t] = 0.0;
+            double mm[kEllMax][NTR];
+#pragma unroll
+            for (int s = 0; s < kEllMax; ++s)
+#pragma unroll
+                for (int t = 0; t < NTR; ++t) mm[s][t] = src[(size_t)col[s] * NTR + t];
 #pragma unroll
             for (int s = 0; s < kEllMax; ++s) {
-                if (s < mt.etw) {
-                    const double a = om * e0[s] + w * e1[s];
-                    const int lr = loc[s];
+                const double a = om * e0[s] + w * e1[s];
 #pragma unroll
-                    for (int t = 0; t < NTR; ++t)
-                        lam[t] += a * (lr >= 0 ? s_mu[lr * NTR + t] : src[(size_t)col[s] * NTR + t]);
-                }
+                for (int t = 0; t < NTR; ++t) lam[t] += a * mm[s][t];
             }
 #pragma unroll
             for (int t = 0; t < NTR; ++t) {
@@ -583,11 +584,10 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
                 for (int t = 0; t < NTR; ++t) out[t] = 0.0;
 #pragma unroll
                 for (int s = 0; s < KMAX; ++s) {
-                    if (s < nc) {
-                        const double a = omq * a0[s] + wq * a1[s];
+                    const double a = omq * a0[s] + wq * a1[s];
+                    const int ls = lr0 + (s < nc ? s : nc - 1);
 #pragma unroll
-                        for (int t = 0; t < NTR; ++t) out[t] += a * s_lam[(lr0 + s) * NTR + t];
-                    }
+                    for (int t = 0; t < NTR; ++t) out[t] += a * s_lam[ls * NTR + t];
                 }
             } else {
 #pragma unroll

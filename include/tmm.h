@@ -155,9 +155,11 @@ enum {
                                 cooperative launch when the grid fits; 0: one launch per step */
     TMM_OPT_DOMAIN_ROWS = 2, /* target rows per workgroup of the persistent kernel (<= 512);
                                 0 = the default (448) */
-    TMM_OPT_MEMBER_KERNEL_MIN = 3 /* forward steps of batches with at least this many members use the
+    TMM_OPT_MEMBER_KERNEL_MIN = 3, /* forward steps of batches with at least this many members use the
                                      member-parallel kernel (one wavefront per water column, lane =
                                      member); default 16; 0 = never */
+    TMM_OPT_GRAPH = 4            /* 1 (default): model years on the launch-per-step path are captured
+                                    once per (members, buffers) into a hipGraph and replayed */
 };
 
 /* Queries (tmm_query). */

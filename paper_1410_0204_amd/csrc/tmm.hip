@@ -254,6 +254,19 @@ struct tmm_ctx {
     int pers_kmax = 16;
     int pers_tpb = 256;            // threads (= maximum rows) per domain
     int wide_min_members = 16;     // batches of at least this many members use k_step_members
+    // captured model years of the launch-per-step path, keyed by their arguments
+    struct YearGraph {
+        int nb;
+        const void* ptrs[4];
+        hipGraphExec_t exec;
+        unsigned long long used;
+    };
+    std::vector<YearGraph> graphs;
+    unsigned long long graph_clock = 0;
+    bool graphs_enabled = true;
+    hipStream_t capture_stream = nullptr;
+    bool capturing = false;
+    hipStream_t launch_stream() const { return capturing ? capture_stream : stream; }
     int num_cu = 0;
     bool pers_used = false;        // a persistent launch happened since the last abort check
     std::vector<int> ae_rowptr, ae_colidx;   // explicit-matrix pattern (domain dependencies)
@@ -355,10 +368,10 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
 #define TMM_MEMBERS(NT, KM)                                                                                  \
     do {                                                                                                     \
         if (h->P.ew <= 5)                                                                                    \
-            hipLaunchKernelGGL((tmm::k_step_members<NT, KM, 5>), grid, blk, 0, h->stream, g, md, mt, h->P.ncol,  \
+            hipLaunchKernelGGL((tmm::k_step_members<NT, KM, 5>), grid, blk, 0, h->launch_stream(), g, md, mt, h->P.ncol,  \
                                nb, j, dtd, y, yo);                                                           \
         else                                                                                                 \
-            hipLaunchKernelGGL((tmm::k_step_members<NT, KM, tmm::kMembersEll>), grid, blk, 0, h->stream, g, md,  \
+            hipLaunchKernelGGL((tmm::k_step_members<NT, KM, tmm::kMembersEll>), grid, blk, 0, h->launch_stream(), g, md,  \
                                mt, h->P.ncol, nb, j, dtd, y, yo);                                            \
     } while (0)
         if (h->P.ntr == 2) {
@@ -385,16 +398,16 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
     tmm::Mats mt = h->mats();
     dim3 grid(t.ntile), blk(block);
     if (CW == 1 && !tangent)
-        hipLaunchKernelGGL((tmm::k_step<1, false, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->stream,
+        hipLaunchKernelGGL((tmm::k_step<1, false, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->launch_stream(),
                            g, md, mt, W, tpr, j, dtd, y, yo, v, vo);
     else if (CW == 1)
-        hipLaunchKernelGGL((tmm::k_step<1, true, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->stream,
+        hipLaunchKernelGGL((tmm::k_step<1, true, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->launch_stream(),
                            g, md, mt, W, tpr, j, dtd, y, yo, v, vo);
     else if (!tangent)
-        hipLaunchKernelGGL((tmm::k_step<2, false, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->stream,
+        hipLaunchKernelGGL((tmm::k_step<2, false, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->launch_stream(),
                            g, md, mt, W, tpr, j, dtd, y, yo, v, vo);
     else
-        hipLaunchKernelGGL((tmm::k_step<2, true, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->stream,
+        hipLaunchKernelGGL((tmm::k_step<2, true, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->launch_stream(),
                            g, md, mt, W, tpr, j, dtd, y, yo, v, vo);
     TMM_LAUNCHED();
     return TMM_OK;
@@ -504,6 +517,57 @@ int check_abort(tmm_ctx* h) {
     return flag ? TMM_EDEVICE : TMM_OK;
 }
 
+// One model year of the launch-per-step path replayed from a hipGraph: the
+// 2880 step launches of a given (members, buffers) combination are captured
+// once on a private stream and replayed on the handle's stream afterwards.
+// The graphs hold kernel nodes only.
+constexpr size_t kMaxYearGraphs = 8;
+
+int run_year_graph(tmm_ctx* h, int nb, const double* y, double* out, double* a, double* b) {
+    const void* key[4] = {y, out, a, b};
+    tmm_ctx::YearGraph* hit = nullptr;
+    for (auto& gr : h->graphs)
+        if (gr.nb == nb && std::equal(key, key + 4, gr.ptrs)) hit = &gr;
+    if (!hit) {
+        if (!h->capture_stream) TMM_TRY(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+        if (h->graphs.size() >= kMaxYearGraphs) {     // evict the least recently used
+            auto lru = std::min_element(h->graphs.begin(), h->graphs.end(),
+                                        [](const tmm_ctx::YearGraph& p, const tmm_ctx::YearGraph& q) {
+                                            return p.used < q.used;
+                                        });
+            TMM_TRY(hipGraphExecDestroy(lru->exec));
+            h->graphs.erase(lru);
+        }
+        TMM_TRY(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
+        h->capturing = true;
+        int rc = TMM_OK;
+        const double* cur = y;
+        for (int j = 0; j < h->P.nstep && rc == TMM_OK; ++j) {
+            double* nxt = j == h->P.nstep - 1 ? out : (j % 2 == 0 ? a : b);
+            rc = launch_step(h, j, nb, cur, nxt, nullptr, nullptr);
+            cur = nxt;
+        }
+        h->capturing = false;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(h->capture_stream, &graph);
+        if (rc != TMM_OK || e != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc != TMM_OK ? rc : TMM_EDEVICE;
+        }
+        tmm_ctx::YearGraph gr;
+        gr.nb = nb;
+        std::copy(key, key + 4, gr.ptrs);
+        e = hipGraphInstantiate(&gr.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return TMM_EDEVICE;
+        h->graphs.push_back(gr);
+        hit = &h->graphs.back();
+    }
+    hit->used = ++h->graph_clock;
+    TMM_TRY(hipGraphLaunch(hit->exec, h->stream));
+    return TMM_OK;
+}
+
 // One model year for nb slots from y to out, ping-ponging through a, b.  The
 // last step writes out directly.  Tangent when v != nullptr (vout, va, vb).
 // One member on a handle with the persistent tables runs as one persistent
@@ -511,6 +575,7 @@ int check_abort(tmm_ctx* h) {
 int run_year(tmm_ctx* h, int nb, const double* y, double* out, double* a, double* b,
              const double* v = nullptr, double* vout = nullptr, double* va = nullptr, double* vb = nullptr) {
     if (nb == 1 && h->pers_ok && h->pers_enabled) return launch_persistent_year(h, y, out, a, b, v, vout, va, vb);
+    if (!v && h->graphs_enabled) return run_year_graph(h, nb, y, out, a, b);
     const double* cur = y;
     const double* vcur = v;
     for (int j = 0; j < h->P.nstep; ++j) {
@@ -888,6 +953,9 @@ int tmm_create(const tmm_desc* d, void* dev_workspace, size_t bytes, void* hip_s
 int tmm_destroy(tmm_handle h) {
     if (!h) return TMM_OK;
     int rc = hipStreamSynchronize(h->stream) == hipSuccess ? TMM_OK : TMM_EDEVICE;
+    for (auto& gr : h->graphs)
+        if (hipGraphExecDestroy(gr.exec) != hipSuccess) rc = TMM_EDEVICE;
+    if (h->capture_stream && hipStreamDestroy(h->capture_stream) != hipSuccess) rc = TMM_EDEVICE;
     delete h;
     return rc;
 }
@@ -1083,11 +1151,24 @@ int tmm_year_jvp(tmm_handle h, int mode, const double* y, const double* v, doubl
     return check_abort(h);
 }
 
+static int drop_graphs(tmm_handle h) {
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return TMM_EDEVICE;
+    for (auto& gr : h->graphs)
+        if (hipGraphExecDestroy(gr.exec) != hipSuccess) return TMM_EDEVICE;
+    h->graphs.clear();
+    return TMM_OK;
+}
+
 int tmm_set_option(tmm_handle h, int option, int value) {
     if (!h) return TMM_EINVAL;
     switch (option) {
         case TMM_OPT_PERSISTENT: h->pers_enabled = value != 0; return TMM_OK;
-        case TMM_OPT_MEMBER_KERNEL_MIN: h->wide_min_members = value < 1 ? 1 << 30 : value; return TMM_OK;
+        case TMM_OPT_MEMBER_KERNEL_MIN:
+            h->wide_min_members = value < 1 ? 1 << 30 : value;
+            return drop_graphs(h);
+        case TMM_OPT_GRAPH:
+            h->graphs_enabled = value != 0;
+            return TMM_OK;
         case TMM_OPT_DOMAIN_ROWS: {
             if (value < 0) return TMM_EINVAL;
             if (hipStreamSynchronize(h->stream) != hipSuccess) return TMM_EDEVICE;

@@ -24,6 +24,7 @@ TMM_JVP_FD_GIVEN_PHI = 2
 TMM_OPT_PERSISTENT = 1
 TMM_OPT_DOMAIN_ROWS = 2
 TMM_OPT_MEMBER_KERNEL_MIN = 3
+TMM_OPT_GRAPH = 4
 TMM_Q_PERSISTENT = 1
 TMM_Q_DOMAINS = 2
 TMM_Q_WORKSPACE = 3

@@ -76,3 +76,22 @@ def test_ensemble_driver(small_ndop):
         exp, er = o.year(U[m], y0[:, 2 * m:2 * m + 2], int(L[m]))
         assert np.abs(out[:, 2 * m:2 * m + 2] - exp).max() <= 1e-12 * np.abs(exp).max(), m
         assert np.allclose(resid[:L[m], m], er[:, 0], rtol=1e-9)
+
+
+def test_autotuner_picks_a_validated_configuration(small_ndop, tmp_path):
+    from paper_1410_0204_amd import autotune
+    tmm = _tmm()
+    inp = small_ndop
+    for nb in (1, 20):
+        U = synth.latin_hypercube(synth.MODEL_NDOP, nb, seed=50 + nb)
+        t = tmm.TMM(inp.desc_arrays(), nbatch_max=nb)
+        res = autotune.tune(t, U, inp.initial_state(nb), years=1)
+        assert res["best"]["ok"] and len(res["candidates"]) >= 2
+        path = str(tmp_path / "tuned.json")
+        autotune.save(res, path)
+        assert autotune.load(t, nb, path)["options"] == res["best"]["options"]
+        # the tuned handle still reproduces the oracle
+        t.set_params(U)
+        got, _ = t.year(t.state(inp.initial_state(nb)))
+        exp, _ = oracle.Oracle(inp).year(U, inp.initial_state(nb))
+        assert np.abs(got.cpu().numpy() - exp).max() <= 1e-12 * np.abs(exp).max()

@@ -27,6 +27,7 @@ class _Desc(C.Structure):
         ("nmat", C.c_int), ("nstep", C.c_int), ("model", C.c_int), ("neuphotic", C.c_int),
         ("ae_nnz", C.c_int), ("ae_rowptr", _ip), ("ae_colidx", _ip), ("ae_val", _dp),
         ("ai_nnz", C.c_int), ("ai_rowptr", _ip), ("ai_colidx", _ip), ("ai_val", _dp),
+        ("nbgc", C.c_int),
     ]
 
 
@@ -47,6 +48,8 @@ def load():
             "oracle_insolation": (C.c_double, [C.c_double, C.c_double]),
             "oracle_spmm_interp": (None, [C.c_int, _ip, _ip, _dp, _dp, C.c_double, C.c_int, _dp, _dp]),
             "oracle_bgc_column": (C.c_int, [C.c_int, C.c_double, C.c_int, _dp, _dp, _dp, _dp, C.c_int]),
+            "oracle_bgc_source": (C.c_int, [C.c_int, C.c_double, C.c_int, _dp, _dp, _dp, _dp, C.c_int,
+                                            C.c_double, C.c_int]),
             "oracle_step": (C.c_int, [C.POINTER(_Desc), C.c_int, _dp, C.c_int, _dp, _dp]),
             "oracle_year": (C.c_int, [C.POINTER(_Desc), C.c_int, _dp, C.c_int, _dp, _dp, _dp]),
             "oracle_year_tangent": (C.c_int, [C.POINTER(_Desc), C.c_int, _dp, _dp, _dp, _dp, _dp]),
@@ -108,10 +111,21 @@ def bgc_column(model, insol, h, y, u, neuphotic):
     return q
 
 
+def bgc_source(model, insol, h, y, u, neuphotic, dt, nsub):
+    """Source of one ocean step for one column with nsub internal BGC steps; y is [ntracer, nlayer]."""
+    y = _f64(y)
+    inc = np.zeros_like(y)
+    rc = load().oracle_bgc_source(model, float(insol), y.shape[1], _d(_f64(h)), _d(y), _d(inc), _d(_f64(u)),
+                                  neuphotic, float(dt), int(nsub))
+    if rc:
+        raise ValueError("oracle_bgc_source failed")
+    return inc
+
+
 class Oracle:
     """Reference implementation bound to one set of inputs (a ``synth.Inputs``)."""
 
-    def __init__(self, inputs, nstep=None, model=None, neuphotic=None):
+    def __init__(self, inputs, nstep=None, model=None, neuphotic=None, nbgc=1):
         a = inputs.desc_arrays()
         self._keep = {k: v for k, v in a.items() if isinstance(v, np.ndarray)}
         self.n = a["n"]
@@ -126,7 +140,9 @@ class Oracle:
             a["nmat"], self.nstep, self.model, neuphotic if neuphotic is not None else a["neuphotic"],
             k["ae_colidx"].size, _i(k["ae_rowptr"]), _i(k["ae_colidx"]), _d(k["ae_val"]),
             k["ai_colidx"].size, _i(k["ai_rowptr"]), _i(k["ai_colidx"]), _d(k["ai_val"]),
+            int(nbgc),
         )
+        self.nbgc = int(nbgc)
         self.lib = load()
 
     def _u(self, u):

@@ -35,6 +35,7 @@ typedef struct {
     int ai_nnz;
     const int *ai_rowptr, *ai_colidx;
     const double *ai_val;   /* [nmat][ai_nnz] */
+    int nbgc;               /* internal BGC steps per ocean step (section 7); 0 or 1 = one */
 } oracle_desc;
 
 int oracle_ntracer(int model);
@@ -57,6 +58,11 @@ void oracle_spmm_interp(int n, const int *rowptr, const int *colidx,
  * the biogeochemical interface (section 5.2): y and q are [ntracer][nlayer]. */
 int oracle_bgc_column(int model, double insol, int nlayer, const double *h,
                       const double *y, double *q, const double *u, int neuphotic);
+
+/* Source of one ocean step of length dt for one column with nsub internal
+ * BGC steps (section 7): inc = y_nsub - y of explicit Euler at fixed forcing. */
+int oracle_bgc_source(int model, double insol, int nlayer, const double *h, const double *y, double *inc,
+                      const double *u, int neuphotic, double dt, int nsub);
 
 /* One step y_out = Ai(t_j) (Ae(t_j) y_in + dt*q(y_in)) (section 3). */
 int oracle_step(const oracle_desc *g, int nbatch, const double *u, int j,

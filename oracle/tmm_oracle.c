@@ -36,6 +36,9 @@
  *   - Michaelis-Menten uses max(N, 0), with derivative 0 for N <= 0.
  *   - The one-tracer N model is the PO4-DOP model without the DOP tracer
  *     (sigma_2 = 0, all production exported).
+ *   - With nbgc > 1 internal BGC steps per ocean step (section 7), the source
+ *     is the increment of nbgc explicit Euler sub-steps of length dt/nbgc at
+ *     the step's forcing; nbgc = 1 is dt*q(y).
  */
 #include "oracle.h"
 
@@ -313,6 +316,82 @@ static void column_q_adjoint(const column_ctx *c, int model, const double *y, co
     }
 }
 
+/* Section 7: the biogeochemical models take eight internal time steps per
+ * ocean step.  The source over one ocean step of length dt is the increment of
+ * nsub explicit Euler sub-steps of length dt/nsub at fixed forcing:
+ *   inc_0 = 0,  inc_{s+1} = inc_s + (dt/nsub) q(y + inc_s),  source = inc_nsub.
+ * With nsub = 1 this is dt*q(y). */
+#define MAX_SUBSTEPS 32
+
+static void column_source(const column_ctx *c, const double *y, double dt, int nsub, double *inc)
+{
+    int len = c->ntracer * c->nl;
+    double yt[2 * MAX_LAYERS], q[2 * MAX_LAYERS];
+    double h = dt / nsub;
+    for (int i = 0; i < len; ++i) inc[i] = 0.0;
+    for (int s = 0; s < nsub; ++s) {
+        for (int i = 0; i < len; ++i) yt[i] = y[i] + inc[i];
+        column_q(c, yt, q);
+        for (int i = 0; i < len; ++i) inc[i] += h * q[i];
+    }
+}
+
+/* Tangent of column_source in direction ydot. */
+static void column_source_tangent(const column_ctx *c, const double *y, const double *ydot, double dt, int nsub,
+                                  double *incdot)
+{
+    int len = c->ntracer * c->nl;
+    double inc[2 * MAX_LAYERS], yt[2 * MAX_LAYERS], ytd[2 * MAX_LAYERS], q[2 * MAX_LAYERS], qd[2 * MAX_LAYERS];
+    double h = dt / nsub;
+    for (int i = 0; i < len; ++i) { inc[i] = 0.0; incdot[i] = 0.0; }
+    for (int s = 0; s < nsub; ++s) {
+        for (int i = 0; i < len; ++i) { yt[i] = y[i] + inc[i]; ytd[i] = ydot[i] + incdot[i]; }
+        column_q(c, yt, q);
+        column_q_tangent(c, yt, ytd, qd);
+        for (int i = 0; i < len; ++i) { inc[i] += h * q[i]; incdot[i] += h * qd[i]; }
+    }
+}
+
+/* Adjoint of column_source: given mu, the cotangent of the source,
+ * ybar = (d source/dy)^T mu and ubar += (d source/du)^T mu. */
+static void column_source_adjoint(const column_ctx *c, int model, const double *y, const double *mu, double dt,
+                                  int nsub, double *ybar, double *ubar)
+{
+    int len = c->ntracer * c->nl;
+    double ytraj[MAX_SUBSTEPS][2 * MAX_LAYERS];
+    double inc[2 * MAX_LAYERS], q[2 * MAX_LAYERS], ibar[2 * MAX_LAYERS], yb[2 * MAX_LAYERS];
+    double h = dt / nsub;
+    for (int i = 0; i < len; ++i) inc[i] = 0.0;
+    for (int s = 0; s < nsub; ++s) {
+        for (int i = 0; i < len; ++i) ytraj[s][i] = y[i] + inc[i];
+        column_q(c, ytraj[s], q);
+        for (int i = 0; i < len; ++i) inc[i] += h * q[i];
+    }
+    for (int i = 0; i < len; ++i) { ibar[i] = mu[i]; ybar[i] = 0.0; }
+    for (int s = nsub - 1; s >= 0; --s) {
+        double ucol[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        column_q_adjoint(c, model, ytraj[s], ibar, yb, ucol);
+        for (int i = 0; i < len; ++i) {
+            ybar[i] += h * yb[i];
+            ibar[i] += h * yb[i];
+        }
+        for (int p = 0; p < 8; ++p) ubar[p] += h * ucol[p];
+    }
+}
+
+int oracle_bgc_source(int model, double insol, int nlayer, const double *h, const double *y, double *inc,
+                      const double *u, int neuphotic, double dt, int nsub)
+{
+    int ntr = oracle_ntracer(model);
+    if (ntr < 0 || nlayer < 1 || nlayer > MAX_LAYERS || neuphotic < 1 || nsub < 1 || nsub > MAX_SUBSTEPS)
+        return -1;
+    column_ctx c;
+    c.ntracer = ntr; c.nl = nlayer; c.neu = neuphotic; c.h = h; c.insol = insol;
+    column_params(&c, model, u);
+    column_source(&c, y, dt, nsub, inc);
+    return 0;
+}
+
 int oracle_bgc_column(int model, double insol, int nlayer, const double *h,
                       const double *y, double *q, const double *u, int neuphotic)
 {
@@ -335,6 +414,7 @@ static int check_desc(const oracle_desc *g, int nbatch)
     if (oracle_ntracer(g->model) < 0 || nbatch < 1) return -1;
     if (g->nmat < 1 || g->nstep < 1 || g->nstep % g->nmat != 0 || (g->nstep / g->nmat) % 2 != 0) return -1;
     if (g->neuphotic < 1 || g->neuphotic > g->nlayer) return -1;
+    if (g->nbgc < 0 || g->nbgc > MAX_SUBSTEPS) return -1;
     if (g->col_start[0] != 0 || g->col_start[g->ncol] != g->n) return -1;
     for (int c = 0; c < g->ncol; ++c) {
         int nl = g->col_start[c + 1] - g->col_start[c];
@@ -344,6 +424,7 @@ static int check_desc(const oracle_desc *g, int nbatch)
 }
 
 static double step_days(const oracle_desc *g) { return DAYS_PER_YEAR / (double)g->nstep; }
+static int substeps(const oracle_desc *g) { return g->nbgc > 1 ? g->nbgc : 1; }
 
 /* Gathers member b of column c from the n x W state into [ntracer][nl]. */
 static void gather_column(const oracle_desc *g, int W, int b, int c, const double *y, double *col)
@@ -381,14 +462,14 @@ static void add_sources(const oracle_desc *g, int nbatch, const double *u, int j
 {
     int ntr = oracle_ntracer(g->model), np = oracle_nparam(g->model), W = nbatch * ntr;
     double t = (double)(((j % g->nstep) + g->nstep) % g->nstep) / (double)g->nstep;
-    double col[2 * MAX_LAYERS], q[2 * MAX_LAYERS];
+    double col[2 * MAX_LAYERS], inc[2 * MAX_LAYERS];
     for (int c = 0; c < g->ncol; ++c) {
         for (int b = 0; b < nbatch; ++b) {
             column_ctx cc;
             make_column(g, c, t, u + (size_t)b * np, g->model, &cc);
             gather_column(g, W, b, c, y, col);
-            column_q(&cc, col, q);
-            scatter_add_column(g, W, b, c, q, step_days(g), z);
+            column_source(&cc, col, step_days(g), substeps(g), inc);
+            scatter_add_column(g, W, b, c, inc, 1.0, z);
         }
     }
 }
@@ -476,8 +557,8 @@ int oracle_year_tangent(const oracle_desc *g, int nbatch, const double *u,
                 make_column(g, c, t, u + (size_t)b * np, g->model, &cc);
                 gather_column(g, W, b, c, ya, col);
                 gather_column(g, W, b, c, va, dcol);
-                column_q_tangent(&cc, col, dcol, qd);
-                scatter_add_column(g, W, b, c, qd, step_days(g), z);
+                column_source_tangent(&cc, col, dcol, step_days(g), substeps(g), qd);
+                scatter_add_column(g, W, b, c, qd, 1.0, z);
             }
         oracle_spmm_interp(g->n, g->ai_rowptr, g->ai_colidx, g->ai_val + (size_t)k0 * g->ai_nnz,
                            g->ai_val + (size_t)k1 * g->ai_nnz, w, W, z, vb);
@@ -626,9 +707,9 @@ static int reverse_year(const oracle_desc *g, int nbatch, const double *u, const
                 make_column(g, c, t, u + (size_t)b * np, g->model, &cc);
                 gather_column(g, W, b, c, yj, col);
                 gather_column(g, W, b, c, mu, mcol);
-                column_q_adjoint(&cc, g->model, col, mcol, yb, ucol);
-                scatter_add_column(g, W, b, c, yb, step_days(g), lam2);
-                for (int p = 0; p < np; ++p) ub[(size_t)b * np + p] += step_days(g) * ucol[p];
+                column_source_adjoint(&cc, g->model, col, mcol, step_days(g), substeps(g), yb, ucol);
+                scatter_add_column(g, W, b, c, yb, 1.0, lam2);
+                for (int p = 0; p < np; ++p) ub[(size_t)b * np + p] += ucol[p];
             }
         int m = snapshot_of(g, j);
         if (obs && m >= 0) {

@@ -398,3 +398,119 @@ def test_initial_state_gradient_matches_central_differences(tiny_ndop):
         d = rng.standard_normal(y0.shape) * y0
         fd = _fd4(lambda s: o.year_misfit(u, y0 + s * d, obs)[0], 0.0, 1e-4)
         assert np.sum(g * d) == pytest.approx(fd, rel=1e-6)
+
+
+# --------------------------------------------------------------------------
+# Internal BGC steps (section 7: several biogeochemical steps per ocean step)
+# --------------------------------------------------------------------------
+
+def _column(inp, c):
+    g = inp.grid
+    return g.col_start[c], g.col_start[c + 1], g.lat[c]
+
+
+def test_single_substep_is_the_plain_source(tiny_ndop):
+    """nbgc = 1 (and 0) reproduce dt*q bitwise, so every other pin covers that path."""
+    inp = tiny_ndop
+    u = synth.nominal(synth.MODEL_NDOP)
+    s, e, lat = _column(inp, 3)
+    y = inp.initial_state()[s:e].T.copy()
+    insol = oracle.insolation(lat, 0.2)
+    dt = 360.0 / inp.nstep
+    q = oracle.bgc_column(inp.model, insol, inp.grid.dz[:e - s], y, u, inp.neuphotic)
+    inc = oracle.bgc_source(inp.model, insol, inp.grid.dz[:e - s], y, u, inp.neuphotic, dt, 1)
+    assert np.array_equal(inc, dt * q)
+    y0 = inp.initial_state()
+    a, _ = oracle.Oracle(inp, nbgc=0).year(u, y0)
+    b, _ = oracle.Oracle(inp, nbgc=1).year(u, y0)
+    assert np.array_equal(a, b)
+
+
+def test_substeps_are_explicit_euler_of_the_column_ode(tiny_ndop):
+    """The source with n internal steps is n explicit Euler steps of dt/n on dy/dt = q(y).
+
+    Brute force from the (separately pinned) column term, and first-order
+    convergence towards a fine-step solution of the same ODE."""
+    inp = tiny_ndop
+    u = synth.nominal(synth.MODEL_NDOP)
+    dt = 360.0 / inp.nstep
+    for c in (0, 40):
+        s, e, lat = _column(inp, c)
+        h = inp.grid.dz[:e - s]
+        y0 = inp.initial_state()[s:e].T.copy()
+        insol = oracle.insolation(lat, 0.45)
+
+        def euler(n, step):
+            y = y0.copy()
+            for _ in range(n):
+                y = y + step * oracle.bgc_column(inp.model, insol, h, y, u, inp.neuphotic)
+            return y
+        for step in (dt, 30.0):
+            end = y0 + oracle.bgc_source(inp.model, insol, h, y0, u, inp.neuphotic, step, 8)
+            assert np.abs(end - euler(8, step / 8)).max() <= 1e-14 * np.abs(y0).max()
+        # first order: over a 5-day step the error against 8192 Euler steps halves as n doubles
+        fine = euler(8192, 5.0 / 8192) - y0
+        errs = [np.abs(oracle.bgc_source(inp.model, insol, h, y0, u, inp.neuphotic, 5.0, n) - fine).max()
+                for n in (4, 8, 16, 32)]
+        assert errs[0] > 1e-6 * np.abs(fine).max()
+        for a, b in zip(errs, errs[1:]):
+            assert 1.8 < a / b < 2.2, errs
+
+
+def test_substep_decay_closed_form(tiny_ndop):
+    """Identity transport and alpha = 0: each ocean step multiplies DOP by (1 - lambda dt/n)^n."""
+    import copy
+    inp = tiny_ndop
+    ident = copy.deepcopy(inp)
+    for kind in ("ae", "ai"):
+        rowptr = getattr(inp.tm, kind + "_rowptr")
+        colidx = getattr(inp.tm, kind + "_colidx")
+        rows = np.repeat(np.arange(inp.n), np.diff(rowptr))
+        val = np.where(rows == colidx, 1.0, 0.0)
+        setattr(ident.tm, kind + "_val", np.broadcast_to(val, (inp.nmat, val.size)).copy())
+    u = synth.nominal(synth.MODEL_NDOP)
+    u[0] = 0.0
+    y0 = np.column_stack([np.full(inp.n, 2.0), np.linspace(0.1, 0.5, inp.n)])
+    dtd = 360.0 / inp.nstep
+    for nb in (2, 8):
+        y1, _ = oracle.Oracle(ident, nbgc=nb).year(u, y0)
+        decay = (1 - u[4] * dtd / nb) ** (nb * inp.nstep)
+        assert np.abs(y1[:, 1] / (y0[:, 1] * decay) - 1).max() < 1e-12
+        assert np.abs(y1.sum(1) / y0.sum(1) - 1).max() < 2e-13
+
+
+def test_substeps_conserve_mass(small_ndop):
+    u = synth.nominal(synth.MODEL_NDOP)
+    y0 = small_ndop.initial_state()
+    y1, _ = oracle.Oracle(small_ndop, nbgc=8).year(u, y0)
+    y1p, _ = oracle.Oracle(small_ndop, nbgc=1).year(u, y0)
+    V = small_ndop.grid.volumes()
+    m0 = V @ y0.sum(1)
+    assert abs(V @ y1.sum(1) - m0) <= 1e-13 * m0
+    assert 0 < np.abs(y1 - y1p).max() < 0.05 * np.abs(y1p).max()   # close to, not equal to, one step
+
+
+def test_substep_derivatives(tiny_ndop):
+    """Tangent vs central differences, tangent vs reverse (dot test), dJ/du vs differences, with nbgc = 8."""
+    inp = tiny_ndop
+    o = oracle.Oracle(inp, nbgc=8)
+    u = synth.nominal(synth.MODEL_NDOP)
+    rng = np.random.default_rng(14)
+    y = inp.initial_state() * rng.uniform(0.8, 1.2, size=(inp.n, 2))
+    v = rng.standard_normal(y.shape) * y
+    w = rng.standard_normal(y.shape)
+    _, jv = o.year_tangent(u, y, v)
+    h = 1e-5
+    fd = (o.year(u, y + h * v)[0] - o.year(u, y - h * v)[0]) / (2 * h)
+    assert np.abs(jv - fd).max() < 1e-7 * np.abs(jv).max()
+    ybar, _ = o.year_vjp(u, y, w)
+    assert np.sum(w * jv) == pytest.approx(np.sum(ybar * v), rel=1e-12)
+    obs = _obs(inp)
+    y0 = inp.initial_state()
+    J, dJdu, _ = o.year_adjoint(u, y0, obs)
+    for p in range(u.size):
+        def Jp(x):
+            q = u.copy()
+            q[p] = x
+            return o.year_misfit(q, y0, obs)[0]
+        assert dJdu[0, p] == pytest.approx(_fd4(Jp, u[p], 1e-4 * abs(u[p])), rel=1e-6), p

@@ -52,7 +52,7 @@ def bytes_per_step(n, nnz_e, nnz_i, W):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("tmm_device.hpp", "tmm_persistent.hpp", "tmm.hip"):
+    for f in ("tmm_device.hpp", "tmm_persistent.hpp", "tmm_substep.hpp", "tmm.hip"):
         with open(os.path.join(ROOT, "paper_1410_0204_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -173,6 +173,11 @@ def main():
         ratio = ms_adj / ms_fwd1
         log(f"[bench] adjoint year {ms_adj:.2f} ms vs forward {ms_fwd1:.2f} ms: ratio {ratio:.2f}")
 
+    # the same workload with 8 internal BGC steps per ocean step (section 7)
+    substeps = None
+    if not args.forward_only:
+        substeps = bench_substeps(args, inp, u, obs, dev, stream, ms_per_year)
+
     cpu = None
     if not args.no_cpu_baseline and not args.forward_only:
         import oracle
@@ -210,10 +215,48 @@ def main():
                      "us_per_time_step": us_per_step},
         "per_step_path": per_step,
         "adjoint_forward_ratio": ratio,
+        "bgc_substeps_8": substeps,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     t.close()
+
+
+def bench_substeps(args, inp, u, obs, dev, stream, ms_plain, nbgc=8):
+    """Forward model years and the adjoint with nbgc internal BGC steps per
+    ocean step on the same workload, against one evaluation per step."""
+    import dataclasses
+    import torch
+    from paper_1410_0204_amd import tmm
+    sub = dataclasses.replace(inp, nbgc=nbgc)
+    t = tmm.TMM(sub.desc_arrays(), nbatch_max=1, adjoint_nbatch_max=1, ckpt_every=240, device=dev, stream=stream)
+    t.set_params(u)
+    y0 = t.state(sub.initial_state())
+    ya = t.state()
+    t.year(y0, nyears=1, out=ya, residuals=False)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    years = max(2, min(args.steps, 5))
+    start.record(stream)
+    t.year(y0, nyears=years, out=ya, residuals=False)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_fwd = start.elapsed_time(stop) / years
+    t.year_adjoint(y0, obs, want_dy0=False)
+    torch.cuda.synchronize()
+    start.record(stream)
+    t.year_adjoint(y0, obs, want_dy0=True)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_adj = start.elapsed_time(stop)
+    rec = {"nbgc": nbgc, "ms_per_year": ms_fwd, "model_years_per_s": 1000.0 / ms_fwd,
+           "cost_vs_one_evaluation": ms_fwd / ms_plain, "adjoint_ms": ms_adj,
+           "adjoint_forward_ratio": ms_adj / ms_fwd,
+           "adjoint_path": "k_adjoint_persistent" if t.query(tmm.TMM_Q_PERSISTENT_ADJOINT) else "k_adjoint"}
+    log(f"[bench] {nbgc} internal BGC steps: {ms_fwd:.3f} ms/model-year ({ms_fwd / ms_plain:.2f}x), "
+        f"adjoint {ms_adj:.2f} ms (ratio {ms_adj / ms_fwd:.2f}, {rec['adjoint_path']})")
+    t.close()
+    return rec
 
 
 def _events():

@@ -82,6 +82,10 @@ typedef struct {
     int nstep;              /* steps per model year (2880); nstep/nmat must be even */
     int model;              /* TMM_MODEL_* */
     int neuphotic;          /* euphotic layers (2 in the paper's experiments, section 7) */
+    int nbgc;               /* internal BGC time steps per ocean step (section 7; 8 in the paper's
+                               experiments): the source of a step is the increment of nbgc explicit
+                               Euler steps of dt/nbgc at the step's forcing.  0 or 1 = one evaluation
+                               dt*q(y).  At most 16; above 1 needs neuphotic <= 4 */
     int nbatch_max;         /* largest ensemble (member count) the handle must hold */
     int adjoint_nbatch_max; /* largest ensemble for tmm_year_adjoint (0 disables it) */
     int ckpt_every;         /* steps between adjoint checkpoints; divides nstep (ignored if no adjoint) */
@@ -167,7 +171,9 @@ enum {
     TMM_Q_PERSISTENT = 1,   /* 1 if the persistent year kernel is available on this handle */
     TMM_Q_DOMAINS = 2,      /* workgroups (column domains) of the persistent kernel */
     TMM_Q_WORKSPACE = 3,    /* workspace bytes in use */
-    TMM_Q_COMPUTE_UNITS = 4 /* compute units of the device */
+    TMM_Q_COMPUTE_UNITS = 4, /* compute units of the device */
+    TMM_Q_PERSISTENT_ADJOINT = 5 /* 1 if single-member adjoints use the persistent reverse kernel (its
+                                    store of internal BGC steps must fit the workgroup's LDS) */
 };
 
 /* Sets an execution option; results are the same either way up to rounding

@@ -125,7 +125,7 @@ def bgc_source(model, insol, h, y, u, neuphotic, dt, nsub):
 class Oracle:
     """Reference implementation bound to one set of inputs (a ``synth.Inputs``)."""
 
-    def __init__(self, inputs, nstep=None, model=None, neuphotic=None, nbgc=1):
+    def __init__(self, inputs, nstep=None, model=None, neuphotic=None, nbgc=None):
         a = inputs.desc_arrays()
         self._keep = {k: v for k, v in a.items() if isinstance(v, np.ndarray)}
         self.n = a["n"]
@@ -140,9 +140,9 @@ class Oracle:
             a["nmat"], self.nstep, self.model, neuphotic if neuphotic is not None else a["neuphotic"],
             k["ae_colidx"].size, _i(k["ae_rowptr"]), _i(k["ae_colidx"]), _d(k["ae_val"]),
             k["ai_colidx"].size, _i(k["ai_rowptr"]), _i(k["ai_colidx"]), _d(k["ai_val"]),
-            int(nbgc),
+            int(nbgc if nbgc is not None else a.get("nbgc", 1)),
         )
-        self.nbgc = int(nbgc)
+        self.nbgc = int(self.desc.nbgc)
         self.lib = load()
 
     def _u(self, u):

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtmm.so")
 SOURCES = [os.path.join(HERE, "csrc", "tmm.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "tmm_device.hpp"), os.path.join(ROOT, "include", "tmm.h")]
+HEADERS = [os.path.join(HERE, "csrc", f) for f in ("tmm_device.hpp", "tmm_persistent.hpp", "tmm_substep.hpp")] + [
+    os.path.join(ROOT, "include", "tmm.h")]
 
 
 def command(out):

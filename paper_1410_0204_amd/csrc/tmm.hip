@@ -73,6 +73,7 @@ std::vector<int> tiling_sizes(int nlayer) {
 struct Plan {
     int n = 0, ncol = 0, nlayer = 0, nmat = 0, nstep = 0, model = 0, neu = 0;
     int nbatch_max = 0, adj_nb = 0, ckpt = 0, ntr = 0, nparam = 0;
+    int nsub = 1;                          // internal BGC steps per ocean step
     int npad = 0, ew = 0, etw = 0;
     size_t nblk = 0;                       // sum of n_c^2
     std::vector<int> col_start, tiles_sizes;
@@ -106,6 +107,8 @@ int validate(const tmm_desc* d, Plan& P) {
     if (ntracer_of(d->model) < 0) return TMM_EINVAL;
     if (d->nmat < 1 || d->nstep < 1 || d->nstep % d->nmat || (d->nstep / d->nmat) % 2) return TMM_EINVAL;
     if (d->neuphotic < 1 || d->neuphotic > d->nlayer) return TMM_EINVAL;
+    if (d->nbgc < 0 || d->nbgc > tmm::kSubMax) return TMM_EINVAL;
+    if (d->nbgc > 1 && d->neuphotic > tmm::kSubNeuMax) return TMM_EUNSUPPORTED;
     if (d->nbatch_max < 1 || d->adjoint_nbatch_max < 0 || d->adjoint_nbatch_max > d->nbatch_max) return TMM_EINVAL;
     if (d->adjoint_nbatch_max > 0 && (d->ckpt_every < 1 || d->nstep % d->ckpt_every)) return TMM_EINVAL;
     if (d->adjoint_nbatch_max * nparam_of(d->model) > 128) return TMM_EINVAL;
@@ -140,6 +143,7 @@ int validate(const tmm_desc* d, Plan& P) {
 
     P.n = d->n; P.ncol = d->ncol; P.nlayer = d->nlayer; P.nmat = d->nmat; P.nstep = d->nstep;
     P.model = d->model; P.neu = d->neuphotic; P.nbatch_max = d->nbatch_max;
+    P.nsub = d->nbgc > 1 ? d->nbgc : 1;
     P.adj_nb = d->adjoint_nbatch_max; P.ckpt = P.adj_nb > 0 ? d->ckpt_every : 0;
     P.ntr = ntracer_of(d->model); P.nparam = nparam_of(d->model);
     P.npad = (d->n + 63) / 64 * 64;
@@ -249,6 +253,7 @@ struct tmm_ctx {
     std::vector<double> h_vec;
     // persistent year kernel
     bool pers_ok = false;          // tables built and the launch fits the device
+    bool pers_adj_ok = false;      // ... and so does the persistent adjoint
     bool pers_enabled = true;      // option TMM_OPT_PERSISTENT
     int pers_G = 0;
     int pers_kmax = 16;
@@ -295,6 +300,8 @@ struct tmm_ctx {
         m.rho = at<double>(P.o_rho);
         m.drho = at<double>(P.o_drho);
         m.member = at<int>(P.o_member);
+        m.nsub = P.nsub;
+        m.hsub = tmm::kDaysPerYear / P.nstep / P.nsub;
         return m;
     }
     tmm::Mats mats() const {
@@ -356,6 +363,7 @@ int copy(tmm_ctx* h, double* dst, const double* src, size_t len) {
 int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const double* v, double* vo) {
     const int W = nb * h->P.ntr;
     const bool tangent = v != nullptr;
+    const bool sub = h->P.nsub > 1;
     if (!tangent && nb >= h->wide_min_members && h->P.nlayer <= 32 && h->P.ew <= tmm::kMembersEll) {
         // member-parallel kernel: one wavefront per column and 64 members
         const int kmax = h->P.nlayer <= 16 ? 16 : h->P.nlayer <= 24 ? 24 : 32;
@@ -367,7 +375,10 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
             blk(64 * tmm::kMembersWaves);
 #define TMM_MEMBERS(NT, KM)                                                                                  \
     do {                                                                                                     \
-        if (h->P.ew <= 5)                                                                                    \
+        if (sub)                                                                                             \
+            hipLaunchKernelGGL((tmm::k_step_members<NT, KM, tmm::kMembersEll, true>), grid, blk, 0,          \
+                               h->launch_stream(), g, md, mt, h->P.ncol, nb, j, dtd, y, yo);                 \
+        else if (h->P.ew <= 5)                                                                               \
             hipLaunchKernelGGL((tmm::k_step_members<NT, KM, 5>), grid, blk, 0, h->launch_stream(), g, md, mt, h->P.ncol,  \
                                nb, j, dtd, y, yo);                                                           \
         else                                                                                                 \
@@ -397,50 +408,64 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
     tmm::Model md = h->model();
     tmm::Mats mt = h->mats();
     dim3 grid(t.ntile), blk(block);
-    if (CW == 1 && !tangent)
-        hipLaunchKernelGGL((tmm::k_step<1, false, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->launch_stream(),
-                           g, md, mt, W, tpr, j, dtd, y, yo, v, vo);
-    else if (CW == 1)
-        hipLaunchKernelGGL((tmm::k_step<1, true, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->launch_stream(),
-                           g, md, mt, W, tpr, j, dtd, y, yo, v, vo);
-    else if (!tangent)
-        hipLaunchKernelGGL((tmm::k_step<2, false, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->launch_stream(),
-                           g, md, mt, W, tpr, j, dtd, y, yo, v, vo);
-    else
-        hipLaunchKernelGGL((tmm::k_step<2, true, kMaxTileRows, kMaxTileRows>), grid, blk, lds, h->launch_stream(),
-                           g, md, mt, W, tpr, j, dtd, y, yo, v, vo);
+#define TMM_STEP(C, T)                                                                                       \
+    do {                                                                                                     \
+        if (sub)                                                                                             \
+            hipLaunchKernelGGL((tmm::k_step<C, T, kMaxTileRows, kMaxTileRows, true>), grid, blk, lds,       \
+                               h->launch_stream(), g, md, mt, W, tpr, j, dtd, y, yo, v, vo);                 \
+        else                                                                                                 \
+            hipLaunchKernelGGL((tmm::k_step<C, T, kMaxTileRows, kMaxTileRows>), grid, blk, lds,             \
+                               h->launch_stream(), g, md, mt, W, tpr, j, dtd, y, yo, v, vo);                 \
+    } while (0)
+    if (CW == 1 && !tangent) TMM_STEP(1, false);
+    else if (CW == 1) TMM_STEP(1, true);
+    else if (!tangent) TMM_STEP(2, false);
+    else TMM_STEP(2, true);
+#undef TMM_STEP
     TMM_LAUNCHED();
     return TMM_OK;
 }
 
-template <int TPB>
-const void* persistent_kernel_tpb(int ntr, bool tangent, int kmax) {
-    if (kmax == 16) {
-        if (ntr == 1) return tangent ? (const void*)&tmm::k_year_persistent<1, true, 16, TPB>
-                                     : (const void*)&tmm::k_year_persistent<1, false, 16, TPB>;
-        return tangent ? (const void*)&tmm::k_year_persistent<2, true, 16, TPB>
-                       : (const void*)&tmm::k_year_persistent<2, false, 16, TPB>;
-    }
-    if (ntr == 1) return tangent ? (const void*)&tmm::k_year_persistent<1, true, 32, TPB>
-                                 : (const void*)&tmm::k_year_persistent<1, false, 32, TPB>;
-    return tangent ? (const void*)&tmm::k_year_persistent<2, true, 32, TPB>
-                   : (const void*)&tmm::k_year_persistent<2, false, 32, TPB>;
+// Persistent kernels by tracers, tangent, block-row bound and internal BGC
+// steps (sn = 0: one evaluation per step; else the euphotic register width);
+// 512-thread workgroups exist for 16-row blocks only.
+template <int NTR, int KMAX, int TPB>
+const void* persistent_kernel_of(bool tangent, int sn) {
+    if (sn == 2) return tangent ? (const void*)&tmm::k_year_persistent<NTR, true, KMAX, TPB, 2>
+                                : (const void*)&tmm::k_year_persistent<NTR, false, KMAX, TPB, 2>;
+    if (sn == 4) return tangent ? (const void*)&tmm::k_year_persistent<NTR, true, KMAX, TPB, 4>
+                                : (const void*)&tmm::k_year_persistent<NTR, false, KMAX, TPB, 4>;
+    return tangent ? (const void*)&tmm::k_year_persistent<NTR, true, KMAX, TPB>
+                   : (const void*)&tmm::k_year_persistent<NTR, false, KMAX, TPB>;
 }
 
-template <int TPB>
-const void* adjoint_kernel_tpb(int ntr, int kmax) {
-    if (kmax == 16) return ntr == 1 ? (const void*)&tmm::k_adjoint_persistent<1, 16, TPB>
-                                    : (const void*)&tmm::k_adjoint_persistent<2, 16, TPB>;
-    return ntr == 1 ? (const void*)&tmm::k_adjoint_persistent<1, 32, TPB>
-                    : (const void*)&tmm::k_adjoint_persistent<2, 32, TPB>;
+const void* persistent_kernel(int ntr, bool tangent, int kmax, int tpb, int sn) {
+    if (tpb == 512)
+        return ntr == 1 ? persistent_kernel_of<1, 16, 512>(tangent, sn) : persistent_kernel_of<2, 16, 512>(tangent, sn);
+    if (kmax == 16)
+        return ntr == 1 ? persistent_kernel_of<1, 16, 256>(tangent, sn) : persistent_kernel_of<2, 16, 256>(tangent, sn);
+    return ntr == 1 ? persistent_kernel_of<1, 32, 256>(tangent, sn) : persistent_kernel_of<2, 32, 256>(tangent, sn);
 }
 
-const void* adjoint_kernel(int ntr, int kmax, int tpb) {
-    return tpb == 512 ? adjoint_kernel_tpb<512>(ntr, kmax) : adjoint_kernel_tpb<256>(ntr, kmax);
+template <int NTR, int KMAX, int TPB>
+const void* adjoint_kernel_of(int sn) {
+    if (sn == 2) return (const void*)&tmm::k_adjoint_persistent<NTR, KMAX, TPB, 2>;
+    if (sn == 4) return (const void*)&tmm::k_adjoint_persistent<NTR, KMAX, TPB, 4>;
+    return (const void*)&tmm::k_adjoint_persistent<NTR, KMAX, TPB>;
 }
 
-const void* persistent_kernel(int ntr, bool tangent, int kmax, int tpb) {
-    return tpb == 512 ? persistent_kernel_tpb<512>(ntr, tangent, kmax) : persistent_kernel_tpb<256>(ntr, tangent, kmax);
+const void* adjoint_kernel(int ntr, int kmax, int tpb, int sn) {
+    if (tpb == 512) return ntr == 1 ? adjoint_kernel_of<1, 16, 512>(sn) : adjoint_kernel_of<2, 16, 512>(sn);
+    if (kmax == 16) return ntr == 1 ? adjoint_kernel_of<1, 16, 256>(sn) : adjoint_kernel_of<2, 16, 256>(sn);
+    return ntr == 1 ? adjoint_kernel_of<1, 32, 256>(sn) : adjoint_kernel_of<2, 32, 256>(sn);
+}
+
+// Internal-step variant of the persistent kernels for a plan.
+int persistent_sn(const Plan& P) { return P.nsub > 1 ? (P.neu <= 2 ? 2 : 4) : 0; }
+
+// Dynamic LDS of the persistent adjoint: the internal-step states of every row.
+size_t adjoint_dyn_lds(const Plan& P, int tpb) {
+    return P.nsub > 1 ? (size_t)P.nsub * tpb * P.ntr * 8 : 0;
 }
 
 tmm::Persist persist_args(tmm_ctx* h) {
@@ -475,7 +500,7 @@ int launch_persistent(tmm_ctx* h, tmm::StepRange sr, const double* y, double* ou
     tmm::Persist ps = persist_args(h);
     double dtd = tmm::kDaysPerYear / P.nstep;
     void* args[] = {&g, &md, &mt, &ps, &sr, &dtd, &y, &out, &a, &b, &v, &vout, &va, &vb};
-    TMM_TRY(hipLaunchCooperativeKernel(persistent_kernel(P.ntr, v != nullptr, h->pers_kmax, h->pers_tpb),
+    TMM_TRY(hipLaunchCooperativeKernel(persistent_kernel(P.ntr, v != nullptr, h->pers_kmax, h->pers_tpb, persistent_sn(P)),
                                        dim3(h->pers_G), dim3(h->pers_tpb), args, 0, h->stream));
     h->pers_used = true;
     return TMM_OK;
@@ -501,8 +526,9 @@ int launch_adjoint_persistent(tmm_ctx* h, int j_lo, int j_hi, const double* ysto
     double dtd = tmm::kDaysPerYear / P.nstep;
     void* args[] = {&g, &md, &mt, &ps, &dtd, &j_lo, &j_hi, &ystore, &obs, &src_scale, &mu_in, &mu_out,
                     &a, &b, &ubar_dom};
-    TMM_TRY(hipLaunchCooperativeKernel(adjoint_kernel(P.ntr, h->pers_kmax, h->pers_tpb), dim3(h->pers_G),
-                                       dim3(h->pers_tpb), args, 0, h->stream));
+    TMM_TRY(hipLaunchCooperativeKernel(adjoint_kernel(P.ntr, h->pers_kmax, h->pers_tpb, persistent_sn(P)),
+                                       dim3(h->pers_G), dim3(h->pers_tpb), args, adjoint_dyn_lds(P, h->pers_tpb),
+                                       h->stream));
     h->pers_used = true;
     return TMM_OK;
 }
@@ -603,24 +629,35 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     TMM_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     h->num_cu = ncu;
     h->pers_ok = false;
+    h->pers_adj_ok = false;
     if (!coop || P.ew > tmm::kEllMax || P.nlayer > 32 || P.neu > tmm::kNeuMax) return TMM_OK;
     h->pers_kmax = P.nlayer <= 16 ? 16 : 32;
     if (target_rows < 1) target_rows = kDefaultDomainRows;
     // 512-thread workgroups only where the row's Ai block fits the halved register budget
     const int tpb = (target_rows > 256 && h->pers_kmax == 16) ? tmm::kPersistThreadsMax : 256;
     target_rows = std::min(target_rows, tpb);
-    int occ = 0;
-    for (int ntr = 1; ntr <= 2; ++ntr)
-        for (int t = 0; t < 2; ++t) {
-            int o = 0;
-            TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, persistent_kernel(ntr, t, h->pers_kmax, tpb),
-                                                                 tpb, 0));
-            occ = (ntr == 1 && t == 0) ? o : std::min(occ, o);
-            if (t == 0) {
-                TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, adjoint_kernel(ntr, h->pers_kmax, tpb), tpb, 0));
-                occ = std::min(occ, o);
-            }
+    // co-residency of the forward kernels (both modes) and, separately, of the adjoint
+    const int sn = persistent_sn(P);
+    int occ = 0, occ_adj = 0;
+    for (int t = 0; t < 2; ++t) {
+        int o = 0;
+        TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, persistent_kernel(P.ntr, t, h->pers_kmax, tpb, sn),
+                                                             tpb, 0));
+        occ = t == 0 ? o : std::min(occ, o);
+    }
+    {
+        // the internal-step store of the adjoint is dynamic LDS beside the static arrays
+        const void* fa = adjoint_kernel(P.ntr, h->pers_kmax, tpb, sn);
+        const size_t dyn = adjoint_dyn_lds(P, tpb);
+        hipFuncAttributes attr;
+        int lds_max = 0;
+        TMM_TRY(hipFuncGetAttributes(&attr, fa));
+        TMM_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        if (attr.sharedSizeBytes + dyn <= (size_t)lds_max) {
+            if (dyn > 0) TMM_TRY(hipFuncSetAttribute(fa, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+            TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_adj, fa, tpb, dyn));
         }
+    }
     const int maxG = std::min(kMaxDomains, std::min(ncu * occ, P.ncol));
     if (maxG < 1) return TMM_OK;
     int G = std::min(maxG, std::max(1, (P.n + target_rows - 1) / target_rows));
@@ -680,6 +717,7 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     h->pers_G = G;
     h->pers_tpb = tpb;
     h->pers_ok = true;
+    h->pers_adj_ok = (long long)ncu * occ_adj >= G;
     return TMM_OK;
 }
 
@@ -1185,6 +1223,9 @@ int tmm_query(tmm_handle h, int what, long long* value) {
         case TMM_Q_DOMAINS: *value = h->pers_G; return TMM_OK;
         case TMM_Q_WORKSPACE: *value = (long long)h->P.total; return TMM_OK;
         case TMM_Q_COMPUTE_UNITS: *value = h->num_cu; return TMM_OK;
+        case TMM_Q_PERSISTENT_ADJOINT:
+            *value = (h->pers_ok && h->pers_adj_ok && h->P.etw <= tmm::kEllMax) ? 1 : 0;
+            return TMM_OK;
         default: return TMM_EINVAL;
     }
 }
@@ -1202,7 +1243,7 @@ int tmm_year_adjoint(tmm_handle h, const double* y0, const double* obs, int ckpt
     const size_t n = P.n, len = n * W;
     const int K = P.ckpt, spm = P.nstep / P.nmat, nseg = P.nstep / K;
     const double dtd = tmm::kDaysPerYear / P.nstep;
-    if (nb == 1 && h->pers_ok && h->pers_enabled && P.etw <= tmm::kEllMax)
+    if (nb == 1 && h->pers_ok && h->pers_adj_ok && h->pers_enabled && P.etw <= tmm::kEllMax)
         return adjoint_persistent(h, y0, obs, J_host, dJdu_host, dJdy0);
     const Tiling& tl = h->tiling_for(W, 1, 256 * 8 * np);
     tmm::Grid g = h->grid(tl);
@@ -1245,14 +1286,19 @@ int tmm_year_adjoint(tmm_handle h, const double* y0, const double* obs, int ckpt
     auto adjoint = [&](int j, int use_ae, int use_ai, const double* mu_in, const double* yj, const double* ob,
                        double* out) -> int {
         const double sc = 1.0 / (P.nmat * h->vtot);
-        if (ntr == 2)
+        double* ub = use_ae ? ubt : nullptr;
+        if (ntr == 2 && P.nsub > 1)
+            hipLaunchKernelGGL((tmm::k_adjoint<2, kMaxTileRows, kMaxTileRows, true>), dim3(tl.ntile), dim3(256), lds,
+                               h->stream, g, md, mt, W, nb, j, dtd, use_ae, use_ai, mu_in, yj, ob, sc, out, ub);
+        else if (ntr == 2)
             hipLaunchKernelGGL((tmm::k_adjoint<2, kMaxTileRows, kMaxTileRows>), dim3(tl.ntile), dim3(256), lds,
-                               h->stream, g, md, mt, W, nb, j, dtd, use_ae, use_ai, mu_in, yj, ob, sc, out,
-                               use_ae ? ubt : nullptr);
+                               h->stream, g, md, mt, W, nb, j, dtd, use_ae, use_ai, mu_in, yj, ob, sc, out, ub);
+        else if (P.nsub > 1)
+            hipLaunchKernelGGL((tmm::k_adjoint<1, kMaxTileRows, kMaxTileRows, true>), dim3(tl.ntile), dim3(256), lds,
+                               h->stream, g, md, mt, W, nb, j, dtd, use_ae, use_ai, mu_in, yj, ob, sc, out, ub);
         else
             hipLaunchKernelGGL((tmm::k_adjoint<1, kMaxTileRows, kMaxTileRows>), dim3(tl.ntile), dim3(256), lds,
-                               h->stream, g, md, mt, W, nb, j, dtd, use_ae, use_ai, mu_in, yj, ob, sc, out,
-                               use_ae ? ubt : nullptr);
+                               h->stream, g, md, mt, W, nb, j, dtd, use_ae, use_ai, mu_in, yj, ob, sc, out, ub);
         TMM_LAUNCHED();
         return TMM_OK;
     };

@@ -38,6 +38,12 @@ struct BgcParams {
     double alpha, kw, k1, ki, lam, sig, b;
 };
 
+}  // namespace tmm
+
+#include "tmm_substep.hpp"
+
+namespace tmm {
+
 __device__ __forceinline__ BgcParams load_params(const double* __restrict__ u, int model, int nparam, int m) {
     const double* p = u + (size_t)m * nparam;
     BgcParams r;
@@ -189,6 +195,8 @@ struct Model {
     const double* rho;       // [members][nlayer+1][nlayer]
     const double* drho;
     const int* member;       // [slots] parameter row of each state slot
+    int nsub;                // internal BGC steps per ocean step (section 7)
+    double hsub;             // their length dt_d / nsub, days
 };
 
 struct Mats {
@@ -296,13 +304,136 @@ __device__ __forceinline__ void bgc_q_tangent(const Grid& g, const Model& md, co
     q2 = p.sig * fdk - p.lam * dopd;
 }
 
+// Euphotic constants of one (column, member) gathered from memory; loads of
+// layers beyond the euphotic zone are clamped to layer 0 and ignored.
+template <int NEU>
+__device__ __forceinline__ Euphotic<NEU> euphotic_from_memory(const Grid& g, const Model& md, const BgcParams& p, int m,
+                                                              int nc, double Q, int& ne) {
+    ne = nc < g.neu ? nc : g.neu;
+    const double* light = md.light + (size_t)m * g.nlayer;
+    const double* rho = md.rho + ((size_t)m * (g.nlayer + 1) + nc) * g.nlayer;
+    double le[NEU], hz[NEU], re[NEU];
+#pragma unroll
+    for (int e = 0; e < NEU; ++e) {
+        const int ee = e < ne ? e : 0;
+        le[e] = light[ee];
+        hz[e] = g.dz[ee];
+        re[e] = rho[ee];
+    }
+    return make_euphotic<NEU>(p, Q, ne, le, hz, re);
+}
+
+// Source of one (row, member) over one ocean step with md.nsub internal BGC
+// steps (section 7), from the state in memory: out = inc_nsub of the row's
+// NTR tracers; with TANGENT also its tangent in direction v.
+template <int NTR, bool TANGENT>
+__device__ __forceinline__ void bgc_inc(const Grid& g, const Model& md, const double* __restrict__ y,
+                                        const double* __restrict__ v, int W, const ColumnRef& c, int slot,
+                                        double* out, double* outd) {
+    constexpr int NEU = kSubNeuMax;
+    const int m = md.member[slot];
+    const BgcParams p = load_params(md.u, md.model, md.nparam, m);
+    int ne;
+    const Euphotic<NEU> E = euphotic_from_memory<NEU>(g, md, p, m, c.nc, c.Q, ne);
+    const double rho_k = md.rho[((size_t)m * (g.nlayer + 1) + c.nc) * g.nlayer + c.k];
+    double ye[NEU][NTR], ve[NEU][NTR], yk[NTR], vk[NTR];
+#pragma unroll
+    for (int e = 0; e < NEU; ++e) {
+        const size_t at = (size_t)(c.rs + (e < ne ? e : 0)) * W + slot * NTR;
+#pragma unroll
+        for (int t = 0; t < NTR; ++t) {
+            ye[e][t] = e < ne ? y[at + t] : 0.0;
+            ve[e][t] = (TANGENT && e < ne) ? v[at + t] : 0.0;
+        }
+    }
+    const size_t ak = (size_t)(c.rs + c.k) * W + slot * NTR;
+#pragma unroll
+    for (int t = 0; t < NTR; ++t) {
+        yk[t] = y[ak + t];
+        vk[t] = TANGENT ? v[ak + t] : 0.0;
+    }
+    double o[NTR], od[NTR];
+    if (TANGENT) {
+        row_source_tangent<NTR, NEU>(p, E, c.k, ye, ve, yk, vk, rho_k, md.hsub, md.nsub, o, od);
+    } else {
+        row_source<NTR, NEU>(p, E, c.k, ye, yk, rho_k, md.hsub, md.nsub, o);
+    }
+#pragma unroll
+    for (int t = 0; t < NTR; ++t) {
+        out[t] = o[t];
+        if (TANGENT) outd[t] = od[t];
+    }
+}
+
+// Reverse mode of bgc_inc for one (row, member) of the tile adjoint: the
+// euphotic internal steps are replayed from the ocean step's state for every
+// reverse internal step (no storage; quadratic in nsub).  Adds h (dq/dy)^T mu
+// to ybar[NTR] and the unscaled (dq/du)^T mu sums to ub[NP].
+template <int NTR, int NP>
+__device__ __forceinline__ void bgc_inc_adjoint(const Grid& g, const Model& md, const double* __restrict__ yj,
+                                                const double* __restrict__ mu, int W, const ColumnRef& c, int slot,
+                                                double* ybar, double* ub) {
+    constexpr int NEU = kSubNeuMax;
+    const int m = md.member[slot];
+    const BgcParams p = load_params(md.u, md.model, md.nparam, m);
+    int ne;
+    const Euphotic<NEU> E = euphotic_from_memory<NEU>(g, md, p, m, c.nc, c.Q, ne);
+    const size_t tab = ((size_t)m * (g.nlayer + 1) + c.nc) * g.nlayer;
+    const double rho_k = md.rho[tab + c.k];
+    const double drho_k = md.drho[tab + c.k];
+    const double h = md.hsub;
+    double zc = 0.0;
+    for (int i = 0; i <= c.k; ++i) zc += g.dz[i];
+    zc -= 0.5 * g.dz[c.k];
+    double ye[NEU][NTR], ib[NEU][NTR], yk[NTR], mk[NTR], yb[NTR], u[NP];
+#pragma unroll
+    for (int e = 0; e < NEU; ++e) {
+        const size_t at = (size_t)(c.rs + (e < ne ? e : 0)) * W + slot * NTR;
+#pragma unroll
+        for (int t = 0; t < NTR; ++t) {
+            ye[e][t] = e < ne ? yj[at + t] : 0.0;
+            ib[e][t] = e < ne ? mu[at + t] : 0.0;
+        }
+    }
+    const size_t ak = (size_t)(c.rs + c.k) * W + slot * NTR;
+#pragma unroll
+    for (int t = 0; t < NTR; ++t) {
+        yk[t] = yj[ak + t];
+        mk[t] = mu[ak + t];
+        yb[t] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) u[q] = 0.0;
+    double pdeep = 0.0;
+    for (int kk = ne; kk < c.nc; ++kk) pdeep += (1.0 - p.sig) * md.rho[tab + kk] * mu[(size_t)(c.rs + kk) * W + slot * NTR];
+    double sphi = 0.0;
+    for (int s = md.nsub - 1; s >= 0; --s) {
+        double inc[NEU][NTR], ys[NEU][NTR];
+#pragma unroll
+        for (int t = 0; t < NTR; ++t)
+#pragma unroll
+            for (int e = 0; e < NEU; ++e) inc[e][t] = 0.0;
+        for (int r = 0; r < s; ++r) euphotic_step<NTR, NEU>(p, E, ye, h, inc);
+#pragma unroll
+        for (int e = 0; e < NEU; ++e)
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) ys[e][t] = ye[e][t] + inc[e][t];
+        sphi += euphotic_reverse<NTR, NEU, NP>(p, E, c.k, zc, rho_k, drho_k, pdeep, ys, h, ib, yb, u);
+    }
+    if (c.k >= ne) deep_reverse<NTR, NP>(p, deep_factors(p, h, md.nsub), md.nsub, h, rho_k, drho_k, sphi, yk, mk, yb, u);
+#pragma unroll
+    for (int t = 0; t < NTR; ++t) ybar[t] += yb[t];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) ub[q] += u[q];
+}
+
 // ---------------------------------------------------------------------------
 // Forward step (and its tangent).  One workgroup per tile; thread task =
 // (row, group of CW state columns).  Phase A: z = Ae(t_j) y + dt_d q(y) into
 // LDS.  Phase B: y_out = Ai(t_j) z from LDS.
 // ---------------------------------------------------------------------------
-template <int CW, bool TANGENT, int MAXR, int MAXC>
-__global__ void k_step(Grid g, Model md, Mats mt, int W, int tpr, int j, double dtd,
+template <int CW, bool TANGENT, int MAXR, int MAXC, bool SUB = false>
+__global__ __launch_bounds__(256) void k_step(Grid g, Model md, Mats mt, int W, int tpr, int j, double dtd,
                        const double* __restrict__ y, double* __restrict__ yo,
                        const double* __restrict__ v, double* __restrict__ vo) {
     extern __shared__ double s_dyn[];
@@ -353,20 +484,31 @@ __global__ void k_step(Grid g, Model md, Mats mt, int W, int tpr, int j, double 
             const int tr = wc % md.ntr;
             if (tr != 0 && cc != 0) continue;   // computed with its tracer-0 column
             const int slot = wc / md.ntr;
-            double q1, q2;
-            bgc_q(g, md, y, W, c, slot, q1, q2);
-            double qd1 = 0.0, qd2 = 0.0;
-            if (TANGENT) bgc_q_tangent(g, md, y, v, W, c, slot, qd1, qd2);
+            double q1, q2, qd1 = 0.0, qd2 = 0.0;
+            double sc = dtd;      // internal steps return the increment itself
+            if (SUB) {
+                double o[2] = {0.0, 0.0}, od[2] = {0.0, 0.0};
+                if (md.ntr == 2) bgc_inc<2, TANGENT>(g, md, y, v, W, c, slot, o, od);
+                else bgc_inc<1, TANGENT>(g, md, y, v, W, c, slot, o, od);
+                q1 = o[0];
+                q2 = o[1];
+                qd1 = od[0];
+                qd2 = od[1];
+                sc = 1.0;
+            } else {
+                bgc_q(g, md, y, W, c, slot, q1, q2);
+                if (TANGENT) bgc_q_tangent(g, md, y, v, W, c, slot, qd1, qd2);
+            }
             if (tr == 0) {
-                acc[cc] += dtd * q1;
-                if (TANGENT) accd[cc] += dtd * qd1;
+                acc[cc] += sc * q1;
+                if (TANGENT) accd[cc] += sc * qd1;
                 if (md.ntr > 1 && cc + 1 < CW && wc + 1 < W) {
-                    acc[cc + 1] += dtd * q2;
-                    if (TANGENT) accd[cc + 1] += dtd * qd2;
+                    acc[cc + 1] += sc * q2;
+                    if (TANGENT) accd[cc + 1] += sc * qd2;
                 }
             } else {   // first column of this thread is tracer 1 of its member
-                acc[cc] += dtd * q2;
-                if (TANGENT) accd[cc] += dtd * qd2;
+                acc[cc] += sc * q2;
+                if (TANGENT) accd[cc] += sc * qd2;
             }
         }
 #pragma unroll
@@ -427,7 +569,7 @@ __global__ void k_step(Grid g, Model md, Mats mt, int W, int tpr, int j, double 
 constexpr int kMembersWaves = 4;      // wavefronts (columns) per workgroup
 constexpr int kMembersEll = 8;        // Ae nonzeros per row supported by k_step_members
 
-template <int NTR, int KMAX, int EL>
+template <int NTR, int KMAX, int EL, bool SUB = false>
 __global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt, int ncol, int nb, int j,
                                                       double dtd, const double* __restrict__ y,
                                                       double* __restrict__ yo) {
@@ -502,6 +644,29 @@ __global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt,
         }
     }
 
+    // internal BGC steps (section 7): increments of the euphotic rows, the
+    // summed export and the decay factors for the rows below
+    double einc[NEU][NTR], sphi = 0.0;
+    DeepFactors DF{0.0, 0.0, 1.0};
+    if (SUB) {
+        static_assert(NEU == kSubNeuMax, "euphotic register width");
+        double ye[NEU][NTR], hz[NEU], re[NEU];
+#pragma unroll
+        for (int e = 0; e < NEU; ++e) {
+            const int ee = e < g.nlayer ? e : 0;
+            const int rr = rs + (e < nc ? e : nc - 1);
+            ye[e][0] = e < ne ? Ne[e] : 0.0;
+            if (NTR > 1) ye[e][NTR - 1] = e < ne ? y[(size_t)rr * W + me + NTR - 1] : 0.0;
+            hz[e] = g.dz[ee];
+            re[e] = md.rho[tab + ee];
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) einc[e][t] = 0.0;
+        }
+        const Euphotic<NEU> E = make_euphotic<NEU>(p, Q, ne, le, hz, re);
+        for (int s = 0; s < md.nsub; ++s) sphi += euphotic_step<NTR, NEU>(p, E, ye, md.hsub, einc);
+        DF = deep_factors(p, md.hsub, md.nsub);
+    }
+
     // z = Ae(t_j) y + dt_d q for every row of the column, in registers
     double z[KMAX][NTR];
 #pragma unroll
@@ -523,16 +688,30 @@ __global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt,
 #pragma unroll
             for (int t = 0; t < NTR; ++t) acc[t] += a * yv[sl][t];
         }
-        double fk = 0.0;
+        if (SUB) {
+            double src[NTR];
+            src[0] = md.hsub * (p.lam * dop * DF.G + (1.0 - p.sig) * rho * sphi);
+            if (NTR > 1) src[NTR - 1] = dop * DF.pm1;
 #pragma unroll
-        for (int e = 0; e < NEU; ++e)
-            if (e == k) fk = f[e];
-        const double q1 = -fk + p.lam * dop + (1.0 - p.sig) * Phi * rho;
-        const double z0 = acc[0] + dtd * q1;
-        z[k][0] = k < nc ? z0 : 0.0;
-        if (NTR > 1) {
-            const double z1 = acc[NTR - 1] + dtd * (p.sig * fk - p.lam * dop);
-            z[k][NTR - 1] = k < nc ? z1 : 0.0;
+            for (int e = 0; e < NEU; ++e)
+                if (e == k && e < ne) {
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) src[t] = einc[e][t];
+                }
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) z[k][t] = k < nc ? acc[t] + src[t] : 0.0;
+        } else {
+            double fk = 0.0;
+#pragma unroll
+            for (int e = 0; e < NEU; ++e)
+                if (e == k) fk = f[e];
+            const double q1 = -fk + p.lam * dop + (1.0 - p.sig) * Phi * rho;
+            const double z0 = acc[0] + dtd * q1;
+            z[k][0] = k < nc ? z0 : 0.0;
+            if (NTR > 1) {
+                const double z1 = acc[NTR - 1] + dtd * (p.sig * fk - p.lam * dop);
+                z[k][NTR - 1] = k < nc ? z1 : 0.0;
+            }
         }
     }
 
@@ -563,8 +742,8 @@ __global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt,
 // from the source alone; use_ai = false ends it, writing lambda_0.
 // Thread task = (row, member); NTR = tracers per member.
 // ---------------------------------------------------------------------------
-template <int NTR, int MAXR, int MAXC>
-__global__ void k_adjoint(Grid g, Model md, Mats mt, int W, int nb, int j, double dtd,
+template <int NTR, int MAXR, int MAXC, bool SUB = false>
+__global__ __launch_bounds__(256) void k_adjoint(Grid g, Model md, Mats mt, int W, int nb, int j, double dtd,
                           int use_ae, int use_ai, const double* __restrict__ mu,
                           const double* __restrict__ yj, const double* __restrict__ obs, double src_scale,
                           double* __restrict__ out, double* __restrict__ ubar_tile) {
@@ -612,55 +791,65 @@ __global__ void k_adjoint(Grid g, Model md, Mats mt, int W, int nb, int j, doubl
 #pragma unroll
                     for (int tr = 0; tr < NTR; ++tr) lam[tr] += a * mu[(size_t)col * W + slot * NTR + tr];
                 }
-                // (dq/dy)^T mu and (dq/du)^T mu for this row
-                const int m = md.member[slot];
-                const BgcParams p = load_params(md.u, md.model, md.nparam, m);
-                const double* light = md.light + (size_t)m * g.nlayer;
-                const size_t tab = ((size_t)m * (g.nlayer + 1) + c.nc) * g.nlayer;
-                const int ne = c.nc < g.neu ? c.nc : g.neu;
-                double Phi = 0.0;
-                for (int e = 0; e < ne; ++e) {
-                    const double N = yj[(size_t)(c.rs + e) * W + slot * NTR];
-                    Phi += g.dz[e] * production(p, N, c.Q, light[e]).f;
-                }
-                const size_t at = (size_t)r * W + slot * NTR;
-                const double mu1 = mu[at];
-                const double mu2 = NTR > 1 ? mu[at + 1] : 0.0;
-                const double dop = NTR > 1 ? yj[at + 1] : 0.0;
-                const double rho = md.rho[tab + c.k];
-                const double drho = md.drho[tab + c.k];
-                double ybar1 = 0.0, ybar2 = 0.0;
-                if (c.k < g.neu) {
-                    double Phibar = 0.0;
-                    for (int kk = 0; kk < c.nc; ++kk)
-                        Phibar += (1.0 - p.sig) * md.rho[tab + kk] * mu[(size_t)(c.rs + kk) * W + slot * NTR];
-                    const Production pr = production(p, yj[at], c.Q, light[c.k]);
-                    const double fbar = -mu1 + p.sig * mu2 + g.dz[c.k] * Phibar;
-                    ybar1 = fbar * pr.dfdN;
-                    // df/dalpha, df/dK_H2O, df/dK_1, df/dK_I
-                    const double Np = yj[at] > 0.0 ? yj[at] : 0.0;
-                    const double zc = [&] {
-                        double d = 0.0;
-                        for (int i = 0; i <= c.k; ++i) d += g.dz[i];
-                        return d - 0.5 * g.dz[c.k];
-                    }();
-                    const double IKI2 = (pr.I + p.ki) * (pr.I + p.ki);
-                    contrib[0] += fbar * pr.limN * pr.limI;
-                    contrib[1] += fbar * p.alpha * pr.limN * p.ki / IKI2 * (-zc * pr.I);
-                    contrib[2] += fbar * (-p.alpha * Np / ((Np + p.k1) * (Np + p.k1)) * pr.limI);
-                    contrib[3] += fbar * (-p.alpha * pr.limN * pr.I / IKI2);
-                    if (NTR > 1) contrib[5] += pr.f * mu2;
-                }
-                if (NTR > 1) {
-                    ybar2 = p.lam * (mu1 - mu2);
-                    contrib[4] += dop * (mu1 - mu2);
-                    contrib[5] += -Phi * rho * mu1;
-                    contrib[NP - 1] += (1.0 - p.sig) * Phi * drho * mu1;
-                    lam[1] += dtd * ybar2;
+                if (SUB) {
+                    // internal BGC steps: the reverse sweep returns h-weighted sums
+                    double yb[NTR];
+#pragma unroll
+                    for (int tr = 0; tr < NTR; ++tr) yb[tr] = 0.0;
+                    bgc_inc_adjoint<NTR, NP>(g, md, yj, mu, W, c, slot, yb, contrib);
+#pragma unroll
+                    for (int tr = 0; tr < NTR; ++tr) lam[tr] += yb[tr];
                 } else {
-                    contrib[NP - 1] += (1.0 - p.sig) * Phi * drho * mu1;
+                    // (dq/dy)^T mu and (dq/du)^T mu for this row
+                    const int m = md.member[slot];
+                    const BgcParams p = load_params(md.u, md.model, md.nparam, m);
+                    const double* light = md.light + (size_t)m * g.nlayer;
+                    const size_t tab = ((size_t)m * (g.nlayer + 1) + c.nc) * g.nlayer;
+                    const int ne = c.nc < g.neu ? c.nc : g.neu;
+                    double Phi = 0.0;
+                    for (int e = 0; e < ne; ++e) {
+                        const double N = yj[(size_t)(c.rs + e) * W + slot * NTR];
+                        Phi += g.dz[e] * production(p, N, c.Q, light[e]).f;
+                    }
+                    const size_t at = (size_t)r * W + slot * NTR;
+                    const double mu1 = mu[at];
+                    const double mu2 = NTR > 1 ? mu[at + 1] : 0.0;
+                    const double dop = NTR > 1 ? yj[at + 1] : 0.0;
+                    const double rho = md.rho[tab + c.k];
+                    const double drho = md.drho[tab + c.k];
+                    double ybar1 = 0.0, ybar2 = 0.0;
+                    if (c.k < g.neu) {
+                        double Phibar = 0.0;
+                        for (int kk = 0; kk < c.nc; ++kk)
+                            Phibar += (1.0 - p.sig) * md.rho[tab + kk] * mu[(size_t)(c.rs + kk) * W + slot * NTR];
+                        const Production pr = production(p, yj[at], c.Q, light[c.k]);
+                        const double fbar = -mu1 + p.sig * mu2 + g.dz[c.k] * Phibar;
+                        ybar1 = fbar * pr.dfdN;
+                        // df/dalpha, df/dK_H2O, df/dK_1, df/dK_I
+                        const double Np = yj[at] > 0.0 ? yj[at] : 0.0;
+                        const double zc = [&] {
+                            double d = 0.0;
+                            for (int i = 0; i <= c.k; ++i) d += g.dz[i];
+                            return d - 0.5 * g.dz[c.k];
+                        }();
+                        const double IKI2 = (pr.I + p.ki) * (pr.I + p.ki);
+                        contrib[0] += fbar * pr.limN * pr.limI;
+                        contrib[1] += fbar * p.alpha * pr.limN * p.ki / IKI2 * (-zc * pr.I);
+                        contrib[2] += fbar * (-p.alpha * Np / ((Np + p.k1) * (Np + p.k1)) * pr.limI);
+                        contrib[3] += fbar * (-p.alpha * pr.limN * pr.I / IKI2);
+                        if (NTR > 1) contrib[5] += pr.f * mu2;
+                    }
+                    if (NTR > 1) {
+                        ybar2 = p.lam * (mu1 - mu2);
+                        contrib[4] += dop * (mu1 - mu2);
+                        contrib[5] += -Phi * rho * mu1;
+                        contrib[NP - 1] += (1.0 - p.sig) * Phi * drho * mu1;
+                        lam[1] += dtd * ybar2;
+                    } else {
+                        contrib[NP - 1] += (1.0 - p.sig) * Phi * drho * mu1;
+                    }
+                    lam[0] += dtd * ybar1;
                 }
-                lam[0] += dtd * ybar1;
             }
             if (obs) {
                 const int lk = c.k;
@@ -692,7 +881,7 @@ __global__ void k_adjoint(Grid g, Model md, Mats mt, int W, int nb, int j, doubl
         }
     }
     if (ubar_tile && (int)threadIdx.x < nb * NP)
-        ubar_tile[(size_t)blockIdx.x * nb * NP + threadIdx.x] += dtd * ured;
+        ubar_tile[(size_t)blockIdx.x * nb * NP + threadIdx.x] += (SUB ? md.hsub : dtd) * ured;
     __syncthreads();
 
     // mu_{j-1} = Ai(t_{j-1})^T lambda_j, or lambda_j itself at the end

@@ -82,15 +82,118 @@ __device__ __forceinline__ void load_month(const Mats& mt, const Grid& g, int m,
         a[s] = s < nc ? mt.ai_rm[(size_t)m * mt.ai_month + blk + (size_t)k * nc + s] : 0.0;
 }
 
+// Source of the thread's row over one ocean step with md.nsub internal BGC
+// steps (section 7), from the domain's state in LDS: q = inc_nsub (and its
+// tangent qd).  light, hz, rho_e: the column's euphotic constants (at least
+// NEU entries, zero beyond ne).
+template <int NTR, bool TANGENT, int NEU, int TV>
+__device__ __forceinline__ void sub_source_lds(const Model& md, const BgcParams& p, double Q, int ne, int k, int lr0,
+                                               const double* light, const double* hz, const double* rho_e,
+                                               double rho_k, const double* s_y, const double* s_v,
+                                               const double (&yr)[NTR], const double (&vr)[TV], double (&q)[NTR],
+                                               double (&qd)[TV]) {
+    const Euphotic<NEU> E = make_euphotic<NEU>(p, Q, ne, light, hz, rho_e);
+    double ye[NEU][NTR], ve[NEU][NTR], vk[NTR];
+#pragma unroll
+    for (int e = 0; e < NEU; ++e) {
+        const int le = lr0 + (e < ne ? e : 0);
+#pragma unroll
+        for (int t = 0; t < NTR; ++t) {
+            ye[e][t] = e < ne ? s_y[le * NTR + t] : 0.0;
+            ve[e][t] = (TANGENT && e < ne) ? s_v[le * TV + t % TV] : 0.0;
+        }
+    }
+    if (TANGENT) {
+        double o[NTR];
+#pragma unroll
+        for (int t = 0; t < NTR; ++t) vk[t] = vr[t % TV];
+        row_source_tangent<NTR, NEU>(p, E, k, ye, ve, yr, vk, rho_k, md.hsub, md.nsub, q, o);
+#pragma unroll
+        for (int t = 0; t < NTR; ++t) qd[t % TV] = o[t];
+    } else {
+        row_source<NTR, NEU>(p, E, k, ye, yr, rho_k, md.hsub, md.nsub, q);
+    }
+}
+
+// Reverse of the internal BGC steps for the thread's row (section 7 with the
+// adjoint of section 6).  The euphotic internal steps are first run forward,
+// the thread of each euphotic row storing its row's state at every internal
+// step in s_traj ([nsub][TPB][NTR], dynamic LDS); after a barrier each thread
+// replays the reverse steps of its column's euphotic rows from there.
+// Returns ybar = the h-weighted sum of (dq/dy)^T mu for the row and adds the
+// unscaled (dq/du)^T mu sums to ub.  Every thread of the workgroup must call
+// this.
+template <int NTR, int NEU, int NP, int TPB>
+__device__ __forceinline__ void sub_adjoint_lds(const Model& md, const BgcParams& p, double Q, int tid, int k, int nc,
+                                                int ne, int lr0, size_t tab, double zc, const double* light,
+                                                const double* hz, const double* rho_e, double rho_k, double drho_k,
+                                                const double* s_y, const double* s_mu, double* s_traj,
+                                                const double (&yj)[NTR], const double (&mr)[NTR],
+                                                double (&ybar)[NTR], double (&ub)[NP]) {
+    const double h = md.hsub;
+    const int nsub = md.nsub;
+    const Euphotic<NEU> E = make_euphotic<NEU>(p, Q, ne, light, hz, rho_e);
+    double ye[NEU][NTR];
+#pragma unroll
+    for (int e = 0; e < NEU; ++e) {
+        const int le = lr0 + (e < ne ? e : 0);
+#pragma unroll
+        for (int t = 0; t < NTR; ++t) ye[e][t] = e < ne ? s_y[le * NTR + t] : 0.0;
+    }
+    {
+        double inc[NEU][NTR];
+#pragma unroll
+        for (int t = 0; t < NTR; ++t)
+#pragma unroll
+            for (int e = 0; e < NEU; ++e) inc[e][t] = 0.0;
+        for (int s = 0; s < nsub; ++s) {
+#pragma unroll
+            for (int e = 0; e < NEU; ++e)
+                if (e == k && e < ne) {
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) s_traj[((size_t)s * TPB + tid) * NTR + t] = ye[e][t] + inc[e][t];
+                }
+            euphotic_step<NTR, NEU>(p, E, ye, h, inc);
+        }
+    }
+    __syncthreads();
+    double ib[NEU][NTR];
+#pragma unroll
+    for (int e = 0; e < NEU; ++e) {
+        const int le = lr0 + (e < ne ? e : 0);
+#pragma unroll
+        for (int t = 0; t < NTR; ++t) ib[e][t] = e < ne ? s_mu[le * NTR + t] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NTR; ++t) ybar[t] = 0.0;
+    double pdeep = 0.0;
+    for (int kk = ne; kk < nc; ++kk) pdeep += (1.0 - p.sig) * md.rho[tab + kk] * s_mu[(lr0 + kk) * NTR];
+    double sphi = 0.0;
+    for (int s = nsub - 1; s >= 0; --s) {
+        double ys[NEU][NTR];
+#pragma unroll
+        for (int e = 0; e < NEU; ++e) {
+            const int le = lr0 + (e < ne ? e : 0);
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) ys[e][t] = e < ne ? s_traj[((size_t)s * TPB + le) * NTR + t] : 0.0;
+        }
+        sphi += euphotic_reverse<NTR, NEU, NP>(p, E, k, zc, rho_k, drho_k, pdeep, ys, h, ib, ybar, ub);
+    }
+    if (k >= ne) deep_reverse<NTR, NP>(p, deep_factors(p, h, nsub), nsub, h, rho_k, drho_k, sphi, yj, mr, ybar, ub);
+}
+
 // NTR tracers of one member; TANGENT also steps v = phi'(y) direction; TPB
-// threads per workgroup = maximum rows per domain.
-template <int NTR, bool TANGENT, int KMAX, int TPB>
+// threads per workgroup = maximum rows per domain; SN = 0 for one BGC
+// evaluation per step, else internal BGC steps with SN >= neu euphotic rows
+// held in registers.
+template <int NTR, bool TANGENT, int KMAX, int TPB, int SN = 0>
 __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     Grid g, Model md, Mats mt, Persist ps, StepRange sr, double dtd, const double* __restrict__ y_in,
     double* __restrict__ y_out, double* __restrict__ buf0, double* __restrict__ buf1,
     const double* __restrict__ v_in, double* __restrict__ v_out, double* __restrict__ vbuf0,
     double* __restrict__ vbuf1) {
     constexpr int TV = TANGENT ? NTR : 1;
+    constexpr bool SUB = SN > 0;
     __shared__ double s_red[TPB];
     __shared__ short s_rowcol[TPB];
     __shared__ short s_rowk[TPB];
@@ -135,11 +238,12 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     const BgcParams p = load_params(md.u, md.model, md.nparam, m);
     const double rho = md.rho[((size_t)m * (g.nlayer + 1) + nc) * g.nlayer + k];
     const int ne = nc < g.neu ? nc : g.neu;
-    double light[kNeuMax], hz[kNeuMax];
+    double light[kNeuMax], hz[kNeuMax], rho_e[kNeuMax];
 #pragma unroll
     for (int e = 0; e < kNeuMax; ++e) {
         light[e] = e < ne ? md.light[(size_t)m * g.nlayer + e] : 0.0;
         hz[e] = e < ne ? g.dz[e] : 0.0;
+        rho_e[e] = (SUB && e < ne) ? md.rho[((size_t)m * (g.nlayer + 1) + nc) * g.nlayer + e] : 0.0;
     }
 
     RowMats<KMAX> R;
@@ -197,7 +301,12 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
 
         // sources from the domain's own rows (no wait needed)
         double q[NTR], qd[TV];
-        {
+        double sc = dtd;        // internal steps return the increment itself
+        if (SUB) {
+            sc = 1.0;
+            sub_source_lds<NTR, TANGENT, (SUB ? SN : 1), TV>(md, p, Q, ne, k, lr0, light, hz, rho_e, rho, s_y, s_v,
+                                                             yr, vr, q, qd);
+        } else {
             double Phi = 0.0, fk = 0.0, Phid = 0.0, fdk = 0.0;
 #pragma unroll
             for (int e = 0; e < kNeuMax; ++e) {
@@ -275,8 +384,8 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             }
 #pragma unroll
             for (int t = 0; t < NTR; ++t) {
-                s_z[tid * NTR + t] = acc[t] + dtd * q[t];
-                if (TANGENT) s_zd[tid * TV + t % TV] = accd[t % TV] + dtd * qd[t % TV];
+                s_z[tid * NTR + t] = acc[t] + sc * q[t];
+                if (TANGENT) s_zd[tid * TV + t % TV] = accd[t % TV] + sc * qd[t % TV];
             }
         }
         __syncthreads();
@@ -354,13 +463,14 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
 // y_j of the segment comes from ystore (slot j - j_lo).  Parameter-gradient
 // sums are reduced per domain at the end and added to ubar_dom[domain][p].
 // ---------------------------------------------------------------------------
-template <int NTR, int KMAX, int TPB>
+template <int NTR, int KMAX, int TPB, int SN = 0>
 __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     Grid g, Model md, Mats mt, Persist ps, double dtd, int j_lo, int j_hi,
     const double* __restrict__ ystore, const double* __restrict__ obs, double src_scale,
     const double* __restrict__ mu_in, double* __restrict__ mu_out, double* __restrict__ buf0,
     double* __restrict__ buf1, double* __restrict__ ubar_dom) {
     constexpr int NP = NTR == 2 ? 7 : 5;
+    constexpr bool SUB = SN > 0;
     __shared__ short s_rowcol[TPB];
     __shared__ short s_rowk[TPB];
     __shared__ short s_colr0[TPB];
@@ -370,6 +480,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     __shared__ double s_lam[TPB * NTR];
     __shared__ double s_red[TPB];
     __shared__ int s_fail;
+    extern __shared__ double s_traj[];   // internal-step states [nsub][TPB][NTR] (SUB only)
 
     const int tid = threadIdx.x;
     const int d = ps.block_dom[blockIdx.x];
@@ -408,11 +519,12 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     const double rho = md.rho[tab + k];
     const double drho = md.drho[tab + k];
     const int ne = nc < g.neu ? nc : g.neu;
-    double light[kNeuMax], hz[kNeuMax];
+    double light[kNeuMax], hz[kNeuMax], rho_e[kNeuMax];
 #pragma unroll
     for (int e = 0; e < kNeuMax; ++e) {
         light[e] = e < ne ? md.light[(size_t)m * g.nlayer + e] : 0.0;
         hz[e] = e < ne ? g.dz[e] : 0.0;
+        rho_e[e] = (SUB && e < ne) ? md.rho[tab + e] : 0.0;
     }
     double zc = 0.0;   // centre depth of the row's layer
     for (int i = 0; i <= k; ++i) zc += g.dz[i];
@@ -493,7 +605,10 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
 
         // (dq/dy)^T mu_j and (dq/du)^T mu_j from the own water column
         double ybar[NTR];
-        {
+        if (SUB) {
+            sub_adjoint_lds<NTR, (SUB ? SN : 1), NP, TPB>(md, p, Q, tid, k, nc, ne, lr0, tab, zc, light, hz, rho_e,
+                                                          rho, drho, s_y, s_mu, s_traj, yj, mr, ybar, ub);
+        } else {
             double Phi = 0.0;
 #pragma unroll
             for (int e = 0; e < kNeuMax; ++e)
@@ -567,7 +682,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
             }
 #pragma unroll
             for (int t = 0; t < NTR; ++t) {
-                lam[t] += dtd * ybar[t];
+                lam[t] += (SUB ? 1.0 : dtd) * ybar[t];
                 if (mo >= 0) lam[t] += vol * (yj[t] - obs[(size_t)mo * state_len + (size_t)r * NTR + t]) * src_scale;
                 s_lam[tid * NTR + t] = lam[t];
             }
@@ -613,7 +728,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
             if (tid < hh) s_red[tid] += s_red[tid + hh];
             __syncthreads();
         }
-        if (tid == 0) ubar_dom[(size_t)d * NP + q] += dtd * s_red[0];
+        if (tid == 0) ubar_dom[(size_t)d * NP + q] += (SUB ? md.hsub : dtd) * s_red[0];
         __syncthreads();
     }
 }

@@ -29,6 +29,7 @@ TMM_Q_PERSISTENT = 1
 TMM_Q_DOMAINS = 2
 TMM_Q_WORKSPACE = 3
 TMM_Q_COMPUTE_UNITS = 4
+TMM_Q_PERSISTENT_ADJOINT = 5
 
 EXPORTED = (
     "tmm_workspace_bytes", "tmm_create", "tmm_destroy", "tmm_set_params", "tmm_step", "tmm_year",
@@ -45,7 +46,7 @@ class TmmDesc(C.Structure):
     _fields_ = [
         ("n", C.c_int), ("ncol", C.c_int), ("nlayer", C.c_int),
         ("col_start", _ip), ("lat", _dp), ("area", _dp), ("dz", _dp),
-        ("nmat", C.c_int), ("nstep", C.c_int), ("model", C.c_int), ("neuphotic", C.c_int),
+        ("nmat", C.c_int), ("nstep", C.c_int), ("model", C.c_int), ("neuphotic", C.c_int), ("nbgc", C.c_int),
         ("nbatch_max", C.c_int), ("adjoint_nbatch_max", C.c_int), ("ckpt_every", C.c_int),
         ("ae_nnz", C.c_int), ("ae_rowptr", _ip), ("ae_colidx", _ip), ("ae_val", _dp),
         ("ai_nnz", C.c_int), ("ai_rowptr", _ip), ("ai_colidx", _ip), ("ai_val", _dp),
@@ -200,7 +201,7 @@ class TMM:
         dp = lambda x: x.ctypes.data_as(_dp)  # noqa: E731
         self.desc = TmmDesc(
             self.n, int(a["ncol"]), int(a["nlayer"]), ip(k["col_start"]), dp(k["lat"]), dp(k["area"]), dp(k["dz"]),
-            self.nmat, self.nstep, self.model, int(a["neuphotic"]),
+            self.nmat, self.nstep, self.model, int(a["neuphotic"]), int(a.get("nbgc", 1)),
             int(nbatch_max), int(adjoint_nbatch_max), int(ckpt_every),
             k["ae_colidx"].size, ip(k["ae_rowptr"]), ip(k["ae_colidx"]), dp(k["ae_val"]),
             k["ai_colidx"].size, ip(k["ai_rowptr"]), ip(k["ai_colidx"]), dp(k["ai_val"]),

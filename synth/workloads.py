@@ -28,6 +28,7 @@ class Inputs:
     model: int
     neuphotic: int
     y_init: tuple          # constant initial value per tracer
+    nbgc: int = 1          # internal BGC steps per ocean step (section 7)
 
     @property
     def n(self):
@@ -63,7 +64,7 @@ class Inputs:
             lat=np.ascontiguousarray(g.lat, dtype=np.float64),
             area=np.ascontiguousarray(g.area, dtype=np.float64),
             dz=np.ascontiguousarray(g.dz, dtype=np.float64),
-            nmat=t.nmat, nstep=t.nstep, model=self.model, neuphotic=self.neuphotic,
+            nmat=t.nmat, nstep=t.nstep, model=self.model, neuphotic=self.neuphotic, nbgc=self.nbgc,
             ae_rowptr=t.ae_rowptr, ae_colidx=t.ae_colidx, ae_val=np.ascontiguousarray(t.ae_val),
             ai_rowptr=t.ai_rowptr, ai_colidx=t.ai_colidx, ai_val=np.ascontiguousarray(t.ai_val),
         )

@@ -37,7 +37,8 @@ def _desc(inp, **over):
     ip = lambda x: x.ctypes.data_as(C.POINTER(C.c_int))  # noqa: E731
     dp = lambda x: x.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
     d = tmm.TmmDesc(a["n"], a["ncol"], a["nlayer"], ip(keep["col_start"]), dp(keep["lat"]), dp(keep["area"]),
-                    dp(keep["dz"]), a["nmat"], a["nstep"], a["model"], a["neuphotic"], over.get("nbatch_max", 1),
+                    dp(keep["dz"]), a["nmat"], a["nstep"], a["model"], a["neuphotic"], a.get("nbgc", 1),
+                    over.get("nbatch_max", 1),
                     over.get("adjoint_nbatch_max", 1), over.get("ckpt_every", 240),
                     keep["ae_colidx"].size, ip(keep["ae_rowptr"]), ip(keep["ae_colidx"]), dp(keep["ae_val"]),
                     keep["ai_colidx"].size, ip(keep["ai_rowptr"]), ip(keep["ai_colidx"]), dp(keep["ai_val"]))
@@ -66,11 +67,22 @@ def test_invalid_descriptors_are_rejected(tiny_n):
     cross[0] = tiny_n.grid.col_start[1]                                   # couples two columns
     for over in ({"ae_rowptr": bad_rowptr}, {"ae_colidx": bad_col}, {"ai_colidx": cross},
                  {"nstep": 2876}, {"nmat": 7}, {"model": 3}, {"neuphotic": 0},
-                 {"ckpt_every": 7}, {"nbatch_max": 0}, {"adjoint_nbatch_max": 2},
+                 {"ckpt_every": 7}, {"nbatch_max": 0}, {"adjoint_nbatch_max": 2}, {"nbgc": -1}, {"nbgc": 17},
                  {"dz": np.r_[tiny_n.grid.dz[:-1], -1.0]}):
         d, _ = _desc(tiny_n, **over)
         rc, _ = _status(d)
         assert rc == -1, over
+
+
+def test_internal_bgc_steps_in_descriptor(small_ndop):
+    """0/1 = one evaluation; up to 16 internal steps; more than 4 euphotic layers only without them."""
+    for nbgc in (0, 1, 8, 16):
+        d, _ = _desc(small_ndop, nbgc=nbgc)
+        assert _status(d)[0] == 0, nbgc
+    d, _ = _desc(small_ndop, nbgc=8, neuphotic=5)
+    assert _status(d)[0] == -6
+    d, _ = _desc(small_ndop, nbgc=1, neuphotic=5)
+    assert _status(d)[0] == 0
 
 
 def test_strerror():

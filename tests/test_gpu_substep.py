@@ -1,0 +1,190 @@
+"""GPU parity with internal BGC steps per ocean step (section 7; 8 in the paper's experiments).
+
+Every kernel path of libtmm runs with nbgc = 8 against the oracle with the
+same nbgc: the tile step kernel, the single-launch year kernel, the
+member-parallel ensemble kernel, both tangents, and the persistent and tile
+adjoints.  Tolerances as for one evaluation per step: one step 1e-14, one
+model year 1e-12, tangent 1e-11, adjoint 1e-10 relative to the largest value.
+"""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+NBGC = 8
+
+
+def _tmm():
+    from paper_1410_0204_amd import tmm
+    return tmm
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def inputs():
+    return {"tiny_n": dataclasses.replace(synth.tiny(), nbgc=NBGC),
+            "tiny_ndop": dataclasses.replace(synth.tiny(model=synth.MODEL_NDOP), nbgc=NBGC),
+            "small": dataclasses.replace(synth.small_ndop(), nbgc=NBGC)}
+
+
+def _make(inp, nbatch_max=1, adjoint=0, ckpt=240):
+    print(f"[gpu] create {inp.name} nbgc={inp.nbgc} nbatch_max={nbatch_max} adjoint={adjoint}", flush=True)
+    return _tmm().TMM(inp.desc_arrays(), nbatch_max=nbatch_max, adjoint_nbatch_max=adjoint, ckpt_every=ckpt)
+
+
+@pytest.mark.parametrize("name", ["tiny_n", "tiny_ndop", "small"])
+def test_substep_step_parity(inputs, name):
+    inp = inputs[name]
+    t = _make(inp)
+    o = oracle.Oracle(inp)
+    assert o.nbgc == NBGC
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    rng = np.random.default_rng(11)
+    y = inp.initial_state() * rng.uniform(0.5, 1.5, size=(inp.n, inp.ntracer))
+    for j in (0, 119, 1439, 2879):
+        got = t.step(j, t.state(y)).cpu().numpy()
+        exp = o.step(u, j, y)
+        assert _rel(got, exp) <= 1e-14, j
+    # the internal steps change the result (against one evaluation per step)
+    plain = oracle.Oracle(inp, nbgc=1).step(u, 0, y)
+    assert _rel(plain, exp) > 1e-12 or inp.model == synth.MODEL_N
+
+
+@pytest.mark.parametrize("persistent", [1, 0])
+@pytest.mark.parametrize("name", ["tiny_n", "tiny_ndop", "small"])
+def test_substep_year_parity(inputs, name, persistent):
+    tmm = _tmm()
+    inp = inputs[name]
+    t = _make(inp)
+    t.set_option(tmm.TMM_OPT_PERSISTENT, persistent)
+    o = oracle.Oracle(inp)
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    y0 = inp.initial_state()
+    got, r = t.year(t.state(y0), nyears=2)
+    exp, re = o.year(u, y0, 2)
+    assert _rel(got.cpu().numpy(), exp) <= 1e-12
+    assert np.allclose(r, re, rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("nb,nsteps", [(20, 2880), (70, 12)])
+def test_substep_member_kernel(inputs, nb, nsteps):
+    tmm = _tmm()
+    inp = inputs["small"]
+    U = synth.latin_hypercube(synth.MODEL_NDOP, nb, seed=40 + nb)
+    t = _make(inp, nbatch_max=nb)
+    t.set_option(tmm.TMM_OPT_MEMBER_KERNEL_MIN, 1)
+    o = oracle.Oracle(inp)
+    t.set_params(U)
+    rng = np.random.default_rng(nb)
+    y0 = inp.initial_state(nb) * rng.uniform(0.7, 1.3, size=(inp.n, 2 * nb))
+    if nsteps == 2880:
+        got, _ = t.year(t.state(y0))
+        exp, _ = o.year(U, y0)
+        assert _rel(got.cpu().numpy(), exp) <= 1e-12
+    else:
+        yd, ye = t.state(y0), y0
+        for j in range(nsteps):
+            yd = t.step(j * 239 % 2880, yd)
+            ye = o.step(U, j * 239 % 2880, ye)
+            assert _rel(yd.cpu().numpy(), ye) <= 1e-13, j
+
+
+@pytest.mark.parametrize("persistent", [1, 0])
+def test_substep_tangent(inputs, persistent):
+    tmm = _tmm()
+    inp = inputs["small"]
+    t = _make(inp)
+    t.set_option(tmm.TMM_OPT_PERSISTENT, persistent)
+    o = oracle.Oracle(inp)
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    rng = np.random.default_rng(13)
+    y = inp.initial_state() * rng.uniform(0.8, 1.2, size=(inp.n, 2))
+    v = rng.standard_normal(y.shape) * y
+    phi, jv = t.year_jvp(t.state(y), t.state(v), mode=tmm.TMM_JVP_TANGENT)
+    ephi, ejv = o.year_tangent(u, y, v)
+    assert _rel(phi.cpu().numpy(), ephi) <= 1e-12
+    assert _rel(jv.cpu().numpy(), ejv) <= 1e-11
+
+
+@pytest.mark.parametrize("persistent", [1, 0])
+@pytest.mark.parametrize("name,ckpt", [("tiny_n", 240), ("tiny_ndop", 240), ("small", 480)])
+def test_substep_adjoint(inputs, name, ckpt, persistent):
+    import torch
+    tmm = _tmm()
+    inp = inputs[name]
+    o = oracle.Oracle(inp)
+    y0 = inp.initial_state()
+    snaps = o.snapshots(synth.hidden_params(inp.model, seed=21), y0)
+    obs = snaps * (1 + 0.05 * synth.obs_noise(snaps.shape, seed=22))
+    u = synth.nominal(inp.model)
+    eJ, eG, eY = o.year_adjoint(u, y0, obs)
+    t = _make(inp, adjoint=1, ckpt=ckpt)
+    t.set_option(tmm.TMM_OPT_PERSISTENT, persistent)
+    if persistent:
+        assert t.query(tmm.TMM_Q_PERSISTENT_ADJOINT) == 1
+    t.set_params(u)
+    J, G, dy0 = t.year_adjoint(t.state(y0), torch.as_tensor(obs).cuda())
+    assert J[0] == pytest.approx(eJ[0], rel=1e-12)
+    assert _rel(G, eG) <= 1e-10
+    assert _rel(dy0.cpu().numpy(), eY) <= 1e-10
+
+
+def test_substep_ensemble_adjoint(inputs):
+    """Two members through the tile adjoint (one launch per step, internal steps replayed per thread)."""
+    import torch
+    inp = inputs["tiny_ndop"]
+    U = synth.latin_hypercube(synth.MODEL_NDOP, 2, seed=3)
+    o = oracle.Oracle(inp)
+    y0 = inp.initial_state(2)
+    snaps = o.snapshots(synth.hidden_params(inp.model, seed=21), inp.initial_state())
+    obs1 = snaps * (1 + 0.05 * synth.obs_noise(snaps.shape, seed=22))
+    obs = np.concatenate([obs1, obs1 * 1.01], axis=2)
+    eJ, eG, eY = o.year_adjoint(U, y0, obs)
+    t = _make(inp, nbatch_max=2, adjoint=2)
+    t.set_params(U)
+    J, G, dy0 = t.year_adjoint(t.state(y0), torch.as_tensor(obs).cuda())
+    assert np.allclose(J, eJ, rtol=1e-12, atol=0)
+    assert _rel(G, eG) <= 1e-10
+    assert _rel(dy0.cpu().numpy(), eY) <= 1e-10
+
+
+def test_substep_global_year():
+    """Full size: one model year of the global grid with 8 internal steps (single-launch kernel)."""
+    tmm = _tmm()
+    inp = dataclasses.replace(synth.global_2p8(), nbgc=NBGC)
+    t = _make(inp)
+    assert t.query(tmm.TMM_Q_PERSISTENT) == 1
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    y0 = inp.initial_state()
+    got, _ = t.year(t.state(y0))
+    print("[gpu] oracle year, global grid, 8 internal steps (~40 s)", flush=True)
+    exp, _ = oracle.Oracle(inp).year(u, y0)
+    assert _rel(got.cpu().numpy(), exp) <= 1e-12
+
+
+def test_substep_ensemble_full_size_step():
+    """Full size: one step of 64 members on the 256x128x23 grid (member-parallel kernel)."""
+    inp = dataclasses.replace(synth.ensemble_1p4(), nbgc=NBGC)
+    nm = 64
+    U = synth.latin_hypercube(synth.MODEL_NDOP, nm, seed=17)
+    t = _make(inp, nbatch_max=nm)
+    t.set_params(U)
+    rng = np.random.default_rng(5)
+    y = inp.initial_state(nm) * rng.uniform(0.8, 1.2, size=(inp.n, 2 * nm))
+    got = t.step(1439, t.state(y)).cpu().numpy()
+    print("[gpu] oracle step, 64 members on the 256x128x23 grid (~30 s)", flush=True)
+    exp = oracle.Oracle(inp).step(U, 1439, y)
+    assert _rel(got, exp) <= 1e-14

@@ -407,6 +407,7 @@ __device__ __forceinline__ void bgc_inc_adjoint(const Grid& g, const Model& md, 
     double pdeep = 0.0;
     for (int kk = ne; kk < c.nc; ++kk) pdeep += (1.0 - p.sig) * md.rho[tab + kk] * mu[(size_t)(c.rs + kk) * W + slot * NTR];
     double sphi = 0.0;
+    EuphoticAdj acc{0.0, 0.0, 0.0, 0.0, 0.0};
     for (int s = md.nsub - 1; s >= 0; --s) {
         double inc[NEU][NTR], ys[NEU][NTR];
 #pragma unroll
@@ -418,9 +419,10 @@ __device__ __forceinline__ void bgc_inc_adjoint(const Grid& g, const Model& md, 
         for (int e = 0; e < NEU; ++e)
 #pragma unroll
             for (int t = 0; t < NTR; ++t) ys[e][t] = ye[e][t] + inc[e][t];
-        sphi += euphotic_reverse<NTR, NEU, NP>(p, E, c.k, zc, rho_k, drho_k, pdeep, ys, h, ib, yb, u);
+        sphi += euphotic_reverse<NTR, NEU>(p, E, c.k, rho_k, pdeep, ys, h, ib, yb, acc);
     }
     if (c.k >= ne) deep_reverse<NTR, NP>(p, deep_factors(p, h, md.nsub), md.nsub, h, rho_k, drho_k, sphi, yk, mk, yb, u);
+    else euphotic_adj_finish<NTR, NEU, NP>(p, E, c.k, zc, drho_k, acc, u);
 #pragma unroll
     for (int t = 0; t < NTR; ++t) ybar[t] += yb[t];
 #pragma unroll

@@ -115,71 +115,121 @@ __device__ __forceinline__ void sub_source_lds(const Model& md, const BgcParams&
     }
 }
 
-// Reverse of the internal BGC steps for the thread's row (section 7 with the
-// adjoint of section 6).  The euphotic internal steps are first run forward,
-// the thread of each euphotic row storing its row's state at every internal
-// step in s_traj ([nsub][TPB][NTR], dynamic LDS); after a barrier each thread
-// replays the reverse steps of its column's euphotic rows from there.
-// Returns ybar = the h-weighted sum of (dq/dy)^T mu for the row and adds the
-// unscaled (dq/du)^T mu sums to ub.  Every thread of the workgroup must call
-// this.
+// Reverse of the internal BGC steps (section 7 with the adjoint of section
+// 6) for the domain's rows.  Phase 1, one thread per water column: the
+// column's euphotic rows are run forward over the internal steps (their
+// states kept in s_traj, [nsub][TPB][NTR] by row, dynamic LDS) and then
+// reversed; each euphotic row's h-weighted (dq/dy)^T mu goes to s_yb, its
+// parameter sums to s_acc, the column's summed export to s_sphi.  Phase 2,
+// one thread per row: a euphotic row takes its results, a row below the
+// euphotic zone uses the summed export and the decay factors.  Only about
+// one wavefront works in phase 1, instead of every row thread repeating its
+// column's internal steps.  Returns ybar of the thread's row and adds its
+// unscaled (dq/du)^T mu to ub.  Every thread of the workgroup must call this.
 template <int NTR, int NEU, int NP, int TPB>
-__device__ __forceinline__ void sub_adjoint_lds(const Model& md, const BgcParams& p, double Q, int tid, int k, int nc,
-                                                int ne, int lr0, size_t tab, double zc, const double* light,
-                                                const double* hz, const double* rho_e, double rho_k, double drho_k,
-                                                const double* s_y, const double* s_mu, double* s_traj,
+__device__ __forceinline__ void sub_adjoint_lds(const Grid& g, const Model& md, const BgcParams& p, int m, int j,
+                                                int c0, int ncols, const short* s_colr0, const short* s_colnc,
+                                                int tid, int k, int ne, int lc, size_t tab, double zc, double rho_k,
+                                                double drho_k, const double* s_y, const double* s_mu,
+                                                double* s_traj, double* s_yb, double* s_acc, double* s_sphi,
                                                 const double (&yj)[NTR], const double (&mr)[NTR],
                                                 double (&ybar)[NTR], double (&ub)[NP]) {
     const double h = md.hsub;
     const int nsub = md.nsub;
-    const Euphotic<NEU> E = make_euphotic<NEU>(p, Q, ne, light, hz, rho_e);
-    double ye[NEU][NTR];
-#pragma unroll
-    for (int e = 0; e < NEU; ++e) {
-        const int le = lr0 + (e < ne ? e : 0);
-#pragma unroll
-        for (int t = 0; t < NTR; ++t) ye[e][t] = e < ne ? s_y[le * NTR + t] : 0.0;
-    }
-    {
-        double inc[NEU][NTR];
-#pragma unroll
-        for (int t = 0; t < NTR; ++t)
-#pragma unroll
-            for (int e = 0; e < NEU; ++e) inc[e][t] = 0.0;
-        for (int s = 0; s < nsub; ++s) {
-#pragma unroll
-            for (int e = 0; e < NEU; ++e)
-                if (e == k && e < ne) {
-#pragma unroll
-                    for (int t = 0; t < NTR; ++t) s_traj[((size_t)s * TPB + tid) * NTR + t] = ye[e][t] + inc[e][t];
-                }
-            euphotic_step<NTR, NEU>(p, E, ye, h, inc);
-        }
-    }
-    __syncthreads();
-    double ib[NEU][NTR];
-#pragma unroll
-    for (int e = 0; e < NEU; ++e) {
-        const int le = lr0 + (e < ne ? e : 0);
-#pragma unroll
-        for (int t = 0; t < NTR; ++t) ib[e][t] = e < ne ? s_mu[le * NTR + t] : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < NTR; ++t) ybar[t] = 0.0;
-    double pdeep = 0.0;
-    for (int kk = ne; kk < nc; ++kk) pdeep += (1.0 - p.sig) * md.rho[tab + kk] * s_mu[(lr0 + kk) * NTR];
-    double sphi = 0.0;
-    for (int s = nsub - 1; s >= 0; --s) {
-        double ys[NEU][NTR];
+    if (tid < ncols) {
+        const int r0q = s_colr0[tid];
+        const int ncq = s_colnc[tid];
+        const int neq = ncq < g.neu ? ncq : g.neu;
+        const double Q = g.ins[(size_t)j * g.nlat + g.col_lat[c0 + tid]];
+        const size_t tabq = ((size_t)m * (g.nlayer + 1) + ncq) * g.nlayer;
+        double light[NEU], hz[NEU], rho[NEU];
 #pragma unroll
         for (int e = 0; e < NEU; ++e) {
-            const int le = lr0 + (e < ne ? e : 0);
-#pragma unroll
-            for (int t = 0; t < NTR; ++t) ys[e][t] = e < ne ? s_traj[((size_t)s * TPB + le) * NTR + t] : 0.0;
+            const int ee = e < neq ? e : 0;
+            light[e] = md.light[(size_t)m * g.nlayer + ee];
+            hz[e] = g.dz[ee];
+            rho[e] = md.rho[tabq + ee];
         }
-        sphi += euphotic_reverse<NTR, NEU, NP>(p, E, k, zc, rho_k, drho_k, pdeep, ys, h, ib, ybar, ub);
+        const Euphotic<NEU> E = make_euphotic<NEU>(p, Q, neq, light, hz, rho);
+        double ye[NEU][NTR], ib[NEU][NTR], yb[NEU][NTR];
+        EuphoticAdj acc[NEU];
+#pragma unroll
+        for (int e = 0; e < NEU; ++e) {
+            const int le = r0q + (e < neq ? e : 0);
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) {
+                ye[e][t] = e < neq ? s_y[le * NTR + t] : 0.0;
+                ib[e][t] = e < neq ? s_mu[le * NTR + t] : 0.0;
+                yb[e][t] = 0.0;
+            }
+            acc[e] = EuphoticAdj{0.0, 0.0, 0.0, 0.0, 0.0};
+        }
+        {
+            double inc[NEU][NTR];
+#pragma unroll
+            for (int e = 0; e < NEU; ++e)
+#pragma unroll
+                for (int t = 0; t < NTR; ++t) inc[e][t] = 0.0;
+            for (int s = 0; s < nsub; ++s) {
+#pragma unroll
+                for (int e = 0; e < NEU; ++e)
+                    if (e < neq) {
+#pragma unroll
+                        for (int t = 0; t < NTR; ++t)
+                            s_traj[((size_t)s * TPB + r0q + e) * NTR + t] = ye[e][t] + inc[e][t];
+                    }
+                euphotic_step<NTR, NEU>(p, E, ye, h, inc);
+            }
+        }
+        double pdeep = 0.0;
+        for (int kk = neq; kk < ncq; ++kk) pdeep += (1.0 - p.sig) * md.rho[tabq + kk] * s_mu[(r0q + kk) * NTR];
+        double sphi = 0.0;
+        for (int s = nsub - 1; s >= 0; --s) {
+            double ys[NEU][NTR];
+#pragma unroll
+            for (int e = 0; e < NEU; ++e) {
+                const int le = r0q + (e < neq ? e : 0);
+#pragma unroll
+                for (int t = 0; t < NTR; ++t) ys[e][t] = e < neq ? s_traj[((size_t)s * TPB + le) * NTR + t] : 0.0;
+            }
+            sphi += euphotic_reverse_rows<NTR, NEU>(p, E, pdeep, ys, h, ib, yb, acc);
+        }
+#pragma unroll
+        for (int e = 0; e < NEU; ++e)
+            if (e < neq) {
+                const int le = r0q + e;
+#pragma unroll
+                for (int t = 0; t < NTR; ++t) s_yb[le * NTR + t] = yb[e][t];
+                s_acc[le * 5 + 0] = acc[e].A;
+                s_acc[le * 5 + 1] = acc[e].B;
+                s_acc[le * 5 + 2] = acc[e].lam;
+                s_acc[le * 5 + 3] = acc[e].sig;
+                s_acc[le * 5 + 4] = acc[e].phib;
+            }
+        s_sphi[tid] = sphi;
     }
-    if (k >= ne) deep_reverse<NTR, NP>(p, deep_factors(p, h, nsub), nsub, h, rho_k, drho_k, sphi, yj, mr, ybar, ub);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NTR; ++t) ybar[t] = 0.0;
+    if (k < ne) {
+#pragma unroll
+        for (int t = 0; t < NTR; ++t) ybar[t] = s_yb[tid * NTR + t];
+        const EuphoticAdj acc{s_acc[tid * 5 + 0], s_acc[tid * 5 + 1], s_acc[tid * 5 + 2], s_acc[tid * 5 + 3],
+                              s_acc[tid * 5 + 4]};
+        const double Q = g.ins[(size_t)j * g.nlat + g.col_lat[c0 + lc]];
+        double light[NEU], hz[NEU], rho[NEU];
+#pragma unroll
+        for (int e = 0; e < NEU; ++e) {
+            const int ee = e < ne ? e : 0;
+            light[e] = md.light[(size_t)m * g.nlayer + ee];
+            hz[e] = g.dz[ee];
+            rho[e] = md.rho[tab + ee];
+        }
+        const Euphotic<NEU> E = make_euphotic<NEU>(p, Q, ne, light, hz, rho);
+        euphotic_adj_finish<NTR, NEU, NP>(p, E, k, zc, drho_k, acc, ub);
+    } else {
+        deep_reverse<NTR, NP>(p, deep_factors(p, h, nsub), nsub, h, rho_k, drho_k, s_sphi[lc], yj, mr, ybar, ub);
+    }
 }
 
 // NTR tracers of one member; TANGENT also steps v = phi'(y) direction; TPB
@@ -481,6 +531,10 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     __shared__ double s_red[TPB];
     __shared__ int s_fail;
     extern __shared__ double s_traj[];   // internal-step states [nsub][TPB][NTR] (SUB only)
+    constexpr int TS = SUB ? TPB : 1;
+    __shared__ double s_yb[TS * NTR];      // internal-step results per euphotic row (SUB only)
+    __shared__ double s_acc[TS * 5];
+    __shared__ double s_sphi[TS];
 
     const int tid = threadIdx.x;
     const int d = ps.block_dom[blockIdx.x];
@@ -519,12 +573,11 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     const double rho = md.rho[tab + k];
     const double drho = md.drho[tab + k];
     const int ne = nc < g.neu ? nc : g.neu;
-    double light[kNeuMax], hz[kNeuMax], rho_e[kNeuMax];
+    double light[kNeuMax], hz[kNeuMax];
 #pragma unroll
     for (int e = 0; e < kNeuMax; ++e) {
         light[e] = e < ne ? md.light[(size_t)m * g.nlayer + e] : 0.0;
         hz[e] = e < ne ? g.dz[e] : 0.0;
-        rho_e[e] = (SUB && e < ne) ? md.rho[tab + e] : 0.0;
     }
     double zc = 0.0;   // centre depth of the row's layer
     for (int i = 0; i <= k; ++i) zc += g.dz[i];
@@ -606,8 +659,9 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
         // (dq/dy)^T mu_j and (dq/du)^T mu_j from the own water column
         double ybar[NTR];
         if (SUB) {
-            sub_adjoint_lds<NTR, (SUB ? SN : 1), NP, TPB>(md, p, Q, tid, k, nc, ne, lr0, tab, zc, light, hz, rho_e,
-                                                          rho, drho, s_y, s_mu, s_traj, yj, mr, ybar, ub);
+            sub_adjoint_lds<NTR, (SUB ? SN : 1), NP, TPB>(g, md, p, m, j, c0, c1 - c0, s_colr0, s_colnc, tid, k, ne,
+                                                          lc, tab, zc, rho, drho, s_y, s_mu, s_traj, s_yb, s_acc,
+                                                          s_sphi, yj, mr, ybar, ub);
         } else {
             double Phi = 0.0;
 #pragma unroll

@@ -209,71 +209,61 @@ __device__ __forceinline__ void row_source_tangent(const BgcParams& p, const Eup
         }
 }
 
+// Sums over the internal steps of the row's own parameter terms while the
+// row is euphotic (finished by euphotic_adj_finish).
+struct EuphoticAdj {
+    double A;      // sum fbar limN            (alpha, K_H2O, K_I)
+    double B;      // sum fbar N+ / (N+ + K_1)^2 (K_1)
+    double lam;    // sum DOP (ib_1 - ib_2)      (lambda'_2)
+    double sig;    // sum f ib_2 - Phi rho_k ib_1 (sigma_2)
+    double phib;   // sum Phi ib_1               (b)
+};
+
 // Reverse of internal step s of the euphotic rows, seen from the row in
-// layer k (centre depth zc, remineralisation rho_k, d rho_k / d b drho_k).
+// layer k.
 //   ys:    state of the euphotic rows at internal step s (y + inc_s)
 //   pdeep: sum over the column's rows below the euphotic zone of
 //          (1 - sigma) rho mu_1 (their nutrient cotangents never change)
 //   ib:    cotangents of the euphotic rows
 // If the row is euphotic, adds h (dq/dy)^T ib of the row to ybar and its
-// unscaled (dq/du)^T ib to ub (the caller multiplies the sum by h).  Then
-// advances ib by h J_q^T ib.  Returns the export Phi of internal step s.
-// ub order: alpha, K_H2O, K_1, K_I, [lambda'_2, sigma_2,] b.
-template <int NTR, int NEU, int NP>
-__device__ __forceinline__ double euphotic_reverse(const BgcParams& p, const Euphotic<NEU>& E, int k, double zc,
-                                                   double rho_k, double drho_k, double pdeep,
-                                                   const double (&ys)[NEU][NTR], double h, double (&ib)[NEU][NTR],
-                                                   double (&ybar)[NTR], double (&ub)[NP]) {
-    double f[NEU], dfdN[NEU], limN[NEU], Npos[NEU];
+// parameter terms to acc.  Then advances ib by h J_q^T ib.  Returns the
+// export Phi of internal step s.
+template <int NTR, int NEU>
+__device__ __forceinline__ double euphotic_reverse(const BgcParams& p, const Euphotic<NEU>& E, int k, double rho_k,
+                                                   double pdeep, const double (&ys)[NEU][NTR], double h,
+                                                   double (&ib)[NEU][NTR], double (&ybar)[NTR], EuphoticAdj& acc) {
+    double f[NEU], dfdN[NEU], limN[NEU], w2[NEU];
     double Phi = 0.0, Phibar = pdeep;
 #pragma unroll
     for (int e = 0; e < NEU; ++e) {
         const bool in = e < E.ne;
         const double N = ys[e][0];
-        Npos[e] = N > 0.0 ? N : 0.0;
-        limN[e] = in ? Npos[e] / (Npos[e] + p.k1) : 0.0;
+        const double Np = N > 0.0 ? N : 0.0;
+        const double inv = 1.0 / (Np + p.k1);
+        limN[e] = in ? Np * inv : 0.0;
+        w2[e] = Np * inv * inv;                       // N+ / (N+ + K_1)^2
         f[e] = p.alpha * limN[e] * E.limI[e];
-        dfdN[e] = (in && N > 0.0) ? p.alpha * p.k1 / ((N + p.k1) * (N + p.k1)) * E.limI[e] : 0.0;
+        dfdN[e] = (in && N > 0.0) ? p.alpha * p.k1 * inv * inv * E.limI[e] : 0.0;
         Phi += E.hz[e] * f[e];
         Phibar += (1.0 - p.sig) * E.rho[e] * ib[e][0];
     }
-
     // the row's own terms, at the cotangents before this step's update
-    const bool eu = k < E.ne;
-    double fk = 0.0, dfk = 0.0, limNk = 0.0, Npk = 0.0, Ik = 0.0, limIk = 0.0, hk = 0.0;
-    double ib1 = 0.0, ib2 = 0.0, dop = 0.0;
 #pragma unroll
     for (int e = 0; e < NEU; ++e)
-        if (e == k && eu) {
-            fk = f[e];
-            dfk = dfdN[e];
-            limNk = limN[e];
-            Npk = Npos[e];
-            Ik = E.I[e];
-            limIk = E.limI[e];
-            hk = E.hz[e];
-            ib1 = ib[e][0];
+        if (e == k && e < E.ne) {
+            const double ib1 = ib[e][0];
+            const double ib2 = NTR > 1 ? ib[e][NTR - 1] : 0.0;
+            const double fbar = -ib1 + p.sig * ib2 + E.hz[e] * Phibar;
+            ybar[0] += h * (fbar * dfdN[e]);
+            acc.A += fbar * limN[e];
+            acc.B += fbar * w2[e];
             if (NTR > 1) {
-                ib2 = ib[e][NTR - 1];
-                dop = ys[e][NTR - 1];
+                ybar[NTR - 1] += h * (p.lam * (ib1 - ib2));
+                acc.lam += ys[e][NTR - 1] * (ib1 - ib2);
+                acc.sig += f[e] * ib2 - Phi * rho_k * ib1;
             }
+            acc.phib += Phi * ib1;
         }
-    if (eu) {
-        const double fbar = -ib1 + p.sig * ib2 + hk * Phibar;
-        const double IKI2 = (Ik + p.ki) * (Ik + p.ki);
-        ybar[0] += h * (fbar * dfk);
-        ub[0] += fbar * limNk * limIk;
-        ub[1] += fbar * p.alpha * limNk * p.ki / IKI2 * (-zc * Ik);
-        ub[2] += fbar * (-p.alpha * Npk / ((Npk + p.k1) * (Npk + p.k1)) * limIk);
-        ub[3] += fbar * (-p.alpha * limNk * Ik / IKI2);
-        if (NTR > 1) {
-            ybar[NTR - 1] += h * (p.lam * (ib1 - ib2));
-            ub[4] += dop * (ib1 - ib2);
-            ub[5] += fk * ib2 - Phi * rho_k * ib1;
-        }
-        ub[NP - 1] += (1.0 - p.sig) * Phi * drho_k * ib1;
-    }
-
     // advance the cotangents of the euphotic rows
 #pragma unroll
     for (int e = 0; e < NEU; ++e) {
@@ -286,6 +276,76 @@ __device__ __forceinline__ double euphotic_reverse(const BgcParams& p, const Eup
         if (NTR > 1) ib[e][NTR - 1] += in ? h * y2 : 0.0;
     }
     return Phi;
+}
+
+// The same reverse step for all euphotic rows of a column at once (one
+// thread per column): each row e gets its own terms in ybar[e] and acc[e].
+template <int NTR, int NEU>
+__device__ __forceinline__ double euphotic_reverse_rows(const BgcParams& p, const Euphotic<NEU>& E, double pdeep,
+                                                        const double (&ys)[NEU][NTR], double h,
+                                                        double (&ib)[NEU][NTR], double (&ybar)[NEU][NTR],
+                                                        EuphoticAdj (&acc)[NEU]) {
+    double f[NEU], dfdN[NEU], limN[NEU], w2[NEU];
+    double Phi = 0.0, Phibar = pdeep;
+#pragma unroll
+    for (int e = 0; e < NEU; ++e) {
+        const bool in = e < E.ne;
+        const double N = ys[e][0];
+        const double Np = N > 0.0 ? N : 0.0;
+        const double inv = 1.0 / (Np + p.k1);
+        limN[e] = in ? Np * inv : 0.0;
+        w2[e] = Np * inv * inv;
+        f[e] = p.alpha * limN[e] * E.limI[e];
+        dfdN[e] = (in && N > 0.0) ? p.alpha * p.k1 * inv * inv * E.limI[e] : 0.0;
+        Phi += E.hz[e] * f[e];
+        Phibar += (1.0 - p.sig) * E.rho[e] * ib[e][0];
+    }
+#pragma unroll
+    for (int e = 0; e < NEU; ++e) {
+        const bool in = e < E.ne;
+        const double ib1 = ib[e][0];
+        const double ib2 = NTR > 1 ? ib[e][NTR - 1] : 0.0;
+        const double fbar = -ib1 + p.sig * ib2 + E.hz[e] * Phibar;
+        const double y1 = fbar * dfdN[e];
+        const double y2 = p.lam * (ib1 - ib2);
+        ybar[e][0] += h * y1;
+        acc[e].A += fbar * limN[e];
+        acc[e].B += fbar * w2[e];
+        if (NTR > 1) {
+            ybar[e][NTR - 1] += h * y2;
+            acc[e].lam += ys[e][NTR - 1] * (ib1 - ib2);
+            acc[e].sig += f[e] * ib2 - Phi * E.rho[e] * ib1;
+        }
+        acc[e].phib += Phi * ib1;
+        ib[e][0] += in ? h * y1 : 0.0;
+        if (NTR > 1) ib[e][NTR - 1] += in ? h * y2 : 0.0;
+    }
+    return Phi;
+}
+
+// Adds the euphotic row's summed parameter terms (unscaled) to ub, in the
+// order alpha, K_H2O, K_1, K_I, [lambda'_2, sigma_2,] b; zc is the row's
+// centre depth.  The light factors are constant over the ocean step.
+template <int NTR, int NEU, int NP>
+__device__ __forceinline__ void euphotic_adj_finish(const BgcParams& p, const Euphotic<NEU>& E, int k, double zc,
+                                                    double drho_k, const EuphoticAdj& acc, double (&ub)[NP]) {
+    double Ik = 0.0, limIk = 0.0;
+#pragma unroll
+    for (int e = 0; e < NEU; ++e)
+        if (e == k) {
+            Ik = E.I[e];
+            limIk = E.limI[e];
+        }
+    const double IKI2 = (Ik + p.ki) * (Ik + p.ki);
+    ub[0] += acc.A * limIk;
+    ub[1] += acc.A * (p.alpha * p.ki / IKI2 * (-zc * Ik));
+    ub[2] += acc.B * (-p.alpha * limIk);
+    ub[3] += acc.A * (-p.alpha * Ik / IKI2);
+    if (NTR > 1) {
+        ub[4] += acc.lam;
+        ub[5] += acc.sig;
+    }
+    ub[NP - 1] += (1.0 - p.sig) * drho_k * acc.phib;
 }
 
 // Reverse mode of a row below the euphotic zone over all internal steps:

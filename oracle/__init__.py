@@ -15,6 +15,9 @@ LIB_PATH = os.environ.get("TMM_ORACLE_LIB", os.path.join(HERE, "liboracle.so"))
 
 MODEL_N = 1
 MODEL_NDOP = 2
+MODEL_NDOPPHY = 3
+_NTRACER = {MODEL_N: 1, MODEL_NDOP: 2, MODEL_NDOPPHY: 3}
+_NPARAM = {MODEL_N: 5, MODEL_NDOP: 7, MODEL_NDOPPHY: 11}
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
@@ -130,8 +133,8 @@ class Oracle:
         self._keep = {k: v for k, v in a.items() if isinstance(v, np.ndarray)}
         self.n = a["n"]
         self.model = model if model is not None else a["model"]
-        self.ntracer = 1 if self.model == MODEL_N else 2
-        self.nparam = 5 if self.model == MODEL_N else 7
+        self.ntracer = _NTRACER[self.model]
+        self.nparam = _NPARAM[self.model]
         self.nstep = nstep if nstep is not None else a["nstep"]
         self.nmat = a["nmat"]
         k = self._keep

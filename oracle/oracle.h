@@ -20,7 +20,7 @@
 extern "C" {
 #endif
 
-enum { ORACLE_MODEL_N = 1, ORACLE_MODEL_NDOP = 2 };
+enum { ORACLE_MODEL_N = 1, ORACLE_MODEL_NDOP = 2, ORACLE_MODEL_NDOPPHY = 3 };
 
 typedef struct {
     int n, ncol, nlayer;

@@ -12,6 +12,7 @@
  *   matrices  A(t_j) = (1-w) A_k0 + w A_k1, monthly anchors          [3, 7]
  *   year map  phi(y_0) = y_nstep, residual ||y - phi(y)||_2           [4, 7]
  *   BGC       PO4-DOP model: production, light, DOP, Martin export    [2.2.1]
+ *             PO4-DOP-PHY model: explicit phytoplankton               [2.2.2]
  *             evaluated per water column through the interface of     [5]
  *   tangent   phi'(y) v, exactly (forward mode) and by finite         [6.1]
  *             differences
@@ -36,6 +37,10 @@
  *   - Michaelis-Menten uses max(N, 0), with derivative 0 for N <= 0.
  *   - The one-tracer N model is the PO4-DOP model without the DOP tracer
  *     (sigma_2 = 0, all production exported).
+ *   - PO4-DOP-PHY: production f_1 = mu_1 PHY N+/(N+ + K_1) I/(I + K_I) with
+ *     PHY entering linearly (not clipped); the exported part is
+ *     (1 - sigma_2) sigma_3 f_1, remineralised as in PO4-DOP; the losses
+ *     lambda_3 PHY + kappa_3 PHY^2 act in the euphotic zone only.
  *   - With nbgc > 1 internal BGC steps per ocean step (section 7), the source
  *     is the increment of nbgc explicit Euler sub-steps of length dt/nbgc at
  *     the step's forcing; nbgc = 1 is dt*q(y).
@@ -52,11 +57,14 @@
 #define SOLAR_CONSTANT 1361.0
 #define DAYS_PER_YEAR 360.0
 #define MAX_LAYERS 256
+#define MAX_TRACERS 3
+#define MAX_PARAMS 11
 
 int oracle_ntracer(int model)
 {
     if (model == ORACLE_MODEL_N) return 1;
     if (model == ORACLE_MODEL_NDOP) return 2;
+    if (model == ORACLE_MODEL_NDOPPHY) return 3;
     return -1;
 }
 
@@ -64,6 +72,7 @@ int oracle_nparam(int model)
 {
     if (model == ORACLE_MODEL_N) return 5;
     if (model == ORACLE_MODEL_NDOP) return 7;
+    if (model == ORACLE_MODEL_NDOPPHY) return 11;
     return -1;
 }
 
@@ -142,12 +151,13 @@ static void spmm_interp_transposed(int n, const int *rowptr, const int *colidx,
  * ------------------------------------------------------------------------ */
 
 typedef struct {
-    int ntracer;            /* 1 (N) or 2 (PO4, DOP) */
+    int ntracer;            /* 1 (N), 2 (PO4, DOP) or 3 (PO4, DOP, PHY) */
     int nl;                 /* wet layers in this column */
     int neu;                /* euphotic layers */
     const double *h;        /* layer heights of the grid, at least max(nl, neu) */
     double insol;           /* I_SWR, W/m^2 */
-    double alpha, kw, k1, ki, lam, sig, b;
+    double alpha, kw, k1, ki, lam, sig, b;     /* alpha is mu_1 in PO4-DOP-PHY */
+    double lam3, kap3, lam3p, sig3;            /* PO4-DOP-PHY only */
 } column_ctx;
 
 static void column_params(column_ctx *c, int model, const double *u)
@@ -156,7 +166,16 @@ static void column_params(column_ctx *c, int model, const double *u)
     c->kw = u[1];
     c->k1 = u[2];
     c->ki = u[3];
-    if (model == ORACLE_MODEL_NDOP) {
+    c->lam3 = c->kap3 = c->lam3p = c->sig3 = 0.0;
+    if (model == ORACLE_MODEL_NDOPPHY) {
+        c->lam = u[4];
+        c->sig = u[5];
+        c->lam3 = u[6];
+        c->kap3 = u[7];
+        c->lam3p = u[8];
+        c->sig3 = u[9];
+        c->b = u[10];
+    } else if (model == ORACLE_MODEL_NDOP) {
         c->lam = u[4];
         c->sig = u[5];
         c->b = u[6];
@@ -172,6 +191,7 @@ static void param_slots(int model, int *ia, int *ikw, int *ik1, int *iki, int *i
 {
     *ia = 0; *ikw = 1; *ik1 = 2; *iki = 3;
     if (model == ORACLE_MODEL_NDOP) { *ilam = 4; *isig = 5; *ib = 6; }
+    else if (model == ORACLE_MODEL_NDOPPHY) { *ilam = 4; *isig = 5; *ib = 10; }
     else { *ilam = -1; *isig = -1; *ib = 4; }
 }
 
@@ -234,10 +254,112 @@ static void remineralisation(const column_ctx *c, double *rho, double *drho_db)
     }
 }
 
+/* Section 2.2.2, PO4-DOP-PHY, one column; y and q are [3][nl] (PO4, DOP, PHY).
+ * In the euphotic zone (k < neu):
+ *   q_1 = -f_1 + lambda'_2 DOP + (1 - sigma_2) Phi rho_k
+ *   q_2 = sigma_2 f_3 + lambda_3 PHY + kappa_3 PHY^2 - lambda'_2 DOP + lambda'_3 PHY
+ *   q_3 = (1 - sigma_3) f_1 - lambda_3 PHY - kappa_3 PHY^2 - lambda'_3 PHY
+ * below it f_1 = 0 and the lambda_3, kappa_3 terms vanish; f_3 = sigma_3 f_1 and
+ * the export is Phi = sum_k h_k f_3,k over the euphotic layers. */
+static void column_q_phy(const column_ctx *c, const double *y, double *q)
+{
+    int nl = c->nl, neu = c->neu;
+    const double *N = y, *D = y + nl, *P = y + 2 * nl;
+    double rho[MAX_LAYERS], f[MAX_LAYERS];
+    remineralisation(c, rho, NULL);
+    double Phi = 0.0;
+    for (int k = 0; k < nl; ++k) {
+        f[k] = 0.0;
+        if (k < neu) {
+            f[k] = production(c, k, N[k]).f * P[k];
+            Phi += c->h[k] * (c->sig3 * f[k]);
+        }
+    }
+    for (int k = 0; k < nl; ++k) {
+        double loss = k < neu ? c->lam3 * P[k] + c->kap3 * P[k] * P[k] : 0.0;
+        q[k] = -f[k] + c->lam * D[k] + (1.0 - c->sig) * Phi * rho[k];
+        q[nl + k] = c->sig * (c->sig3 * f[k]) + loss - c->lam * D[k] + c->lam3p * P[k];
+        q[2 * nl + k] = (1.0 - c->sig3) * f[k] - loss - c->lam3p * P[k];
+    }
+}
+
+static void column_q_phy_tangent(const column_ctx *c, const double *y, const double *yd, double *qd)
+{
+    int nl = c->nl, neu = c->neu;
+    const double *N = y, *P = y + 2 * nl;
+    const double *Nd = yd, *Dd = yd + nl, *Pd = yd + 2 * nl;
+    double rho[MAX_LAYERS], fd[MAX_LAYERS];
+    remineralisation(c, rho, NULL);
+    double Phid = 0.0;
+    for (int k = 0; k < nl; ++k) {
+        fd[k] = 0.0;
+        if (k < neu) {
+            production_t pr = production(c, k, N[k]);
+            fd[k] = pr.dfdN * Nd[k] * P[k] + pr.f * Pd[k];
+            Phid += c->h[k] * (c->sig3 * fd[k]);
+        }
+    }
+    for (int k = 0; k < nl; ++k) {
+        double lossd = k < neu ? (c->lam3 + 2.0 * c->kap3 * P[k]) * Pd[k] : 0.0;
+        qd[k] = -fd[k] + c->lam * Dd[k] + (1.0 - c->sig) * Phid * rho[k];
+        qd[nl + k] = c->sig * (c->sig3 * fd[k]) + lossd - c->lam * Dd[k] + c->lam3p * Pd[k];
+        qd[2 * nl + k] = (1.0 - c->sig3) * fd[k] - lossd - c->lam3p * Pd[k];
+    }
+}
+
+/* ybar = (dq/dy)^T mu, ubar += (dq/du)^T mu in the parameter order of the
+ * table of section 2.2.2. */
+static void column_q_phy_adjoint(const column_ctx *c, const double *y, const double *mu, double *ybar,
+                                 double *ubar)
+{
+    int nl = c->nl, neu = c->neu;
+    const double *N = y, *D = y + nl, *P = y + 2 * nl;
+    const double *m1 = mu, *m2 = mu + nl, *m3 = mu + 2 * nl;
+    double rho[MAX_LAYERS], drho[MAX_LAYERS];
+    remineralisation(c, rho, drho);
+    double Phi = 0.0, Phibar = 0.0;
+    for (int k = 0; k < nl; ++k) {
+        if (k < neu) Phi += c->h[k] * (c->sig3 * (production(c, k, N[k]).f * P[k]));
+        Phibar += (1.0 - c->sig) * rho[k] * m1[k];
+    }
+    for (int k = 0; k < nl; ++k) {
+        double *bN = ybar + k, *bD = ybar + nl + k, *bP = ybar + 2 * nl + k;
+        *bN = 0.0;
+        *bP = 0.0;
+        if (k < neu) {
+            production_t pr = production(c, k, N[k]);
+            double f = pr.f * P[k];
+            /* f_1 enters q_1 (-1), q_2 (sigma_2 sigma_3), q_3 (1 - sigma_3) and Phi (h_k sigma_3) */
+            double fbar = -m1[k] + c->sig * c->sig3 * m2[k] + (1.0 - c->sig3) * m3[k] + c->sig3 * c->h[k] * Phibar;
+            double dloss = c->lam3 + 2.0 * c->kap3 * P[k];
+            *bN = fbar * pr.dfdN * P[k];
+            *bP += fbar * pr.f + dloss * (m2[k] - m3[k]);
+            ubar[0] += fbar * pr.dalpha * P[k];
+            ubar[1] += fbar * pr.dkw * P[k];
+            ubar[2] += fbar * pr.dk1 * P[k];
+            ubar[3] += fbar * pr.dki * P[k];
+            ubar[5] += c->sig3 * f * m2[k];
+            ubar[6] += P[k] * (m2[k] - m3[k]);
+            ubar[7] += P[k] * P[k] * (m2[k] - m3[k]);
+            ubar[9] += f * (c->sig * m2[k] - m3[k] + c->h[k] * Phibar);
+        }
+        *bD = c->lam * (m1[k] - m2[k]);
+        *bP += c->lam3p * (m2[k] - m3[k]);
+        ubar[4] += D[k] * (m1[k] - m2[k]);
+        ubar[5] += -Phi * rho[k] * m1[k];
+        ubar[8] += P[k] * (m2[k] - m3[k]);
+        ubar[10] += (1.0 - c->sig) * Phi * drho[k] * m1[k];
+    }
+}
+
 /* q for one column: y and q are [ntracer][nl] (tracer-major, as in the
  * Fortran form of the interface). */
 static void column_q(const column_ctx *c, const double *y, double *q)
 {
+    if (c->ntracer == 3) {
+        column_q_phy(c, y, q);
+        return;
+    }
     int nl = c->nl, neu = c->neu, ntr = c->ntracer;
     double rho[MAX_LAYERS], f[MAX_LAYERS];
     remineralisation(c, rho, NULL);
@@ -259,6 +381,10 @@ static void column_q(const column_ctx *c, const double *y, double *q)
 /* Tangent: qdot = (dq/dy) ydot. */
 static void column_q_tangent(const column_ctx *c, const double *y, const double *ydot, double *qdot)
 {
+    if (c->ntracer == 3) {
+        column_q_phy_tangent(c, y, ydot, qdot);
+        return;
+    }
     int nl = c->nl, neu = c->neu, ntr = c->ntracer;
     double rho[MAX_LAYERS], fdot[MAX_LAYERS];
     remineralisation(c, rho, NULL);
@@ -281,6 +407,10 @@ static void column_q_tangent(const column_ctx *c, const double *y, const double 
 static void column_q_adjoint(const column_ctx *c, int model, const double *y, const double *mu,
                              double *ybar, double *ubar)
 {
+    if (c->ntracer == 3) {
+        column_q_phy_adjoint(c, y, mu, ybar, ubar);
+        return;
+    }
     int nl = c->nl, neu = c->neu, ntr = c->ntracer;
     int ia, ikw, ik1, iki, ilam, isig, ib;
     param_slots(model, &ia, &ikw, &ik1, &iki, &ilam, &isig, &ib);
@@ -326,7 +456,7 @@ static void column_q_adjoint(const column_ctx *c, int model, const double *y, co
 static void column_source(const column_ctx *c, const double *y, double dt, int nsub, double *inc)
 {
     int len = c->ntracer * c->nl;
-    double yt[2 * MAX_LAYERS], q[2 * MAX_LAYERS];
+    double yt[MAX_TRACERS * MAX_LAYERS], q[MAX_TRACERS * MAX_LAYERS];
     double h = dt / nsub;
     for (int i = 0; i < len; ++i) inc[i] = 0.0;
     for (int s = 0; s < nsub; ++s) {
@@ -341,7 +471,7 @@ static void column_source_tangent(const column_ctx *c, const double *y, const do
                                   double *incdot)
 {
     int len = c->ntracer * c->nl;
-    double inc[2 * MAX_LAYERS], yt[2 * MAX_LAYERS], ytd[2 * MAX_LAYERS], q[2 * MAX_LAYERS], qd[2 * MAX_LAYERS];
+    double inc[MAX_TRACERS * MAX_LAYERS], yt[MAX_TRACERS * MAX_LAYERS], ytd[MAX_TRACERS * MAX_LAYERS], q[MAX_TRACERS * MAX_LAYERS], qd[MAX_TRACERS * MAX_LAYERS];
     double h = dt / nsub;
     for (int i = 0; i < len; ++i) { inc[i] = 0.0; incdot[i] = 0.0; }
     for (int s = 0; s < nsub; ++s) {
@@ -358,8 +488,8 @@ static void column_source_adjoint(const column_ctx *c, int model, const double *
                                   int nsub, double *ybar, double *ubar)
 {
     int len = c->ntracer * c->nl;
-    double ytraj[MAX_SUBSTEPS][2 * MAX_LAYERS];
-    double inc[2 * MAX_LAYERS], q[2 * MAX_LAYERS], ibar[2 * MAX_LAYERS], yb[2 * MAX_LAYERS];
+    double ytraj[MAX_SUBSTEPS][MAX_TRACERS * MAX_LAYERS];
+    double inc[MAX_TRACERS * MAX_LAYERS], q[MAX_TRACERS * MAX_LAYERS], ibar[MAX_TRACERS * MAX_LAYERS], yb[MAX_TRACERS * MAX_LAYERS];
     double h = dt / nsub;
     for (int i = 0; i < len; ++i) inc[i] = 0.0;
     for (int s = 0; s < nsub; ++s) {
@@ -369,13 +499,13 @@ static void column_source_adjoint(const column_ctx *c, int model, const double *
     }
     for (int i = 0; i < len; ++i) { ibar[i] = mu[i]; ybar[i] = 0.0; }
     for (int s = nsub - 1; s >= 0; --s) {
-        double ucol[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double ucol[MAX_PARAMS] = {0};
         column_q_adjoint(c, model, ytraj[s], ibar, yb, ucol);
         for (int i = 0; i < len; ++i) {
             ybar[i] += h * yb[i];
             ibar[i] += h * yb[i];
         }
-        for (int p = 0; p < 8; ++p) ubar[p] += h * ucol[p];
+        for (int p = 0; p < MAX_PARAMS; ++p) ubar[p] += h * ucol[p];
     }
 }
 
@@ -462,7 +592,7 @@ static void add_sources(const oracle_desc *g, int nbatch, const double *u, int j
 {
     int ntr = oracle_ntracer(g->model), np = oracle_nparam(g->model), W = nbatch * ntr;
     double t = (double)(((j % g->nstep) + g->nstep) % g->nstep) / (double)g->nstep;
-    double col[2 * MAX_LAYERS], inc[2 * MAX_LAYERS];
+    double col[MAX_TRACERS * MAX_LAYERS], inc[MAX_TRACERS * MAX_LAYERS];
     for (int c = 0; c < g->ncol; ++c) {
         for (int b = 0; b < nbatch; ++b) {
             column_ctx cc;
@@ -542,7 +672,7 @@ int oracle_year_tangent(const oracle_desc *g, int nbatch, const double *u,
     if (!ya || !yb || !va || !vb || !z) { free(ya); free(yb); free(va); free(vb); free(z); return -2; }
     memcpy(ya, y, sizeof(double) * len);
     memcpy(va, v, sizeof(double) * len);
-    double col[2 * MAX_LAYERS], dcol[2 * MAX_LAYERS], qd[2 * MAX_LAYERS];
+    double col[MAX_TRACERS * MAX_LAYERS], dcol[MAX_TRACERS * MAX_LAYERS], qd[MAX_TRACERS * MAX_LAYERS];
     for (int j = 0; j < g->nstep; ++j) {
         int k0, k1;
         double w;
@@ -687,7 +817,7 @@ static int reverse_year(const oracle_desc *g, int nbatch, const double *u, const
                 lam[i * W + c] += V[i] * (ys[i * W + c] - o[i * W + c]) / (g->nmat * vtot);
     }
 
-    double col[2 * MAX_LAYERS], mcol[2 * MAX_LAYERS], yb[2 * MAX_LAYERS];
+    double col[MAX_TRACERS * MAX_LAYERS], mcol[MAX_TRACERS * MAX_LAYERS], yb[MAX_TRACERS * MAX_LAYERS];
     for (int j = nstep - 1; j >= 0; --j) {
         int k0, k1;
         double w;
@@ -703,7 +833,7 @@ static int reverse_year(const oracle_desc *g, int nbatch, const double *u, const
         for (int c = 0; c < g->ncol; ++c)
             for (int b = 0; b < nbatch; ++b) {
                 column_ctx cc;
-                double ucol[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                double ucol[MAX_PARAMS] = {0};
                 make_column(g, c, t, u + (size_t)b * np, g->model, &cc);
                 gather_column(g, W, b, c, yj, col);
                 gather_column(g, W, b, c, mu, mcol);

@@ -22,7 +22,7 @@ take these arrays as plain inputs.
 from .grid import Grid, make_grid  # noqa: F401
 from .transport import Transport, make_transport  # noqa: F401
 from .params import (  # noqa: F401
-    MODEL_N, MODEL_NDOP, NTRACER, NPARAM, PARAM_NAMES,
+    MODEL_N, MODEL_NDOP, MODEL_NDOPPHY, NTRACER, NPARAM, PARAM_NAMES,
     nominal, bounds, latin_hypercube, spinup_lengths, hidden_params, obs_noise,
 )
 from .workloads import Inputs, tiny, small_ndop, global_2p8, ensemble_1p4, by_name  # noqa: F401

@@ -16,7 +16,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .grid import Grid, make_grid
-from .params import MODEL_N, MODEL_NDOP, NTRACER, NPARAM
+from .params import MODEL_N, MODEL_NDOP, MODEL_NDOPPHY, NTRACER, NPARAM
 from .transport import Transport, make_transport
 
 
@@ -76,15 +76,17 @@ def _build(name, nlon, nlat, nlayer, ncol, n, model, neu, y_init, seed, nmat=12,
     return Inputs(name=name, grid=grid, tm=tm, model=model, neuphotic=neu, y_init=y_init)
 
 
+# constant initial field per tracer: PO4, DOP, PHY (mmol P / m^3)
+Y_INIT = {MODEL_N: (2.17,), MODEL_NDOP: (2.17, 1e-4), MODEL_NDOPPHY: (2.17, 1e-4, 1e-2)}
+
+
 def tiny(seed: int = 7, model: int = MODEL_N, nstep: int = 2880) -> Inputs:
-    y0 = (2.17,) if model == MODEL_N else (2.17, 1e-4)
     neu = 1 if model == MODEL_N else 2
-    return _build("tiny_16x8x4", 16, 8, 4, 90, 300, model, neu, y0, seed, nstep=nstep)
+    return _build("tiny_16x8x4", 16, 8, 4, 90, 300, model, neu, Y_INIT[model], seed, nstep=nstep)
 
 
-def global_2p8(seed: int = 11, nstep: int = 2880) -> Inputs:
-    return _build("global_128x64x15", 128, 64, 15, 4448, 52749, MODEL_NDOP, 2, (2.17, 1e-4), seed,
-                  nstep=nstep)
+def global_2p8(seed: int = 11, nstep: int = 2880, model: int = MODEL_NDOP) -> Inputs:
+    return _build("global_128x64x15", 128, 64, 15, 4448, 52749, model, 2, Y_INIT[model], seed, nstep=nstep)
 
 
 def ensemble_1p4(seed: int = 13, nstep: int = 2880) -> Inputs:
@@ -92,9 +94,9 @@ def ensemble_1p4(seed: int = 13, nstep: int = 2880) -> Inputs:
                   nstep=nstep)
 
 
-def small_ndop(seed: int = 5, nstep: int = 2880) -> Inputs:
-    """A 32x16x8 N-DOP grid (about 2.7k points): several tiles and a ragged tail."""
-    return _build("small_32x16x8", 32, 16, 8, 400, 2700, MODEL_NDOP, 2, (2.17, 1e-4), seed, nstep=nstep)
+def small_ndop(seed: int = 5, nstep: int = 2880, model: int = MODEL_NDOP) -> Inputs:
+    """A 32x16x8 grid (about 2.7k points, N-DOP by default): several tiles and a ragged tail."""
+    return _build("small_32x16x8", 32, 16, 8, 400, 2700, model, 2, Y_INIT[model], seed, nstep=nstep)
 
 
 def by_name(name: str) -> Inputs:

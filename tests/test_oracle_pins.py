@@ -514,3 +514,150 @@ def test_substep_derivatives(tiny_ndop):
             q[p] = x
             return o.year_misfit(q, y0, obs)[0]
         assert dJdu[0, p] == pytest.approx(_fd4(Jp, u[p], 1e-4 * abs(u[p])), rel=1e-6), p
+
+
+# --------------------------------------------------------------------------
+# PO4-DOP-PHY (section 2.2.2)
+# --------------------------------------------------------------------------
+
+PHY = synth.MODEL_NDOPPHY
+
+
+def _identity_transport(inp):
+    import copy
+    ident = copy.deepcopy(inp)
+    for kind in ("ae", "ai"):
+        rowptr = getattr(inp.tm, kind + "_rowptr")
+        colidx = getattr(inp.tm, kind + "_colidx")
+        rows = np.repeat(np.arange(inp.n), np.diff(rowptr))
+        val = np.where(rows == colidx, 1.0, 0.0)
+        setattr(ident.tm, kind + "_val", np.broadcast_to(val, (inp.nmat, val.size)).copy())
+    return ident
+
+
+@pytest.fixture(scope="module")
+def tiny_phy():
+    return synth.tiny(model=PHY)
+
+
+def test_phy_column_conserves_phosphorus(tiny_phy):
+    """sum_k h_k (q_PO4 + q_DOP + q_PHY) = 0 in every column: export, grazing and losses only move P."""
+    inp = tiny_phy
+    g = inp.grid
+    rng = np.random.default_rng(20)
+    u = synth.latin_hypercube(PHY, 1, seed=21)[0]
+    checked = 0
+    for c in range(g.ncol):
+        s, e = g.col_start[c], g.col_start[c + 1]
+        h = g.dz[:e - s]
+        y = np.vstack([rng.uniform(0.5, 3.0, e - s), rng.uniform(0.0, 0.2, e - s), rng.uniform(0.0, 0.5, e - s)])
+        q = oracle.bgc_column(PHY, 300.0, h, y, u, inp.neuphotic)
+        scale = np.abs(q * h).max()
+        assert abs(np.sum(q * h)) <= 1e-14 * scale * q.size, c
+        checked += 1
+    assert checked == g.ncol
+
+
+def test_phy_reduces_to_po4_dop(tiny_phy, tiny_ndop):
+    """sigma_3 = 1 and no PHY losses keep PHY at its initial constant c; PO4 and DOP then follow the
+    PO4-DOP model with alpha = mu_1 c (same grid and matrices)."""
+    c = 0.8
+    u = synth.nominal(PHY)
+    u[6] = u[7] = u[8] = 0.0      # lambda_3, kappa_3, lambda'_3
+    u[9] = 1.0                    # sigma_3: everything produced is grazed
+    u2 = synth.nominal(synth.MODEL_NDOP)
+    u2[[1, 2, 3, 4, 5, 6]] = u[[1, 2, 3, 4, 5, 10]]
+    u2[0] = u[0] * c
+    g = tiny_phy.grid
+    s, e = g.col_start[7], g.col_start[8]
+    rng = np.random.default_rng(22)
+    yc = np.vstack([rng.uniform(0.5, 3.0, e - s), rng.uniform(0.0, 0.2, e - s), np.full(e - s, c)])
+    q3 = oracle.bgc_column(PHY, 250.0, g.dz[:e - s], yc, u, 2)
+    q2 = oracle.bgc_column(synth.MODEL_NDOP, 250.0, g.dz[:e - s], yc[:2], u2, 2)
+    assert np.abs(q3[:2] - q2).max() <= 1e-15 * np.abs(q2).max()
+    assert np.array_equal(q3[2], np.zeros(e - s))
+    y0 = np.column_stack([tiny_phy.initial_state()[:, :2], np.full(tiny_phy.n, c)])
+    y3, _ = oracle.Oracle(tiny_phy).year(u, y0)
+    y2, _ = oracle.Oracle(tiny_ndop).year(u2, y0[:, :2])
+    assert np.abs(y3[:, :2] - y2).max() <= 1e-12 * np.abs(y2).max()
+    assert np.abs(y3[:, 2] / c - 1).max() <= 1e-13
+
+
+def test_phy_linear_losses_closed_form(tiny_phy):
+    """Identity transport, mu_1 = kappa_3 = 0: PHY_j = PHY_0 (1 - dt_d (chi lambda_3 + lambda'_3))^j with chi = 1
+    in the euphotic zone, and PO4 + DOP + PHY is constant at every point."""
+    inp = _identity_transport(tiny_phy)
+    u = synth.nominal(PHY)
+    u[0] = 0.0
+    u[7] = 0.0
+    y0 = np.column_stack([np.full(inp.n, 2.0), np.linspace(0.1, 0.5, inp.n), np.linspace(0.05, 0.3, inp.n)])
+    y1, _ = oracle.Oracle(inp).year(u, y0)
+    dtd = 360.0 / inp.nstep
+    g = inp.grid
+    layer = np.concatenate([np.arange(g.col_start[c + 1] - g.col_start[c]) for c in range(g.ncol)])
+    chi = (layer < inp.neuphotic).astype(float)
+    expect = y0[:, 2] * (1 - dtd * (chi * u[6] + u[8])) ** inp.nstep
+    assert np.abs(y1[:, 2] / expect - 1).max() < 2e-13
+    assert np.abs(y1.sum(1) / y0.sum(1) - 1).max() < 2e-13
+
+
+def test_phy_quadratic_loss(tiny_phy):
+    """Identity transport, mu_1 = lambda_3 = lambda'_3 = 0: euphotic PHY follows PHY <- PHY - dt_d kappa_3 PHY^2,
+    within O(dt) of the ODE solution PHY_0 / (1 + kappa_3 PHY_0 t); PHY below is unchanged."""
+    inp = _identity_transport(tiny_phy)
+    u = synth.nominal(PHY)
+    u[0] = u[6] = u[8] = 0.0
+    y0 = np.column_stack([np.full(inp.n, 2.0), np.full(inp.n, 0.1), np.linspace(0.05, 0.9, inp.n)])
+    y1, _ = oracle.Oracle(inp).year(u, y0)
+    dtd = 360.0 / inp.nstep
+    g = inp.grid
+    layer = np.concatenate([np.arange(g.col_start[c + 1] - g.col_start[c]) for c in range(g.ncol)])
+    eu = layer < inp.neuphotic
+    p = y0[:, 2].copy()
+    for _ in range(inp.nstep):
+        p = np.where(eu, p - dtd * u[7] * p * p, p)
+    assert np.abs(y1[:, 2] / p - 1).max() < 1e-12
+    ode = y0[:, 2] / (1 + u[7] * y0[:, 2] * 360.0)
+    assert np.abs(y1[eu, 2] - ode[eu]).max() < 0.05 * ode[eu].max()
+    assert np.abs(y1.sum(1) / y0.sum(1) - 1).max() < 2e-13
+
+
+def test_phy_mass_conserved_and_positive():
+    inp = synth.small_ndop(model=PHY)
+    u = synth.nominal(PHY)
+    y0 = inp.initial_state()
+    y1, _ = oracle.Oracle(inp).year(u, y0)
+    V = inp.grid.volumes()
+    assert abs(V @ y1.sum(1) - V @ y0.sum(1)) <= 1e-13 * (V @ y0.sum(1))
+    assert y1.min() > 0.0
+    assert np.abs(y1[:, 2] - y0[:, 2]).max() > 1e-3       # PHY changed
+
+
+def test_phy_derivatives(tiny_phy):
+    """Tangent vs central differences, tangent vs reverse (dot test), dJ/du (11 parameters) and dJ/dy0
+    vs fourth-order central differences."""
+    inp = tiny_phy
+    o = oracle.Oracle(inp)
+    u = synth.nominal(PHY)
+    rng = np.random.default_rng(23)
+    y = inp.initial_state() * rng.uniform(0.8, 1.2, size=(inp.n, 3))
+    v = rng.standard_normal(y.shape) * y
+    w = rng.standard_normal(y.shape)
+    _, jv = o.year_tangent(u, y, v)
+    h = 1e-5
+    fd = (o.year(u, y + h * v)[0] - o.year(u, y - h * v)[0]) / (2 * h)
+    assert np.abs(jv - fd).max() < 1e-7 * np.abs(jv).max()
+    ybar, _ = o.year_vjp(u, y, w)
+    assert np.sum(w * jv) == pytest.approx(np.sum(ybar * v), rel=1e-12)
+    obs = _obs(inp)
+    y0 = inp.initial_state()
+    J, dJdu, dJdy0 = o.year_adjoint(u, y0, obs)
+    for p in range(u.size):
+        def Jp(x):
+            q = u.copy()
+            q[p] = x
+            return o.year_misfit(q, y0, obs)[0]
+        assert dJdu[0, p] == pytest.approx(_fd4(Jp, u[p], 1e-4 * abs(u[p])), rel=1e-6), p
+    d = rng.standard_normal(y0.shape) * y0
+    fdy = _fd4(lambda s: o.year_misfit(u, y0 + s * d, obs)[0], 0.0, 1e-4)
+    assert np.sum(dJdy0 * d) == pytest.approx(fdy, rel=1e-6)

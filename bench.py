@@ -21,7 +21,9 @@ Further measurements, each printed as its own JSON line (not run by default):
                       lengths 1..8 years on the 256x128x23 grid, batched, against
                       one-member runs;
   --mode copy         a plain 512 MiB device copy, for scaling hardware byte
-                      counters.
+                      counters;
+  --mode grids        the launch-per-step path on the global, 256x128x23 and
+                      1.0-degree 360x180x23 grids (bandwidth against grid size).
 """
 
 import argparse
@@ -77,7 +79,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20, help="timed model years")
     ap.add_argument("--warmup", type=int, default=2, help="untimed model years")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="forward", choices=["forward", "newton", "ensemble", "copy"])
+    ap.add_argument("--mode", default="forward", choices=["forward", "newton", "ensemble", "copy", "grids"])
     ap.add_argument("--log", default=None, help="JSONL progress log (newton mode)")
     ap.add_argument("--forward-only", action="store_true",
                     help="skip the per-step comparison and the adjoint (for hardware counter runs)")
@@ -87,7 +89,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.mode != "forward":
-        {"newton": bench_newton, "ensemble": bench_ensemble, "copy": bench_copy}[args.mode](args)
+        {"newton": bench_newton, "ensemble": bench_ensemble, "copy": bench_copy, "grids": bench_grids}[args.mode](args)
         return
 
     import torch
@@ -281,6 +283,48 @@ def bench_copy(args):
     ms = s.elapsed_time(e) / 3
     print(json.dumps({"mode": "copy", "bytes_read": n * 8, "bytes_written": n * 8, "ms": ms,
                       "GB_per_s": 2 * n * 8 / ms / 1e6}), flush=True)
+
+
+def bench_grids(args):
+    """Launch-per-step model years (graph-replayed k_step, one member, N-DOP) on the
+    global 128x64x15, the 256x128x23 and the 1.0-degree 360x180x23 grids: how the
+    achieved bandwidth of the step kernel scales with the grid.  On the larger
+    grids the month pair of matrices no longer fits the 256 MB Infinity Cache and
+    every step streams it from HBM."""
+    import torch
+    import synth
+    from paper_1410_0204_amd import tmm
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    rows = []
+    for make in (synth.global_2p8, synth.ensemble_1p4, synth.one_degree):
+        inp = make()
+        B = bytes_per_step(inp.n, inp.tm.ae_nnz, inp.tm.ai_nnz, inp.ntracer)
+        t = tmm.TMM(inp.desc_arrays(), nbatch_max=1, device=dev, stream=stream)
+        t.set_option(tmm.TMM_OPT_PERSISTENT, 0)
+        t.set_params(synth.nominal(inp.model))
+        y0 = t.state(inp.initial_state())
+        ya = t.state()
+        t.year(y0, nyears=1, out=ya, residuals=False)
+        torch.cuda.synchronize()
+        s, e = _events()
+        years = 2
+        s.record(stream)
+        t.year(y0, nyears=years, out=ya, residuals=False)
+        e.record(stream)
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / years
+        us_step = ms * 1000.0 / inp.nstep
+        rec = {"workload": inp.name, "n": inp.n, "nnz_explicit": inp.tm.ae_nnz, "nnz_implicit": inp.tm.ai_nnz,
+               "bytes_per_step": B, "ms_per_year": ms, "model_years_per_s": 1000.0 / ms, "us_per_step": us_step,
+               "GB_per_s": B / (us_step * 1e-6) / 1e9, "frac_of_peak": B / (us_step * 1e-6) / 1e9 / HBM_PEAK_GBPS}
+        log(f"[bench] {inp.name}: {ms:.2f} ms/model-year, {us_step:.1f} us/step, {rec['GB_per_s']:.0f} GB/s")
+        rows.append(rec)
+        t.close()
+        del t
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "grids", "kernel": "k_step (graph-replayed, one launch per step)", "rows": rows}),
+          flush=True)
 
 
 def bench_newton(args):

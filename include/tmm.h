@@ -58,8 +58,12 @@ enum {
  * paper's parameter table. */
 enum {
     TMM_MODEL_N = 1,        /* 1 tracer (nutrient); u = alpha, K_H2O, K_N, K_I, b */
-    TMM_MODEL_NDOP = 2      /* PO4-DOP (section 2.2.1), 2 tracers;
+    TMM_MODEL_NDOP = 2,     /* PO4-DOP (section 2.2.1), 2 tracers;
                                u = alpha, K_H2O, K_1, K_I, lambda'_2, sigma_2, b */
+    TMM_MODEL_NDOPPHY = 3   /* PO4-DOP-PHY (section 2.2.2), 3 tracers (PO4, DOP, PHY);
+                               u = mu_1, K_H2O, K_1, K_I, lambda'_2, sigma_2, lambda_3, kappa_3,
+                               lambda'_3, sigma_3, b.  Internal BGC steps (nbgc > 1) are not
+                               supported with this model (TMM_EUNSUPPORTED) */
 };
 
 /* Directional derivative of the year map (section 6.1). */

@@ -33,8 +33,12 @@ constexpr size_t kAlign = 256;
         if (hipGetLastError() != hipSuccess) return TMM_EDEVICE; \
     } while (0)
 
-int ntracer_of(int model) { return model == TMM_MODEL_N ? 1 : model == TMM_MODEL_NDOP ? 2 : -1; }
-int nparam_of(int model) { return model == TMM_MODEL_N ? 5 : model == TMM_MODEL_NDOP ? 7 : -1; }
+int ntracer_of(int model) {
+    return model == TMM_MODEL_N ? 1 : model == TMM_MODEL_NDOP ? 2 : model == TMM_MODEL_NDOPPHY ? 3 : -1;
+}
+int nparam_of(int model) {
+    return model == TMM_MODEL_N ? 5 : model == TMM_MODEL_NDOP ? 7 : model == TMM_MODEL_NDOPPHY ? 11 : -1;
+}
 
 // One partition of the water columns into tiles of at most max_rows rows.
 struct Tiling {
@@ -108,7 +112,7 @@ int validate(const tmm_desc* d, Plan& P) {
     if (d->nmat < 1 || d->nstep < 1 || d->nstep % d->nmat || (d->nstep / d->nmat) % 2) return TMM_EINVAL;
     if (d->neuphotic < 1 || d->neuphotic > d->nlayer) return TMM_EINVAL;
     if (d->nbgc < 0 || d->nbgc > tmm::kSubMax) return TMM_EINVAL;
-    if (d->nbgc > 1 && d->neuphotic > tmm::kSubNeuMax) return TMM_EUNSUPPORTED;
+    if (d->nbgc > 1 && (d->neuphotic > tmm::kSubNeuMax || d->model == TMM_MODEL_NDOPPHY)) return TMM_EUNSUPPORTED;
     if (d->nbatch_max < 1 || d->adjoint_nbatch_max < 0 || d->adjoint_nbatch_max > d->nbatch_max) return TMM_EINVAL;
     if (d->adjoint_nbatch_max > 0 && (d->ckpt_every < 1 || d->nstep % d->ckpt_every)) return TMM_EINVAL;
     if (d->adjoint_nbatch_max * nparam_of(d->model) > 128) return TMM_EINVAL;
@@ -364,7 +368,8 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
     const int W = nb * h->P.ntr;
     const bool tangent = v != nullptr;
     const bool sub = h->P.nsub > 1;
-    if (!tangent && nb >= h->wide_min_members && h->P.nlayer <= 32 && h->P.ew <= tmm::kMembersEll) {
+    if (!tangent && nb >= h->wide_min_members && h->P.ntr <= 2 && h->P.nlayer <= 32 &&
+        h->P.ew <= tmm::kMembersEll) {
         // member-parallel kernel: one wavefront per column and 64 members
         const int kmax = h->P.nlayer <= 16 ? 16 : h->P.nlayer <= 24 ? 24 : 32;
         const double dtd = tmm::kDaysPerYear / h->P.nstep;
@@ -440,6 +445,16 @@ const void* persistent_kernel_of(bool tangent, int sn) {
 }
 
 const void* persistent_kernel(int ntr, bool tangent, int kmax, int tpb, int sn) {
+    if (ntr == 3) {    // PO4-DOP-PHY: one evaluation per step
+        if (tpb == 512)
+            return tangent ? (const void*)&tmm::k_year_persistent<3, true, 16, 512>
+                           : (const void*)&tmm::k_year_persistent<3, false, 16, 512>;
+        if (kmax == 16)
+            return tangent ? (const void*)&tmm::k_year_persistent<3, true, 16, 256>
+                           : (const void*)&tmm::k_year_persistent<3, false, 16, 256>;
+        return tangent ? (const void*)&tmm::k_year_persistent<3, true, 32, 256>
+                       : (const void*)&tmm::k_year_persistent<3, false, 32, 256>;
+    }
     if (tpb == 512)
         return ntr == 1 ? persistent_kernel_of<1, 16, 512>(tangent, sn) : persistent_kernel_of<2, 16, 512>(tangent, sn);
     if (kmax == 16)
@@ -455,6 +470,10 @@ const void* adjoint_kernel_of(int sn) {
 }
 
 const void* adjoint_kernel(int ntr, int kmax, int tpb, int sn) {
+    if (ntr == 3)
+        return tpb == 512 ? (const void*)&tmm::k_adjoint_persistent<3, 16, 512>
+                          : kmax == 16 ? (const void*)&tmm::k_adjoint_persistent<3, 16, 256>
+                                       : (const void*)&tmm::k_adjoint_persistent<3, 32, 256>;
     if (tpb == 512) return ntr == 1 ? adjoint_kernel_of<1, 16, 512>(sn) : adjoint_kernel_of<2, 16, 512>(sn);
     if (kmax == 16) return ntr == 1 ? adjoint_kernel_of<1, 16, 256>(sn) : adjoint_kernel_of<2, 16, 256>(sn);
     return ntr == 1 ? adjoint_kernel_of<1, 32, 256>(sn) : adjoint_kernel_of<2, 32, 256>(sn);
@@ -777,7 +796,11 @@ int adjoint_persistent(tmm_ctx* h, const double* y0, const double* obs, double* 
         const size_t lds = (size_t)tl.max_rows * P.ntr * 8 + (size_t)256 * np * 8;
         const double sc = 1.0 / (P.nmat * h->vtot);
         const double* ob = obs + (size_t)(P.nmat - 1) * len;
-        if (P.ntr == 2)
+        if (P.ntr == 3)
+            hipLaunchKernelGGL((tmm::k_adjoint<3, kMaxTileRows, kMaxTileRows>), dim3(tl.ntile), dim3(256), lds,
+                               h->stream, g, md, mt, P.ntr, 1, P.nstep, dtd, 0, 1, nullptr, fin, ob, sc, mu[0],
+                               nullptr);
+        else if (P.ntr == 2)
             hipLaunchKernelGGL((tmm::k_adjoint<2, kMaxTileRows, kMaxTileRows>), dim3(tl.ntile), dim3(256), lds,
                                h->stream, g, md, mt, P.ntr, 1, P.nstep, dtd, 0, 1, nullptr, fin, ob, sc, mu[0],
                                nullptr);
@@ -1006,7 +1029,8 @@ int tmm_set_params(tmm_handle h, int nbatch, const double* u) {
         for (int i = 0; i < np; ++i)
             if (!std::isfinite(p[i])) return TMM_EINVAL;
         if (p[2] <= 0.0 || p[3] <= 0.0) return TMM_EINVAL;
-        if (h->P.model == TMM_MODEL_NDOP && (p[5] < 0.0 || p[5] > 1.0)) return TMM_EINVAL;
+        if (h->P.model != TMM_MODEL_N && (p[5] < 0.0 || p[5] > 1.0)) return TMM_EINVAL;
+        if (h->P.model == TMM_MODEL_NDOPPHY && (p[9] < 0.0 || p[9] > 1.0)) return TMM_EINVAL;
     }
     std::vector<double> uu(u, u + (size_t)nbatch * np);
     if (upload(h, h->at<double>(h->P.o_u), uu.data(), uu.size() * 8)) return TMM_EDEVICE;
@@ -1287,7 +1311,10 @@ int tmm_year_adjoint(tmm_handle h, const double* y0, const double* obs, int ckpt
                        double* out) -> int {
         const double sc = 1.0 / (P.nmat * h->vtot);
         double* ub = use_ae ? ubt : nullptr;
-        if (ntr == 2 && P.nsub > 1)
+        if (ntr == 3)
+            hipLaunchKernelGGL((tmm::k_adjoint<3, kMaxTileRows, kMaxTileRows>), dim3(tl.ntile), dim3(256), lds,
+                               h->stream, g, md, mt, W, nb, j, dtd, use_ae, use_ai, mu_in, yj, ob, sc, out, ub);
+        else if (ntr == 2 && P.nsub > 1)
             hipLaunchKernelGGL((tmm::k_adjoint<2, kMaxTileRows, kMaxTileRows, true>), dim3(tl.ntile), dim3(256), lds,
                                h->stream, g, md, mt, W, nb, j, dtd, use_ae, use_ai, mu_in, yj, ob, sc, out, ub);
         else if (ntr == 2)

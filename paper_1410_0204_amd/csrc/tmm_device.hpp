@@ -4,7 +4,8 @@
 // 1410.0204).  One time step (section 3)
 //     z = Ae(t_j) y_j + dt_d q(y_j, u),   y_{j+1} = Ai(t_j) z
 // with Ae, Ai linear interpolations of monthly matrices and q the PO4-DOP
-// model of section 2.2.1 evaluated per water column (section 5).
+// model of section 2.2.1 (or the PO4-DOP-PHY model of section 2.2.2)
+// evaluated per water column (section 5).
 //
 // Data layout on the device (built by the host code at creation):
 //  * Ae, Ae^T: ELL, slot-major: val[month][slot][npad], col[slot][npad].
@@ -32,10 +33,12 @@ constexpr double kSigmaIce = 0.0;       // no ice in the synthetic forcing
 constexpr double kSolarConstant = 1361.0;
 constexpr double kDaysPerYear = 360.0;  // section 5.1
 
-enum { MODEL_N = 1, MODEL_NDOP = 2 };
+enum { MODEL_N = 1, MODEL_NDOP = 2, MODEL_NDOPPHY = 3 };
 
+// alpha is mu_1 in PO4-DOP-PHY; lam3, kap3, lam3p, sig3 exist only there.
 struct BgcParams {
     double alpha, kw, k1, ki, lam, sig, b;
+    double lam3, kap3, lam3p, sig3;
 };
 
 }  // namespace tmm
@@ -51,7 +54,16 @@ __device__ __forceinline__ BgcParams load_params(const double* __restrict__ u, i
     r.kw = p[1];
     r.k1 = p[2];
     r.ki = p[3];
-    if (model == MODEL_NDOP) {
+    r.lam3 = r.kap3 = r.lam3p = r.sig3 = 0.0;
+    if (model == MODEL_NDOPPHY) {
+        r.lam = p[4];
+        r.sig = p[5];
+        r.lam3 = p[6];
+        r.kap3 = p[7];
+        r.lam3p = p[8];
+        r.sig3 = p[9];
+        r.b = p[10];
+    } else if (model == MODEL_NDOP) {
         r.lam = p[4];
         r.sig = p[5];
         r.b = p[6];
@@ -283,6 +295,110 @@ __device__ __forceinline__ void bgc_q(const Grid& g, const Model& md, const doub
     q2 = p.sig * fk - p.lam * dop;
 }
 
+// PO4-DOP-PHY (section 2.2.2) for one (row, member): f_1 = mu_1 PHY N+/(N+ + K_1)
+// I/(I + K_I), f_3 = sigma_3 f_1, export Phi = sum_e h_e f_3,e; the losses
+// lambda_3 PHY + kappa_3 PHY^2 act in the euphotic zone only.  q[3].
+__device__ __forceinline__ void bgc_q_phy(const Grid& g, const Model& md, const double* __restrict__ y, int W,
+                                          const ColumnRef& c, int slot, double* q) {
+    const int m = md.member[slot];
+    const BgcParams p = load_params(md.u, md.model, md.nparam, m);
+    const double* light = md.light + (size_t)m * g.nlayer;
+    const int ne = c.nc < g.neu ? c.nc : g.neu;
+    double Phi = 0.0, fk = 0.0;
+    for (int e = 0; e < ne; ++e) {
+        const size_t at = (size_t)(c.rs + e) * W + slot * 3;
+        const double f = production(p, y[at], c.Q, light[e]).f * y[at + 2];
+        Phi += g.dz[e] * (p.sig3 * f);
+        if (e == c.k) fk = f;
+    }
+    const double rho = md.rho[((size_t)m * (g.nlayer + 1) + c.nc) * g.nlayer + c.k];
+    const size_t ak = (size_t)(c.rs + c.k) * W + slot * 3;
+    const double D = y[ak + 1], P = y[ak + 2];
+    const double loss = c.k < ne ? p.lam3 * P + p.kap3 * P * P : 0.0;
+    q[0] = -fk + p.lam * D + (1.0 - p.sig) * Phi * rho;
+    q[1] = p.sig * (p.sig3 * fk) + loss - p.lam * D + p.lam3p * P;
+    q[2] = (1.0 - p.sig3) * fk - loss - p.lam3p * P;
+}
+
+__device__ __forceinline__ void bgc_q_phy_tangent(const Grid& g, const Model& md, const double* __restrict__ y,
+                                                  const double* __restrict__ v, int W, const ColumnRef& c, int slot,
+                                                  double* qd) {
+    const int m = md.member[slot];
+    const BgcParams p = load_params(md.u, md.model, md.nparam, m);
+    const double* light = md.light + (size_t)m * g.nlayer;
+    const int ne = c.nc < g.neu ? c.nc : g.neu;
+    double Phid = 0.0, fdk = 0.0;
+    for (int e = 0; e < ne; ++e) {
+        const size_t at = (size_t)(c.rs + e) * W + slot * 3;
+        const Production pr = production(p, y[at], c.Q, light[e]);
+        const double fd = pr.dfdN * v[at] * y[at + 2] + pr.f * v[at + 2];
+        Phid += g.dz[e] * (p.sig3 * fd);
+        if (e == c.k) fdk = fd;
+    }
+    const double rho = md.rho[((size_t)m * (g.nlayer + 1) + c.nc) * g.nlayer + c.k];
+    const size_t ak = (size_t)(c.rs + c.k) * W + slot * 3;
+    const double P = y[ak + 2], Dd = v[ak + 1], Pd = v[ak + 2];
+    const double lossd = c.k < ne ? (p.lam3 + 2.0 * p.kap3 * P) * Pd : 0.0;
+    qd[0] = -fdk + p.lam * Dd + (1.0 - p.sig) * Phid * rho;
+    qd[1] = p.sig * (p.sig3 * fdk) + lossd - p.lam * Dd + p.lam3p * Pd;
+    qd[2] = (1.0 - p.sig3) * fdk - lossd - p.lam3p * Pd;
+}
+
+// Reverse mode of bgc_q_phy for one (row, member): lam += dtd (dq/dy)^T mu for
+// the row's three tracers and contrib += (dq/du)^T mu (unscaled), parameters
+// in the order of the table of section 2.2.2.
+__device__ __forceinline__ void bgc_q_phy_adjoint(const Grid& g, const Model& md, const double* __restrict__ yj,
+                                                  const double* __restrict__ mu, int W, const ColumnRef& c, int slot,
+                                                  double dtd, double* lam, double* contrib) {
+    const int m = md.member[slot];
+    const BgcParams p = load_params(md.u, md.model, md.nparam, m);
+    const double* light = md.light + (size_t)m * g.nlayer;
+    const size_t tab = ((size_t)m * (g.nlayer + 1) + c.nc) * g.nlayer;
+    const int ne = c.nc < g.neu ? c.nc : g.neu;
+    double Phi = 0.0, Phibar = 0.0;
+    for (int e = 0; e < ne; ++e) {
+        const size_t at = (size_t)(c.rs + e) * W + slot * 3;
+        Phi += g.dz[e] * (p.sig3 * (production(p, yj[at], c.Q, light[e]).f * yj[at + 2]));
+    }
+    for (int kk = 0; kk < c.nc; ++kk)
+        Phibar += (1.0 - p.sig) * md.rho[tab + kk] * mu[(size_t)(c.rs + kk) * W + slot * 3];
+    const size_t ak = (size_t)(c.rs + c.k) * W + slot * 3;
+    const double m1 = mu[ak], m2 = mu[ak + 1], m3 = mu[ak + 2];
+    const double D = yj[ak + 1], P = yj[ak + 2];
+    const double rho = md.rho[tab + c.k], drho = md.drho[tab + c.k];
+    double b0 = 0.0, b2 = 0.0;
+    if (c.k < ne) {
+        const Production pr = production(p, yj[ak], c.Q, light[c.k]);
+        const double f = pr.f * P;
+        // f_1 enters q_1 (-1), q_2 (sigma_2 sigma_3), q_3 (1 - sigma_3) and Phi (h_k sigma_3)
+        const double fbar = -m1 + p.sig * p.sig3 * m2 + (1.0 - p.sig3) * m3 + p.sig3 * g.dz[c.k] * Phibar;
+        const double dloss = p.lam3 + 2.0 * p.kap3 * P;
+        b0 = fbar * pr.dfdN * P;
+        b2 = fbar * pr.f + dloss * (m2 - m3);
+        const double Np = yj[ak] > 0.0 ? yj[ak] : 0.0;
+        double zc = 0.0;
+        for (int i = 0; i <= c.k; ++i) zc += g.dz[i];
+        zc -= 0.5 * g.dz[c.k];
+        const double IKI2 = (pr.I + p.ki) * (pr.I + p.ki);
+        contrib[0] += fbar * pr.limN * pr.limI * P;
+        contrib[1] += fbar * p.alpha * pr.limN * p.ki / IKI2 * (-zc * pr.I) * P;
+        contrib[2] += fbar * (-p.alpha * Np / ((Np + p.k1) * (Np + p.k1)) * pr.limI) * P;
+        contrib[3] += fbar * (-p.alpha * pr.limN * pr.I / IKI2) * P;
+        contrib[5] += p.sig3 * f * m2;
+        contrib[6] += P * (m2 - m3);
+        contrib[7] += P * P * (m2 - m3);
+        contrib[9] += f * (p.sig * m2 - m3 + g.dz[c.k] * Phibar);
+    }
+    b2 += p.lam3p * (m2 - m3);
+    contrib[4] += D * (m1 - m2);
+    contrib[5] += -Phi * rho * m1;
+    contrib[8] += P * (m2 - m3);
+    contrib[10] += (1.0 - p.sig) * Phi * drho * m1;
+    lam[0] += dtd * b0;
+    lam[1] += dtd * (p.lam * (m1 - m2));
+    lam[2] += dtd * b2;
+}
+
 // Tangent of bgc_q in direction v.
 __device__ __forceinline__ void bgc_q_tangent(const Grid& g, const Model& md, const double* __restrict__ y,
                                               const double* __restrict__ v, int W, const ColumnRef& c,
@@ -479,6 +595,25 @@ __global__ __launch_bounds__(256) void k_step(Grid g, Model md, Mats mt, int W, 
             }
         }
         // sources: one BGC evaluation per member, both tracers
+        if (md.ntr == 3) {
+            // PO4-DOP-PHY: the sources of each member once, then the thread's columns
+            double qs[3] = {0.0, 0.0, 0.0}, qds[3] = {0.0, 0.0, 0.0};
+            int cur = -1;
+#pragma unroll
+            for (int cc = 0; cc < CW; ++cc) {
+                const int wc = wc0 + cc;
+                if (wc >= W) break;
+                const int slot = wc / 3;
+                if (slot != cur) {
+                    bgc_q_phy(g, md, y, W, c, slot, qs);
+                    if (TANGENT) bgc_q_phy_tangent(g, md, y, v, W, c, slot, qds);
+                    cur = slot;
+                }
+                const int tr = wc % 3;
+                acc[cc] += dtd * qs[tr];
+                if (TANGENT) accd[cc] += dtd * qds[tr];
+            }
+        } else {
 #pragma unroll
         for (int cc = 0; cc < CW; ++cc) {
             const int wc = wc0 + cc;
@@ -512,6 +647,7 @@ __global__ __launch_bounds__(256) void k_step(Grid g, Model md, Mats mt, int W, 
                 acc[cc] += sc * q2;
                 if (TANGENT) accd[cc] += sc * qd2;
             }
+        }
         }
 #pragma unroll
         for (int cc = 0; cc < CW; ++cc) {
@@ -751,7 +887,7 @@ __global__ __launch_bounds__(256) void k_adjoint(Grid g, Model md, Mats mt, int 
                           double* __restrict__ out, double* __restrict__ ubar_tile) {
     extern __shared__ double s_dyn[];
     __shared__ TileLds<MAXR, MAXC> L;
-    constexpr int NP = NTR == 2 ? 7 : 5;
+    constexpr int NP = NTR == 3 ? 11 : (NTR == 2 ? 7 : 5);
     const TileMap tm = build_tile<MAXR, MAXC>(g, L, use_ae ? j % g.nstep : -1);
     double* s_lam = s_dyn;                                  // [nrows][W]
     double* s_contrib = s_dyn + (size_t)tm.nrows * W;       // [blockDim][NP]
@@ -793,7 +929,7 @@ __global__ __launch_bounds__(256) void k_adjoint(Grid g, Model md, Mats mt, int 
 #pragma unroll
                     for (int tr = 0; tr < NTR; ++tr) lam[tr] += a * mu[(size_t)col * W + slot * NTR + tr];
                 }
-                if (SUB) {
+                if constexpr (SUB) {
                     // internal BGC steps: the reverse sweep returns h-weighted sums
                     double yb[NTR];
 #pragma unroll
@@ -801,6 +937,8 @@ __global__ __launch_bounds__(256) void k_adjoint(Grid g, Model md, Mats mt, int 
                     bgc_inc_adjoint<NTR, NP>(g, md, yj, mu, W, c, slot, yb, contrib);
 #pragma unroll
                     for (int tr = 0; tr < NTR; ++tr) lam[tr] += yb[tr];
+                } else if constexpr (NTR == 3) {
+                    bgc_q_phy_adjoint(g, md, yj, mu, W, c, slot, dtd, lam, contrib);
                 } else {
                     // (dq/dy)^T mu and (dq/du)^T mu for this row
                     const int m = md.member[slot];

@@ -352,10 +352,41 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
         // sources from the domain's own rows (no wait needed)
         double q[NTR], qd[TV];
         double sc = dtd;        // internal steps return the increment itself
-        if (SUB) {
+        if constexpr (SUB) {
             sc = 1.0;
             sub_source_lds<NTR, TANGENT, (SUB ? SN : 1), TV>(md, p, Q, ne, k, lr0, light, hz, rho_e, rho, s_y, s_v,
                                                              yr, vr, q, qd);
+        } else if constexpr (NTR == 3) {
+            // PO4-DOP-PHY (section 2.2.2): f_1 grows with PHY, f_3 = sigma_3 f_1 is
+            // exported, PHY losses in the euphotic zone only
+            double Phi = 0.0, fk = 0.0, Phid = 0.0, fdk = 0.0;
+#pragma unroll
+            for (int e = 0; e < kNeuMax; ++e) {
+                if (e < ne) {
+                    const int le = lr0 + e;
+                    const Production pr = production(p, s_y[le * 3], Q, light[e]);
+                    const double f = pr.f * s_y[le * 3 + 2];
+                    Phi += hz[e] * (p.sig3 * f);
+                    if (e == k) fk = f;
+                    if (TANGENT) {
+                        const double fd = pr.dfdN * s_v[le * TV] * s_y[le * 3 + 2] + pr.f * s_v[le * TV + TV - 1];
+                        Phid += hz[e] * (p.sig3 * fd);
+                        if (e == k) fdk = fd;
+                    }
+                }
+            }
+            const double D = yr[1], P = yr[2];
+            const double loss = k < ne ? p.lam3 * P + p.kap3 * P * P : 0.0;
+            q[0] = -fk + p.lam * D + (1.0 - p.sig) * Phi * rho;
+            q[1] = p.sig * (p.sig3 * fk) + loss - p.lam * D + p.lam3p * P;
+            q[2] = (1.0 - p.sig3) * fk - loss - p.lam3p * P;
+            if (TANGENT) {
+                const double Dd = vr[1 % TV], Pd = vr[TV - 1];
+                const double lossd = k < ne ? (p.lam3 + 2.0 * p.kap3 * P) * Pd : 0.0;
+                qd[0] = -fdk + p.lam * Dd + (1.0 - p.sig) * Phid * rho;
+                qd[1 % TV] = p.sig * (p.sig3 * fdk) + lossd - p.lam * Dd + p.lam3p * Pd;
+                qd[TV - 1] = (1.0 - p.sig3) * fdk - lossd - p.lam3p * Pd;
+            }
         } else {
             double Phi = 0.0, fk = 0.0, Phid = 0.0, fdk = 0.0;
 #pragma unroll
@@ -519,7 +550,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     const double* __restrict__ ystore, const double* __restrict__ obs, double src_scale,
     const double* __restrict__ mu_in, double* __restrict__ mu_out, double* __restrict__ buf0,
     double* __restrict__ buf1, double* __restrict__ ubar_dom) {
-    constexpr int NP = NTR == 2 ? 7 : 5;
+    constexpr int NP = NTR == 3 ? 11 : (NTR == 2 ? 7 : 5);
     constexpr bool SUB = SN > 0;
     __shared__ short s_rowcol[TPB];
     __shared__ short s_rowk[TPB];
@@ -658,10 +689,54 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
 
         // (dq/dy)^T mu_j and (dq/du)^T mu_j from the own water column
         double ybar[NTR];
-        if (SUB) {
+        if constexpr (SUB) {
             sub_adjoint_lds<NTR, (SUB ? SN : 1), NP, TPB>(g, md, p, m, j, c0, c1 - c0, s_colr0, s_colnc, tid, k, ne,
                                                           lc, tab, zc, rho, drho, s_y, s_mu, s_traj, s_yb, s_acc,
                                                           s_sphi, yj, mr, ybar, ub);
+        } else if constexpr (NTR == 3) {
+            // PO4-DOP-PHY (section 2.2.2)
+            double Phi = 0.0;
+#pragma unroll
+            for (int e = 0; e < kNeuMax; ++e)
+                if (e < ne) {
+                    const int le = lr0 + e;
+                    Phi += hz[e] * (p.sig3 * (production(p, s_y[le * 3], Q, light[e]).f * s_y[le * 3 + 2]));
+                }
+            const double m1 = mr[0], m2 = mr[1], m3 = mr[2];
+            const double D = yj[1], P = yj[2];
+            ybar[0] = 0.0;
+            ybar[2] = 0.0;
+            if (k < g.neu) {
+                double Phibar = 0.0;
+                for (int kk = 0; kk < nc; ++kk) Phibar += (1.0 - p.sig) * md.rho[tab + kk] * s_mu[(lr0 + kk) * 3];
+                double lk = 0.0;
+#pragma unroll
+                for (int e = 0; e < kNeuMax; ++e)
+                    if (e == k) lk = light[e];
+                const Production pr = production(p, yj[0], Q, lk);
+                const double f = pr.f * P;
+                // f_1 enters q_1 (-1), q_2 (sigma_2 sigma_3), q_3 (1 - sigma_3) and Phi (h_k sigma_3)
+                const double fbar = -m1 + p.sig * p.sig3 * m2 + (1.0 - p.sig3) * m3 + p.sig3 * g.dz[k] * Phibar;
+                const double dloss = p.lam3 + 2.0 * p.kap3 * P;
+                ybar[0] = fbar * pr.dfdN * P;
+                ybar[2] = fbar * pr.f + dloss * (m2 - m3);
+                const double Np = yj[0] > 0.0 ? yj[0] : 0.0;
+                const double IKI2 = (pr.I + p.ki) * (pr.I + p.ki);
+                ub[0] += fbar * pr.limN * pr.limI * P;
+                ub[1] += fbar * p.alpha * pr.limN * p.ki / IKI2 * (-zc * pr.I) * P;
+                ub[2] += fbar * (-p.alpha * Np / ((Np + p.k1) * (Np + p.k1)) * pr.limI) * P;
+                ub[3] += fbar * (-p.alpha * pr.limN * pr.I / IKI2) * P;
+                ub[5] += p.sig3 * f * m2;
+                ub[6] += P * (m2 - m3);
+                ub[7] += P * P * (m2 - m3);
+                ub[9] += f * (p.sig * m2 - m3 + g.dz[k] * Phibar);
+            }
+            ybar[1] = p.lam * (m1 - m2);
+            ybar[2] += p.lam3p * (m2 - m3);
+            ub[4] += D * (m1 - m2);
+            ub[5] += -Phi * rho * m1;
+            ub[8] += P * (m2 - m3);
+            ub[10] += (1.0 - p.sig) * Phi * drho * m1;
         } else {
             double Phi = 0.0;
 #pragma unroll

@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(HERE, "libtmm.so")
 TMM_OK = 0
 TMM_MODEL_N = 1
 TMM_MODEL_NDOP = 2
+TMM_MODEL_NDOPPHY = 3
+_NTRACER = {TMM_MODEL_N: 1, TMM_MODEL_NDOP: 2, TMM_MODEL_NDOPPHY: 3}
+_NPARAM = {TMM_MODEL_N: 5, TMM_MODEL_NDOP: 7, TMM_MODEL_NDOPPHY: 11}
 TMM_JVP_FD = 0
 TMM_JVP_TANGENT = 1
 TMM_JVP_FD_GIVEN_PHI = 2
@@ -192,8 +195,8 @@ class TMM:
         a = arrays
         self.n = int(a["n"])
         self.model = int(a["model"])
-        self.ntracer = 1 if self.model == TMM_MODEL_N else 2
-        self.nparam = 5 if self.model == TMM_MODEL_N else 7
+        self.ntracer = _NTRACER[self.model]
+        self.nparam = _NPARAM[self.model]
         self.nstep = int(a["nstep"])
         self.nmat = int(a["nmat"])
         self.ckpt_every = int(ckpt_every)

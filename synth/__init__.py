@@ -12,7 +12,7 @@ structure:
 * ``params``    -- biogeochemical parameter vectors, bounds, Latin-hypercube
                    ensembles, spin-up lengths and observation noise.
 * ``workloads`` -- the named workloads (tiny 16x8x4, global 128x64x15,
-                   ensemble 256x128x23).
+                   ensemble 256x128x23, one degree 360x180x23).
 
 Nothing here evaluates the time step, the biogeochemical model or any
 derivative of them: both the reference implementation and the GPU library
@@ -25,4 +25,4 @@ from .params import (  # noqa: F401
     MODEL_N, MODEL_NDOP, MODEL_NDOPPHY, NTRACER, NPARAM, PARAM_NAMES,
     nominal, bounds, latin_hypercube, spinup_lengths, hidden_params, obs_noise,
 )
-from .workloads import Inputs, tiny, small_ndop, global_2p8, ensemble_1p4, by_name  # noqa: F401
+from .workloads import Inputs, tiny, small_ndop, global_2p8, ensemble_1p4, one_degree, by_name  # noqa: F401

@@ -66,7 +66,7 @@ def test_invalid_descriptors_are_rejected(tiny_n):
     cross = tm.ai_colidx.copy()
     cross[0] = tiny_n.grid.col_start[1]                                   # couples two columns
     for over in ({"ae_rowptr": bad_rowptr}, {"ae_colidx": bad_col}, {"ai_colidx": cross},
-                 {"nstep": 2876}, {"nmat": 7}, {"model": 3}, {"neuphotic": 0},
+                 {"nstep": 2876}, {"nmat": 7}, {"model": 4}, {"neuphotic": 0},
                  {"ckpt_every": 7}, {"nbatch_max": 0}, {"adjoint_nbatch_max": 2}, {"nbgc": -1}, {"nbgc": 17},
                  {"dz": np.r_[tiny_n.grid.dz[:-1], -1.0]}):
         d, _ = _desc(tiny_n, **over)
@@ -83,6 +83,16 @@ def test_internal_bgc_steps_in_descriptor(small_ndop):
     assert _status(d)[0] == -6
     d, _ = _desc(small_ndop, nbgc=1, neuphotic=5)
     assert _status(d)[0] == 0
+
+
+def test_po4_dop_phy_descriptor():
+    """Three tracers are accepted; internal BGC steps are not supported with them."""
+    import synth
+    inp = synth.tiny(model=synth.MODEL_NDOPPHY)
+    d, _ = _desc(inp)
+    assert _status(d)[0] == 0
+    d, _ = _desc(inp, nbgc=8)
+    assert _status(d)[0] == -6
 
 
 def test_strerror():

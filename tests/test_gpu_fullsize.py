@@ -1,10 +1,13 @@
-"""GPU parity at the benchmark's full sizes, in the launch configurations bench.py times.
+"""GPU parity at full sizes, in the launch configurations bench.py times.
 
 * global 128x64x15 (52749 points): the checkpointed adjoint of one model year
   (persistent kernels, checkpoints every 240 steps) against the oracle's
   full-trajectory reverse mode;
 * ensemble 256x128x23 (500000 points, 64 members, W = 128): steps of the
-  member-parallel kernel against the oracle's step, all outputs compared.
+  member-parallel kernel against the oracle's step, all outputs compared;
+* 1.0-degree stand-in 360x180x23 (760000 points): a month of steps of the
+  launch-per-step path against the oracle, and phosphorus conservation over
+  one model year (a property that holds at any size).
 """
 
 import numpy as np
@@ -55,3 +58,28 @@ def test_ensemble_steps_against_oracle():
         got = t.step(j, t.state(y)).cpu().numpy()
         exp = o.step(U, j, y)
         assert _rel(got, exp) <= 1e-14, j
+
+
+def test_one_degree_month_and_conservation():
+    """1.0-degree stand-in (360x180x23, 760000 points): 240 consecutive steps (one month, launch-per-step
+    path) against the oracle, then one GPU model year conserves volume-weighted phosphorus."""
+    from paper_1410_0204_amd import tmm
+    inp = synth.one_degree()
+    u = synth.nominal(inp.model)
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=1)
+    t.set_params(u)
+    o = oracle.Oracle(inp)
+    rng = np.random.default_rng(9)
+    y = inp.initial_state() * rng.uniform(0.8, 1.2, size=(inp.n, 2))
+    yd = t.state(y)
+    print("[gpu] 240 steps on the 1-degree grid against the oracle (~20 s)", flush=True)
+    for j in range(1320, 1560):
+        yd = t.step(j, yd)
+        y = o.step(u, j, y)
+    assert _rel(yd.cpu().numpy(), y) <= 1e-13
+    y0 = inp.initial_state()
+    y1, _ = t.year(t.state(y0))
+    V = inp.grid.volumes()
+    m0 = V @ y0.sum(1)
+    m1 = V @ y1.cpu().numpy().sum(1)
+    assert abs(m1 - m0) <= 1e-12 * m0

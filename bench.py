@@ -175,10 +175,16 @@ def main():
         ratio = ms_adj / ms_fwd1
         log(f"[bench] adjoint year {ms_adj:.2f} ms vs forward {ms_fwd1:.2f} ms: ratio {ratio:.2f}")
 
-    # the same workload with 8 internal BGC steps per ocean step (section 7)
-    substeps = None
+    # the same grid with 8 internal BGC steps per ocean step (section 7), and
+    # with the three-tracer PO4-DOP-PHY model (section 2.2.2)
+    substeps = phy = None
     if not args.forward_only:
-        substeps = bench_substeps(args, inp, u, obs, dev, stream, ms_per_year)
+        import dataclasses
+        substeps = bench_variant(args, dataclasses.replace(inp, nbgc=8), dev, stream, ms_per_year,
+                                 "8 internal BGC steps")
+        substeps["nbgc"] = 8
+        phy = bench_variant(args, synth.global_2p8(model=synth.MODEL_NDOPPHY), dev, stream, ms_per_year,
+                            "PO4-DOP-PHY")
 
     cpu = None
     if not args.no_cpu_baseline and not args.forward_only:
@@ -218,22 +224,22 @@ def main():
         "per_step_path": per_step,
         "adjoint_forward_ratio": ratio,
         "bgc_substeps_8": substeps,
+        "po4_dop_phy": phy,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     t.close()
 
 
-def bench_substeps(args, inp, u, obs, dev, stream, ms_plain, nbgc=8):
-    """Forward model years and the adjoint with nbgc internal BGC steps per
-    ocean step on the same workload, against one evaluation per step."""
-    import dataclasses
+def bench_variant(args, inp, dev, stream, ms_plain, label):
+    """Forward model years and the adjoint of a model variant on the same grid
+    (internal BGC steps, or another BGC model), against the headline forward."""
     import torch
     from paper_1410_0204_amd import tmm
-    sub = dataclasses.replace(inp, nbgc=nbgc)
-    t = tmm.TMM(sub.desc_arrays(), nbatch_max=1, adjoint_nbatch_max=1, ckpt_every=240, device=dev, stream=stream)
-    t.set_params(u)
-    y0 = t.state(sub.initial_state())
+    import synth
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=1, adjoint_nbatch_max=1, ckpt_every=240, device=dev, stream=stream)
+    t.set_params(synth.nominal(inp.model))
+    y0 = t.state(inp.initial_state())
     ya = t.state()
     t.year(y0, nyears=1, out=ya, residuals=False)
     torch.cuda.synchronize()
@@ -244,6 +250,9 @@ def bench_substeps(args, inp, u, obs, dev, stream, ms_plain, nbgc=8):
     stop.record(stream)
     torch.cuda.synchronize()
     ms_fwd = start.elapsed_time(stop) / years
+    shape = (inp.nmat, inp.n, inp.ntracer)
+    obs = torch.as_tensor(np.broadcast_to(inp.initial_state(), shape).copy()
+                          * (1 + 0.05 * synth.obs_noise(shape, seed=3))).to(dev)
     t.year_adjoint(y0, obs, want_dy0=False)
     torch.cuda.synchronize()
     start.record(stream)
@@ -251,11 +260,11 @@ def bench_substeps(args, inp, u, obs, dev, stream, ms_plain, nbgc=8):
     stop.record(stream)
     torch.cuda.synchronize()
     ms_adj = start.elapsed_time(stop)
-    rec = {"nbgc": nbgc, "ms_per_year": ms_fwd, "model_years_per_s": 1000.0 / ms_fwd,
-           "cost_vs_one_evaluation": ms_fwd / ms_plain, "adjoint_ms": ms_adj,
-           "adjoint_forward_ratio": ms_adj / ms_fwd,
+    rec = {"ms_per_year": ms_fwd, "model_years_per_s": 1000.0 / ms_fwd,
+           "cost_vs_headline": ms_fwd / ms_plain, "adjoint_ms": ms_adj, "adjoint_forward_ratio": ms_adj / ms_fwd,
+           "forward_path": "k_year_persistent" if t.query(tmm.TMM_Q_PERSISTENT) else "k_step",
            "adjoint_path": "k_adjoint_persistent" if t.query(tmm.TMM_Q_PERSISTENT_ADJOINT) else "k_adjoint"}
-    log(f"[bench] {nbgc} internal BGC steps: {ms_fwd:.3f} ms/model-year ({ms_fwd / ms_plain:.2f}x), "
+    log(f"[bench] {label}: {ms_fwd:.3f} ms/model-year ({ms_fwd / ms_plain:.2f}x), "
         f"adjoint {ms_adj:.2f} ms (ratio {ms_adj / ms_fwd:.2f}, {rec['adjoint_path']})")
     t.close()
     return rec
@@ -329,7 +338,8 @@ def bench_grids(args):
 
 def bench_newton(args):
     """Steady periodic solution of the global grid by Newton-Krylov (FD and
-    tangent JVPs), and spin-up for the same number of model years."""
+    tangent JVPs with the line search, tangent with the trust region), and
+    spin-up for the same number of model years."""
     import torch
     import synth
     from paper_1410_0204_amd import drivers, tmm
@@ -339,16 +349,17 @@ def bench_newton(args):
     u = synth.nominal(inp.model)
     y0 = inp.initial_state()
     out = {"mode": "newton", "workload": "global_128x64x15 N-DOP", "tol": 1e-8, "restart": 30}
-    for jvp in ("fd", "tangent"):
+    for jvp, glob in (("fd", "line_search"), ("tangent", "line_search"), ("tangent", "trust_region")):
+        key = jvp if glob == "line_search" else f"{jvp}_trust_region"
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         y, hist = drivers.newton_krylov(t, u, y0, tol=1e-8, jvp=jvp, restart=30, max_newton=args.steps,
-                                        max_krylov=300, log_path=args.log)
+                                        max_krylov=300, log_path=args.log, globalization=glob)
         dt = time.perf_counter() - t0
-        out[jvp] = {"fnorm": hist["fnorm"], "year_maps": hist["years"], "seconds": dt,
+        out[key] = {"fnorm": hist["fnorm"], "year_maps": hist["years"], "seconds": dt,
                     "newton_iterations": len(hist["newton"]),
                     "krylov_per_newton": [r["krylov"] for r in hist["newton"]]}
-        log(f"[newton/{jvp}] |F| {hist['fnorm'][0]:.3e} -> {hist['fnorm'][-1]:.3e} in {len(hist['newton'])} "
+        log(f"[newton/{key}] |F| {hist['fnorm'][0]:.3e} -> {hist['fnorm'][-1]:.3e} in {len(hist['newton'])} "
             f"Newton steps, {hist['years']} year maps, {dt:.1f} s")
     years = out["fd"]["year_maps"]
     t0 = time.perf_counter()

@@ -3,8 +3,9 @@
 These follow sections 4, 6 and 7 of the paper.  A periodic solution is a
 fixed point of the year map phi (section 4).  Spin-up finds it by the plain
 iteration y <- phi(y) and logs ||y - phi(y)||_2 each year (section 7).  The
-Newton solver works on F(y) = y - phi(y) with a globalising backtracking line
-search (section 6).  Its linear systems are solved matrix-free by restarted
+Newton solver works on F(y) = y - phi(y), globalised either by a backtracking
+line search with cubic interpolation or by a trust region (the two basic
+techniques of section 6, after Dennis and Schnabel).  Its linear systems are solved matrix-free by restarted
 GMRES with modified Gram-Schmidt and inexact-Newton forcing terms after
 Eisenstat and Walker (section 6.2).  Jacobian-vector products come from
 libtmm, either as finite differences or as the exact tangent (section 6.1).
@@ -143,17 +144,31 @@ def gmres(matvec, b, rtol, restart=30, maxiter=300, log=None):
 # ---------------------------------------------------------------------------
 
 def newton_krylov(t, u, y0, tol=1e-8, jvp="fd", restart=30, max_newton=30, max_krylov=300,
-                  eta0=0.5, eta_max=0.9, gamma=0.9, ew_alpha=2.0, line_search=True, log_path=None):
+                  eta0=0.5, eta_max=0.9, gamma=0.9, ew_alpha=2.0, line_search=True, log_path=None,
+                  globalization="line_search", delta0=0.2, delta_max=1e10):
     """Solves F(y) = y - phi(y) = 0 from y0 until ||F|| <= tol.
 
     Linear systems (I - phi'(y)) d = -F by GMRES(restart) with forcing terms
     eta_k = gamma (|F_k|/|F_{k-1}|)^ew_alpha (Eisenstat-Walker choice 2,
     safeguarded, capped at eta_max).  ``jvp`` is "fd" (finite differences
     reusing phi(y): one model year per product) or "tangent" (exact).
-    Backtracking on |F|^2 with quadratic/cubic interpolation (Dennis and
-    Schnabel) when ``line_search``.  Returns (y, history); history counts
-    year maps (tangent years count 1 each).
+
+    ``globalization`` = "line_search": backtracking on |F|^2 with
+    quadratic/cubic interpolation (Dennis and Schnabel); ``line_search=False``
+    takes full steps.  "trust_region": the step is the inexact Newton step d
+    cut back to the radius Delta (s = min(1, Delta/|d|) d); with r the GMRES
+    residual (J d = -F - r) the linear model predicts |F + J s|^2 =
+    |(1 - tau) F - tau r|^2 without another product; the step is accepted
+    when the actual reduction of |F|^2 is at least 1e-4 of the predicted one,
+    and Delta shrinks to |s|/4 when their ratio is below 1/4 and doubles
+    (up to ``delta_max``) when it exceeds 3/4 on the boundary.  The first
+    radius is ``delta0`` * max(|y0|, 1).
+
+    Returns (y, history); history counts year maps (tangent years count 1
+    each).
     """
+    if globalization not in ("line_search", "trust_region"):
+        raise ValueError("globalization must be 'line_search' or 'trust_region'")
     u = np.atleast_2d(np.asarray(u, dtype=np.float64))
     t.set_params(u)
     shape = (t.n, t.W)
@@ -173,6 +188,7 @@ def newton_krylov(t, u, y0, tol=1e-8, jvp="fd", restart=30, max_newton=30, max_k
     hist = {"newton": [], "years": 0, "fnorm": [fnorm]}
     _log(log_path, {"kind": "newton", "it": 0, "fnorm": fnorm, "years": years})
     eta_prev, fnorm_prev = eta0, None
+    delta = delta0 * max(float(np.linalg.norm(y)), 1.0)
     for it in range(1, max_newton + 1):
         if fnorm <= tol:
             break
@@ -200,6 +216,36 @@ def newton_krylov(t, u, y0, tol=1e-8, jvp="fd", restart=30, max_newton=30, max_k
 
         d, rlin, mv = gmres(matvec, -F, eta, restart=restart, maxiter=max_krylov)
         lres = float(np.linalg.norm(rlin))
+        if globalization == "trust_region":
+            dnorm = float(np.linalg.norm(d))
+            rejected = 0
+            while True:
+                tau = min(1.0, delta / dnorm) if dnorm > 0.0 else 1.0
+                y_try = y + tau * d.reshape(shape)
+                yt = t.state(y_try)
+                F_try = F_of(y_try, yt, phi_try)
+                model = (1.0 - tau) * F - tau * rlin          # F + J s of the linear model
+                pred = fnorm ** 2 - float(np.dot(model, model))
+                ared = fnorm ** 2 - float(np.dot(F_try, F_try))
+                ratio = ared / pred if pred > 0.0 else -1.0
+                snorm = tau * dnorm
+                if ratio < 0.25:
+                    delta = 0.25 * snorm
+                elif ratio > 0.75 and tau < 1.0:
+                    delta = min(2.0 * delta, delta_max)
+                if ratio >= 1e-4 or snorm < 1e-12 * max(float(np.linalg.norm(y)), 1.0):
+                    break
+                rejected += 1
+            y, yd, F = y_try, yt, F_try
+            phi, phi_try = phi_try, phi
+            fnorm_prev, eta_prev = fnorm, eta
+            fnorm = float(np.linalg.norm(F))
+            rec = {"kind": "newton", "it": it, "fnorm": fnorm, "eta": eta, "krylov": mv, "tau": tau,
+                   "delta": delta, "rho": ratio, "rejected": rejected, "linear_residual": lres, "years": years}
+            hist["newton"].append(rec)
+            hist["fnorm"].append(fnorm)
+            _log(log_path, rec)
+            continue
         # line search on f = |F|^2 / 2; J d = -F - r, so the slope is F.(J d) = -|F|^2 - F.r
         lam, f0 = 1.0, 0.5 * fnorm ** 2
         slope = -fnorm ** 2 - float(np.dot(F, rlin))

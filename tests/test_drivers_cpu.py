@@ -92,6 +92,63 @@ def test_newton_krylov_reaches_fixed_point(tiny_ndop, jvp):
     assert hist["fnorm"][-1] <= 1e-8 and hist["years"] > 0
 
 
+class AtanHandle:
+    """Toy year map phi(y) = y - atan(y - c) on one 'point', so F(y) = atan(y - c): full Newton
+    steps diverge from |y - c| >= 1.39 (the textbook example), a globalised Newton converges."""
+
+    n, nstep, nmat, model, ntracer = 3, 1, 1, 1, 1
+
+    def __init__(self, c):
+        self.c = np.asarray(c, dtype=np.float64).reshape(3, 1)
+        self.nbatch = 1
+
+    @property
+    def W(self):
+        return 1
+
+    def set_params(self, u):
+        pass
+
+    def state(self, host=None):
+        return torch.as_tensor(np.array(host, dtype=np.float64)) if host is not None else \
+            torch.zeros((3, 1), dtype=torch.float64)
+
+    def year(self, y, nyears=1, years_per_member=None, out=None, residuals=True):
+        yy = y.numpy()
+        out.copy_(torch.as_tensor(yy - np.arctan(yy - self.c)))
+        return out, None
+
+    def year_jvp(self, y, v, mode=T.TMM_JVP_TANGENT, want_phi=True, phi=None):
+        yy, vv = y.numpy(), v.numpy()
+        return None, torch.as_tensor(vv - vv / (1.0 + (yy - self.c) ** 2))
+
+
+def test_trust_region_converges_where_full_newton_steps_diverge():
+    c = [0.5, -1.0, 2.0]
+    y0 = np.array(c).reshape(3, 1) + 3.0
+    h = AtanHandle(c)
+    y, hist = drivers.newton_krylov(h, [0.0], y0, tol=1e-12, jvp="tangent", max_newton=40,
+                                    globalization="trust_region", delta0=0.5)
+    assert np.abs(y.ravel() - np.array(c)).max() <= 1e-12
+    assert any(rec["tau"] < 1.0 for rec in hist["newton"])          # the radius was active
+    _, full = drivers.newton_krylov(h, [0.0], y0, tol=1e-12, jvp="tangent", max_newton=3, line_search=False)
+    assert full["fnorm"][-1] > full["fnorm"][0]                     # undamped Newton moves away
+
+
+@pytest.mark.parametrize("delta0", [0.2, 1e-4])
+def test_trust_region_newton_reaches_the_same_fixed_point(tiny_ndop, delta0):
+    h = OracleHandle(tiny_ndop)
+    u = synth.nominal(synth.MODEL_NDOP)
+    y0 = tiny_ndop.initial_state()
+    y, hist = drivers.newton_krylov(h, u, y0, tol=1e-8, jvp="tangent", max_newton=30, max_krylov=200,
+                                    globalization="trust_region", delta0=delta0)
+    assert hist["fnorm"][-1] <= 1e-8
+    y_ls, _ = drivers.newton_krylov(h, u, y0, tol=1e-8, jvp="tangent", max_newton=12, max_krylov=200)
+    assert np.abs(y - y_ls).max() <= 1e-7 * np.abs(y_ls).max()
+    if delta0 < 1e-3:
+        assert hist["newton"][0]["tau"] < 1.0
+
+
 def test_spinup_residual_decreases_and_resumes(tiny_ndop, tmp_path):
     h = OracleHandle(tiny_ndop)
     u = synth.nominal(synth.MODEL_NDOP)

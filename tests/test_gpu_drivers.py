@@ -95,3 +95,16 @@ def test_autotuner_picks_a_validated_configuration(small_ndop, tmp_path):
         got, _ = t.year(t.state(inp.initial_state(nb)))
         exp, _ = oracle.Oracle(inp).year(U, inp.initial_state(nb))
         assert np.abs(got.cpu().numpy() - exp).max() <= 1e-12 * np.abs(exp).max()
+
+
+def test_trust_region_newton_on_gpu(tiny_ndop):
+    from paper_1410_0204_amd import drivers
+    tmm = _tmm()
+    inp = tiny_ndop
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=1)
+    u = synth.nominal(inp.model)
+    y, hist = drivers.newton_krylov(t, u, inp.initial_state(), tol=1e-8, jvp="tangent", max_newton=20,
+                                    globalization="trust_region", delta0=1e-3)
+    phi, _ = oracle.Oracle(inp).year(u, y)
+    assert np.linalg.norm(y - phi) <= 2e-8
+    assert hist["fnorm"][-1] <= 1e-8 and hist["newton"][0]["tau"] < 1.0

@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="forward", choices=["forward", "newton", "ensemble", "copy", "grids"])
     ap.add_argument("--log", default=None, help="JSONL progress log (newton mode)")
+    ap.add_argument("--grid-steps", type=int, default=0,
+                    help="grids mode: time this many single steps per grid instead of model years")
     ap.add_argument("--forward-only", action="store_true",
                     help="skip the per-step comparison and the adjoint (for hardware counter runs)")
     args = ap.parse_args()
@@ -314,16 +316,28 @@ def bench_grids(args):
         t.set_params(synth.nominal(inp.model))
         y0 = t.state(inp.initial_state())
         ya = t.state()
-        t.year(y0, nyears=1, out=ya, residuals=False)
-        torch.cuda.synchronize()
         s, e = _events()
-        years = 2
-        s.record(stream)
-        t.year(y0, nyears=years, out=ya, residuals=False)
-        e.record(stream)
-        torch.cuda.synchronize()
-        ms = s.elapsed_time(e) / years
-        us_step = ms * 1000.0 / inp.nstep
+        if args.grid_steps > 0:
+            # a few single steps only (hardware-counter passes serialise every launch)
+            yb = t.step(0, y0)
+            torch.cuda.synchronize()
+            s.record(stream)
+            for j in range(args.grid_steps):
+                yb = t.step(j % inp.nstep, yb)
+            e.record(stream)
+            torch.cuda.synchronize()
+            us_step = s.elapsed_time(e) * 1000.0 / args.grid_steps
+            ms = us_step * inp.nstep / 1000.0
+        else:
+            t.year(y0, nyears=1, out=ya, residuals=False)
+            torch.cuda.synchronize()
+            years = 2
+            s.record(stream)
+            t.year(y0, nyears=years, out=ya, residuals=False)
+            e.record(stream)
+            torch.cuda.synchronize()
+            ms = s.elapsed_time(e) / years
+            us_step = ms * 1000.0 / inp.nstep
         rec = {"workload": inp.name, "n": inp.n, "nnz_explicit": inp.tm.ae_nnz, "nnz_implicit": inp.tm.ai_nnz,
                "bytes_per_step": B, "ms_per_year": ms, "model_years_per_s": 1000.0 / ms, "us_per_step": us_step,
                "GB_per_s": B / (us_step * 1e-6) / 1e9, "frac_of_peak": B / (us_step * 1e-6) / 1e9 / HBM_PEAK_GBPS}

@@ -352,8 +352,9 @@ def bench_grids(args):
 
 def bench_newton(args):
     """Steady periodic solution of the global grid by Newton-Krylov (FD and
-    tangent JVPs with the line search, tangent with the trust region), and
-    spin-up for the same number of model years."""
+    tangent JVPs with the line search, tangent with the trust region, tangent
+    with the transport preconditioner), and spin-up for the same number of
+    model years."""
     import torch
     import synth
     from paper_1410_0204_amd import drivers, tmm
@@ -363,12 +364,15 @@ def bench_newton(args):
     u = synth.nominal(inp.model)
     y0 = inp.initial_state()
     out = {"mode": "newton", "workload": "global_128x64x15 N-DOP", "tol": 1e-8, "restart": 30}
-    for jvp, glob in (("fd", "line_search"), ("tangent", "line_search"), ("tangent", "trust_region")):
+    for jvp, glob, pre in (("fd", "line_search", None), ("tangent", "line_search", None),
+                           ("tangent", "trust_region", None), ("tangent", "line_search", "transport")):
         key = jvp if glob == "line_search" else f"{jvp}_trust_region"
+        key = key if pre is None else f"{key}_preconditioned"
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         y, hist = drivers.newton_krylov(t, u, y0, tol=1e-8, jvp=jvp, restart=30, max_newton=args.steps,
-                                        max_krylov=300, log_path=args.log, globalization=glob)
+                                        max_krylov=300, log_path=args.log, globalization=glob,
+                                        preconditioner=pre)
         dt = time.perf_counter() - t0
         out[key] = {"fnorm": hist["fnorm"], "year_maps": hist["years"], "seconds": dt,
                     "newton_iterations": len(hist["newton"]),

@@ -25,4 +25,4 @@ from .params import (  # noqa: F401
     MODEL_N, MODEL_NDOP, MODEL_NDOPPHY, NTRACER, NPARAM, PARAM_NAMES,
     nominal, bounds, latin_hypercube, spinup_lengths, hidden_params, obs_noise,
 )
-from .workloads import Inputs, tiny, small_ndop, global_2p8, ensemble_1p4, one_degree, by_name  # noqa: F401
+from .workloads import Inputs, tiny, small_ndop, global_2p8, ensemble_1p4, one_degree, custom, by_name  # noqa: F401

@@ -109,6 +109,16 @@ def small_ndop(seed: int = 5, nstep: int = 2880, model: int = MODEL_NDOP) -> Inp
     return _build("small_32x16x8", 32, 16, 8, 400, 2700, model, 2, Y_INIT[model], seed, nstep=nstep)
 
 
+def custom(nlon: int, nlat: int, nlayer: int, ncol: int, n: int, model: int = MODEL_NDOP, neuphotic: int = 2,
+           seed: int = 3, nmat: int = 12, nstep: int = 2880, nbgc: int = 1) -> Inputs:
+    """Any grid shape built like the named workloads (for edge cases: single points, shallow or
+    deep columns, short years, one matrix)."""
+    inp = _build(f"custom_{nlon}x{nlat}x{nlayer}", nlon, nlat, nlayer, ncol, n, model, neuphotic, Y_INIT[model],
+                 seed, nmat=nmat, nstep=nstep)
+    inp.nbgc = nbgc
+    return inp
+
+
 def by_name(name: str) -> Inputs:
     table = {"tiny": tiny, "global": global_2p8, "ensemble": ensemble_1p4, "small": small_ndop,
              "one_degree": one_degree}

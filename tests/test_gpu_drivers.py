@@ -108,3 +108,17 @@ def test_trust_region_newton_on_gpu(tiny_ndop):
     phi, _ = oracle.Oracle(inp).year(u, y)
     assert np.linalg.norm(y - phi) <= 2e-8
     assert hist["fnorm"][-1] <= 1e-8 and hist["newton"][0]["tau"] < 1.0
+
+
+def test_preconditioned_newton_on_gpu(tiny_ndop):
+    from paper_1410_0204_amd import drivers
+    tmm = _tmm()
+    inp = tiny_ndop
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=1)
+    u = synth.nominal(inp.model)
+    y, hist = drivers.newton_krylov(t, u, inp.initial_state(), tol=1e-8, jvp="tangent", max_newton=20,
+                                    preconditioner="transport")
+    phi, _ = oracle.Oracle(inp).year(u, y)
+    assert np.linalg.norm(y - phi) <= 2e-8
+    V = inp.grid.volumes()
+    assert (V @ y.sum(1)) == pytest.approx(V @ inp.initial_state().sum(1), rel=1e-10)

@@ -1,0 +1,118 @@
+"""GPU parity on degenerate and extreme inputs, against the oracle.
+
+* a grid of one wet point (one column of one layer, one workgroup, one domain);
+* a grid whose columns are all no deeper than the euphotic zone (every export
+  remineralised in a bottom layer);
+* the shortest year the month interpolation allows (24 steps: two per month,
+  the month pair changes every other step) and a single monthly matrix
+  (nmat = 1, no interpolation, two steps a year);
+* 24-layer columns (the persistent kernels with 32-entry column blocks and
+  256-thread workgroups) and 64-layer columns (the deepest the library takes:
+  launch-per-step kernels only);
+* zero model years (the state comes back unchanged).
+Each case runs steps, a year on every available path, the tangent and the
+adjoint, to the usual tolerances.  With fewer steps per year the rates
+(alpha, lambda'_2) are scaled by nstep/2880 so that dt times each rate is that
+of the standard configuration; otherwise the explicit Euler production
+overshoots, N goes negative and rounding differences grow without bound.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "point": dict(nlon=1, nlat=1, nlayer=1, ncol=1, n=1, neuphotic=1),
+    "shallow": dict(nlon=8, nlat=4, nlayer=2, ncol=20, n=33, neuphotic=2),
+    "short_year": dict(nlon=8, nlat=4, nlayer=4, ncol=20, n=50, nstep=24),
+    "one_matrix": dict(nlon=8, nlat=4, nlayer=4, ncol=20, n=50, nmat=1, nstep=2),
+    "deep24": dict(nlon=32, nlat=16, nlayer=24, ncol=300, n=5000),
+    "deep64": dict(nlon=8, nlat=8, nlayer=64, ncol=40, n=1800),
+}
+CKPT = {"short_year": 4, "one_matrix": 1}
+
+
+def _tmm():
+    from paper_1410_0204_amd import tmm
+    return tmm
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def inputs():
+    return {k: synth.custom(**kw) for k, kw in CASES.items()}
+
+
+def _params(inp, u=None):
+    u = synth.nominal(inp.model) if u is None else u.copy()
+    u[0] *= inp.nstep / 2880.0
+    u[4] *= inp.nstep / 2880.0
+    return u
+
+
+def _make(inp, name, adjoint=0):
+    print(f"[gpu] create {name} n={inp.n} nlayer={inp.grid.nlayer} nstep={inp.nstep} nmat={inp.nmat}", flush=True)
+    ckpt = CKPT.get(name, 240)
+    return _tmm().TMM(inp.desc_arrays(), nbatch_max=1, adjoint_nbatch_max=adjoint, ckpt_every=ckpt)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_edge_steps_and_years(inputs, name):
+    tmm = _tmm()
+    inp = inputs[name]
+    t = _make(inp, name)
+    o = oracle.Oracle(inp)
+    u = _params(inp)
+    t.set_params(u)
+    rng = np.random.default_rng(7)
+    y = inp.initial_state() * rng.uniform(0.5, 1.5, size=(inp.n, inp.ntracer))
+    for j in sorted({0, 1, inp.nstep // 2, inp.nstep - 1}):
+        assert _rel(t.step(j, t.state(y)).cpu().numpy(), o.step(u, j, y)) <= 1e-14, j
+    exp, re = o.year(u, y, 2)
+    paths = [1, 0] if t.query(tmm.TMM_Q_PERSISTENT) else [0]
+    if name == "deep24":
+        assert paths == [1, 0]        # the persistent kernels with 32-entry blocks are exercised
+    if name == "deep64":
+        assert paths == [0]
+    for pers in paths:
+        t.set_option(tmm.TMM_OPT_PERSISTENT, pers)
+        got, r = t.year(t.state(y), nyears=2)
+        assert _rel(got.cpu().numpy(), exp) <= 1e-12, pers
+        # a residual near zero is rounding noise: compare it against the state's size
+        assert np.abs(r - re).max() <= 1e-9 * np.abs(re).max() + 1e-12 * np.linalg.norm(exp), pers
+    same, _ = t.year(t.state(y), nyears=0)
+    assert np.array_equal(same.cpu().numpy(), y)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_edge_tangent_and_adjoint(inputs, name):
+    import torch
+    tmm = _tmm()
+    inp = inputs[name]
+    o = oracle.Oracle(inp)
+    u = _params(inp)
+    rng = np.random.default_rng(8)
+    y = inp.initial_state() * rng.uniform(0.8, 1.2, size=(inp.n, inp.ntracer))
+    v = rng.standard_normal(y.shape) * y
+    _, ejv = o.year_tangent(u, y, v)
+    snaps = o.snapshots(_params(inp, synth.hidden_params(inp.model, seed=21)), inp.initial_state())
+    obs = snaps * (1 + 0.05 * synth.obs_noise(snaps.shape, seed=22))
+    eJ, eG, eY = o.year_adjoint(u, inp.initial_state(), obs)
+    t = _make(inp, name, adjoint=1)
+    t.set_params(u)
+    paths = [1, 0] if t.query(tmm.TMM_Q_PERSISTENT) else [0]
+    for pers in paths:
+        t.set_option(tmm.TMM_OPT_PERSISTENT, pers)
+        _, jv = t.year_jvp(t.state(y), t.state(v), mode=tmm.TMM_JVP_TANGENT)
+        assert _rel(jv.cpu().numpy(), ejv) <= 1e-11, pers
+        J, G, dy0 = t.year_adjoint(t.state(inp.initial_state()), torch.as_tensor(obs).cuda())
+        assert J[0] == pytest.approx(eJ[0], rel=1e-12), pers
+        assert _rel(G, eG) <= 1e-10, pers
+        assert _rel(dy0.cpu().numpy(), eY) <= 1e-10, pers

@@ -82,7 +82,7 @@ def main():
     ap.add_argument("--mode", default="forward", choices=["forward", "newton", "ensemble", "copy", "grids"])
     ap.add_argument("--log", default=None, help="JSONL progress log (newton mode)")
     ap.add_argument("--grid-steps", type=int, default=0,
-                    help="grids mode: time this many single steps per grid instead of model years")
+                    help="grids / ensemble modes: time this many single steps instead of model years")
     ap.add_argument("--forward-only", action="store_true",
                     help="skip the per-step comparison and the adjoint (for hardware counter runs)")
     args = ap.parse_args()
@@ -409,6 +409,21 @@ def bench_ensemble(args):
     # warm-up: one step at full width
     t.step(0, y0)
     torch.cuda.synchronize()
+    W = 2 * nm
+    B = bytes_per_step(inp.n, inp.tm.ae_nnz, inp.tm.ai_nnz, W)
+    if args.grid_steps > 0:
+        # full-width steps only (for hardware-counter passes, which serialise every launch)
+        yb = y0
+        s.record()
+        for j in range(args.grid_steps):
+            yb = t.step(j % inp.nstep, yb)
+        e.record()
+        torch.cuda.synchronize()
+        us = s.elapsed_time(e) * 1000.0 / args.grid_steps
+        log(f"[ensemble] {args.grid_steps} full-width steps: {us:.1f} us/step, {B / (us * 1e-6) / 1e9:.0f} GB/s")
+        print(json.dumps({"mode": "ensemble_steps", "us_per_step": us, "bytes_per_step": B,
+                          "GB_per_s": B / (us * 1e-6) / 1e9}), flush=True)
+        return
     s.record()
     out_b, _ = t.year(y0, nyears=int(L.max()), years_per_member=L, residuals=False)
     e.record()
@@ -425,8 +440,6 @@ def bench_ensemble(args):
     e.record()
     torch.cuda.synchronize()
     ms_1 = s.elapsed_time(e)
-    W = 2 * nm
-    B = bytes_per_step(inp.n, inp.tm.ae_nnz, inp.tm.ai_nnz, W)
     res = {"mode": "ensemble", "workload": "ensemble_256x128x23 N-DOP", "n": inp.n, "members": nm,
            "member_years": member_years, "batched_ms": ms_b,
            "batched_member_years_per_s": member_years / (ms_b / 1000.0),

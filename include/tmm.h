@@ -150,7 +150,10 @@ int tmm_year_jvp(tmm_handle h, int mode, const double *y, const double *v,
  *   J_b = sum_m sum_i sum_tr V_i (y_{s_m} - obs_m)^2 / (2 nmat V_tot),
  * s_m = (m+1) nstep/nmat, over one model year from y0, by a discrete adjoint
  * (the derivative route the paper names in sections 1.2, 6.1 and 9) with
- * checkpoints every ckpt_every steps and recomputation in between.
+ * checkpoints every ckpt_every steps and recomputation in between.  The
+ * forward sweep keeps the states of the last checkpoint segment, so that
+ * segment is not recomputed: ckpt_every = nstep stores the whole year
+ * (nstep x n x W doubles of workspace) and recomputes nothing.
  * y0, obs ([nmat][n][W]) and dJdy0 (nullable, n x W) are device arrays;
  * J_host [nbatch] and dJdu_host [nbatch][nparam] are host arrays.
  * ckpt_every must equal the descriptor's value.  Synchronises. */

@@ -764,7 +764,9 @@ int sqdiff(tmm_ctx* h, int nb, const double* a, const double* b, int volume, dou
 // launches: a forward sweep storing y every ckpt steps and the month-end
 // misfit sums; the misfit source of the last month and Ai^T for the last
 // step; then per segment, last first, a forward replay storing every state
-// and a reverse sweep over the segment.
+// and a reverse sweep over the segment.  The forward sweep writes the last
+// segment's states straight into the segment store, so that segment is not
+// replayed; with one segment (ckpt = nstep) nothing is.
 int adjoint_persistent(tmm_ctx* h, const double* y0, const double* obs, double* J_host, double* dJdu_host,
                        double* dJdy0) {
     const Plan& P = h->P;
@@ -780,10 +782,22 @@ int adjoint_persistent(tmm_ctx* h, const double* y0, const double* obs, double* 
     double* jpart = h->at<double>(P.o_pjpart);
     int rc;
     if ((rc = fill(h, ubar, (size_t)G * np, 0.0)) || (rc = fill(h, jpart, (size_t)P.nmat * G, 0.0))) return rc;
-    // forward sweep: checkpoints y_{sK} at slot s, misfit partial sums
-    tmm::StepRange fw{0, P.nstep, ckpt, K, obs, jpart};
-    if ((rc = launch_persistent(h, fw, y0, fin, h->ybuf(0), h->ybuf(1), nullptr, nullptr, nullptr, nullptr)))
-        return rc;
+    // forward sweep: checkpoints y_{sK} at slot s up to the last segment, whose
+    // states y_lo .. y_{nstep-1} go to the segment store; misfit partial sums
+    const int lo_last = (nseg - 1) * K;
+    const double* ylast = y0;
+    if (nseg > 1) {
+        tmm::StepRange fw{0, lo_last, ckpt, K, obs, jpart};
+        double* yl = ckpt + (size_t)(nseg - 1) * len;
+        if ((rc = launch_persistent(h, fw, y0, yl, h->ybuf(0), h->ybuf(1), nullptr, nullptr, nullptr, nullptr)))
+            return rc;
+        ylast = yl;
+    }
+    {
+        tmm::StepRange fl{lo_last, P.nstep, seg, 1, obs, jpart};
+        if ((rc = launch_persistent(h, fl, ylast, fin, h->ybuf(0), h->ybuf(1), nullptr, nullptr, nullptr, nullptr)))
+            return rc;
+    }
     hipLaunchKernelGGL(tmm::k_sum_tiles, dim3(1), dim3(64), 0, h->stream, P.nmat * G, 1, 1, jpart,
                        1.0 / (2.0 * P.nmat * h->vtot), 0, 0, h->vec(4));
     TMM_LAUNCHED();
@@ -813,9 +827,11 @@ int adjoint_persistent(tmm_ctx* h, const double* y0, const double* obs, double* 
     int im = 0;
     for (int sg = nseg - 1; sg >= 0; --sg) {
         const int lo = sg * K, hi = lo + K;
-        // replay: y_lo .. y_{hi-1} into the segment store
+        // replay: y_lo .. y_{hi-1} into the segment store (the forward sweep
+        // left the last segment there)
         tmm::StepRange rp{lo, hi, seg, 1, nullptr, nullptr};
-        if ((rc = launch_persistent(h, rp, ckpt + (size_t)sg * len, h->ybuf(2), h->ybuf(0), h->ybuf(1), nullptr,
+        if (sg < nseg - 1 &&
+            (rc = launch_persistent(h, rp, ckpt + (size_t)sg * len, h->ybuf(2), h->ybuf(0), h->ybuf(1), nullptr,
                                     nullptr, nullptr, nullptr)))
             return rc;
         double* out = sg == 0 ? (dJdy0 ? dJdy0 : mu[1 - im]) : mu[1 - im];
@@ -1284,7 +1300,9 @@ int tmm_year_adjoint(tmm_handle h, const double* y0, const double* obs, int ckpt
     if ((rc = fill(h, ubt, (size_t)tl.ntile * nb * np, 0.0))) return rc;
 
     auto ckpt_ptr = [&](int s) -> const double* { return s == 0 ? y0 : ckpt + (size_t)s * len; };
-    // forward sweep with checkpoints and misfit partials
+    // forward sweep with checkpoints and misfit partials; the states of the
+    // last segment stay in the segment store, so that segment is not replayed
+    const int lo_last = (nseg - 1) * K;
     {
         const double* cur = y0;
         for (int j = 0; j < P.nstep; ++j) {
@@ -1292,6 +1310,7 @@ int tmm_year_adjoint(tmm_handle h, const double* y0, const double* obs, int ckpt
             double* nxt;
             if (nj == P.nstep) nxt = fin;
             else if (nj % K == 0) nxt = ckpt + (size_t)(nj / K) * len;
+            else if (nj > lo_last) nxt = seg + (size_t)(nj - lo_last) * len;
             else nxt = (cur == seg) ? seg + len : seg;          // two scratch slots of the segment store
             if ((rc = launch_step(h, j, nb, cur, nxt, nullptr, nullptr))) return rc;
             if (nj % spm == 0) {
@@ -1336,7 +1355,7 @@ int tmm_year_adjoint(tmm_handle h, const double* y0, const double* obs, int ckpt
         const int base = s * K;
         // replay the segment, keeping y_{base+1} .. y_{base+K-1}
         const double* cur = ckpt_ptr(s);
-        for (int jj = base; jj < base + K - 1; ++jj) {
+        for (int jj = base; s < nseg - 1 && jj < base + K - 1; ++jj) {
             double* nxt = seg + (size_t)(jj + 1 - base) * len;
             if ((rc = launch_step(h, jj, nb, cur, nxt, nullptr, nullptr))) return rc;
             cur = nxt;

@@ -34,13 +34,17 @@ def test_global_adjoint_against_oracle():
     obs = snaps * (1 + 0.05 * synth.obs_noise(snaps.shape, seed=22))
     u = synth.nominal(inp.model)
     eJ, eG, eY = o.year_adjoint(u, y0, obs)
-    t = tmm.TMM(inp.desc_arrays(), nbatch_max=1, adjoint_nbatch_max=1, ckpt_every=240)
-    assert t.query(tmm.TMM_Q_PERSISTENT) == 1
-    t.set_params(u)
-    J, G, dy0 = t.year_adjoint(t.state(y0), torch.as_tensor(obs).cuda())
-    assert J[0] == pytest.approx(eJ[0], rel=1e-12)
-    assert _rel(G, eG) <= 1e-9
-    assert _rel(dy0.cpu().numpy(), eY) <= 1e-9
+    # checkpoints every 240 steps, and the whole year stored (no recomputation)
+    for ckpt in (240, inp.nstep):
+        print(f"[gpu] adjoint, ckpt_every={ckpt}", flush=True)
+        t = tmm.TMM(inp.desc_arrays(), nbatch_max=1, adjoint_nbatch_max=1, ckpt_every=ckpt)
+        assert t.query(tmm.TMM_Q_PERSISTENT) == 1
+        t.set_params(u)
+        J, G, dy0 = t.year_adjoint(t.state(y0), torch.as_tensor(obs).cuda())
+        assert J[0] == pytest.approx(eJ[0], rel=1e-12), ckpt
+        assert _rel(G, eG) <= 1e-9, ckpt
+        assert _rel(dy0.cpu().numpy(), eY) <= 1e-9, ckpt
+        t.close()
 
 
 def test_ensemble_steps_against_oracle():

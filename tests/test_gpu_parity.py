@@ -145,7 +145,8 @@ def test_jvp_tangent_and_fd(inputs):
 
 
 @pytest.mark.parametrize("persistent", [1, 0])
-@pytest.mark.parametrize("name,ckpt", [("tiny_n", 240), ("tiny_ndop", 240), ("small", 480), ("small", 1)])
+@pytest.mark.parametrize("name,ckpt", [("tiny_n", 240), ("tiny_ndop", 240), ("small", 480), ("small", 1),
+                                       ("tiny_ndop", 2880), ("small", 2880)])
 def test_adjoint_parity(inputs, name, ckpt, persistent):
     inp = inputs[name]
     o = oracle.Oracle(inp)

@@ -128,7 +128,8 @@ def test_phy_adjoint(inputs, name, ckpt, persistent):
     assert _rel(dy0.cpu().numpy(), eY) <= 1e-10
 
 
-def test_phy_ensemble_adjoint(inputs):
+@pytest.mark.parametrize("ckpt", [240, 2880])
+def test_phy_ensemble_adjoint(inputs, ckpt):
     import torch
     inp = inputs["tiny"]
     U = synth.latin_hypercube(PHY, 2, seed=3)
@@ -137,7 +138,7 @@ def test_phy_ensemble_adjoint(inputs):
     obs = np.concatenate([obs1, obs1 * 1.02], axis=2)
     y0 = inp.initial_state(2)
     eJ, eG, eY = o.year_adjoint(U, y0, obs)
-    t = _make(inp, nbatch_max=2, adjoint=2)
+    t = _make(inp, nbatch_max=2, adjoint=2, ckpt=ckpt)
     t.set_params(U)
     J, G, dy0 = t.year_adjoint(t.state(y0), torch.as_tensor(obs).cuda())
     assert np.allclose(J, eJ, rtol=1e-12, atol=0)

@@ -165,7 +165,7 @@ enum {
     TMM_OPT_PERSISTENT = 1,  /* 1 (default): single-member model years run as one persistent
                                 cooperative launch when the grid fits; 0: one launch per step */
     TMM_OPT_DOMAIN_ROWS = 2, /* target rows per workgroup of the persistent kernel (<= 512);
-                                0 = the default (448) */
+                                0 = the default (256) */
     TMM_OPT_MEMBER_KERNEL_MIN = 3, /* forward steps of batches with at least this many members use the
                                      member-parallel kernel (one wavefront per water column, lane =
                                      member); default 16; 0 = never */

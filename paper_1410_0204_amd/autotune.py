@@ -24,7 +24,7 @@ import torch
 
 from . import tmm as T
 
-DOMAIN_ROWS = (256, 320, 384, 448, 512)
+DOMAIN_ROWS = (160, 192, 224, 256, 320, 448)
 
 
 def _signature(t, nbatch):

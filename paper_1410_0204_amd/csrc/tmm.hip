@@ -95,12 +95,17 @@ struct Plan {
     size_t o_ins, o_collat, o_latu;
     // persistent-kernel tables (sized for up to kMaxDomains domains)
     size_t o_pblock, o_pdomcol, o_pdepptr, o_pdepidx, o_pflags, o_pabort;
-    size_t dep_capacity;
+    size_t o_ring, o_vring;         // state rings of the persistent forward kernel (0: none)
+    size_t o_phaloptr, o_phalo;     // halo rows of each domain
+    size_t dep_capacity, halo_capacity;
     size_t total;
 };
 
 constexpr int kMaxDomains = 4096;
-constexpr int kDefaultDomainRows = 448;     // rows per persistent workgroup unless set by option (tuned on MI355X)
+// grids up to this many rows get the persistent kernel's state rings
+// (2 x kRing x n x ntr doubles); larger ones cannot be resident anyway
+constexpr int kMaxPersistentRows = 256 * tmm::kPersistThreadsMax;
+constexpr int kDefaultDomainRows = 256;     // rows per persistent workgroup unless set by option (tuned on MI355X)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -240,6 +245,15 @@ int validate(const tmm_desc* d, Plan& P) {
     P.o_pdepidx = take(P.dep_capacity * 4);
     P.o_pflags = take((size_t)kMaxDomains * 4);
     P.o_pabort = take(64);
+    P.o_phaloptr = take((size_t)(kMaxDomains + 1) * 4);
+    P.halo_capacity = (size_t)d->ae_nnz + 1;
+    P.o_phalo = take(P.halo_capacity * 4);
+    if (d->n <= kMaxPersistentRows) {
+        P.o_ring = take((size_t)tmm::kRing * d->n * P.ntr * 8);
+        P.o_vring = take((size_t)tmm::kRing * d->n * P.ntr * 8);
+    } else {
+        P.o_ring = P.o_vring = 0;
+    }
     P.total = o;
     return TMM_OK;
 }
@@ -262,6 +276,7 @@ struct tmm_ctx {
     int pers_G = 0;
     int pers_kmax = 16;
     int pers_tpb = 256;            // threads (= maximum rows) per domain
+    int pers_hmax = 0;             // largest domain halo (rows)
     int wide_min_members = 16;     // batches of at least this many members use k_step_members
     // captured model years of the launch-per-step path, keyed by their arguments
     struct YearGraph {
@@ -497,6 +512,11 @@ tmm::Persist persist_args(tmm_ctx* h) {
     ps.flags = h->at<int>(P.o_pflags);
     ps.abort_flag = h->at<int>(P.o_pabort);
     ps.spin_limit = 1ll << 22;
+    ps.ring = h->at<double>(P.o_ring);
+    ps.vring = h->at<double>(P.o_vring);
+    ps.halo_ptr = h->at<int>(P.o_phaloptr);
+    ps.halo_row = h->at<int>(P.o_phalo);
+    ps.halo_max = h->pers_hmax;
     return ps;
 }
 
@@ -508,27 +528,38 @@ int reset_flags(tmm_ctx* h) {
 }
 
 // Steps sr.j0 .. sr.j1-1 in one cooperative launch (one member).
-int launch_persistent(tmm_ctx* h, tmm::StepRange sr, const double* y, double* out, double* a, double* b,
-                      const double* v, double* vout, double* va, double* vb) {
+int launch_persistent(tmm_ctx* h, tmm::StepRange sr, const double* y, double* out, const double* v = nullptr,
+                      double* vout = nullptr) {
     const Plan& P = h->P;
     int rc = reset_flags(h);
     if (rc) return rc;
+    // ring slot 0 = the initial state, the others the sentinel
+    const size_t slen = (size_t)P.n * P.ntr, ring_len = (size_t)tmm::kRing * slen;
+    hipLaunchKernelGGL(tmm::k_ring_init, dim3(launch_blocks(ring_len)), dim3(256), 0, h->stream,
+                       h->at<double>(P.o_ring), y, slen, ring_len);
+    TMM_LAUNCHED();
+    if (v) {
+        hipLaunchKernelGGL(tmm::k_ring_init, dim3(launch_blocks(ring_len)), dim3(256), 0, h->stream,
+                           h->at<double>(P.o_vring), v, slen, ring_len);
+        TMM_LAUNCHED();
+    }
     tmm::Grid g = h->grid(h->tilings.front());
     tmm::Model md = h->model();
     tmm::Mats mt = h->mats();
     tmm::Persist ps = persist_args(h);
     double dtd = tmm::kDaysPerYear / P.nstep;
-    void* args[] = {&g, &md, &mt, &ps, &sr, &dtd, &y, &out, &a, &b, &v, &vout, &va, &vb};
+    void* args[] = {&g, &md, &mt, &ps, &sr, &dtd, &y, &out, &v, &vout};
     TMM_TRY(hipLaunchCooperativeKernel(persistent_kernel(P.ntr, v != nullptr, h->pers_kmax, h->pers_tpb, persistent_sn(P)),
-                                       dim3(h->pers_G), dim3(h->pers_tpb), args, 0, h->stream));
+                                       dim3(h->pers_G), dim3(h->pers_tpb), args,
+                                       tmm::year_kernel_dyn_lds(h->pers_tpb, h->pers_hmax, P.ntr, v != nullptr),
+                                       h->stream));
     h->pers_used = true;
     return TMM_OK;
 }
 
-int launch_persistent_year(tmm_ctx* h, const double* y, double* out, double* a, double* b, const double* v,
-                           double* vout, double* va, double* vb) {
+int launch_persistent_year(tmm_ctx* h, const double* y, double* out, const double* v, double* vout) {
     tmm::StepRange sr{0, h->P.nstep, nullptr, 1, nullptr, nullptr};
-    return launch_persistent(h, sr, y, out, a, b, v, vout, va, vb);
+    return launch_persistent(h, sr, y, out, v, vout);
 }
 
 // Reverse sweep over steps j_hi-1 .. j_lo in one cooperative launch.
@@ -619,7 +650,7 @@ int run_year_graph(tmm_ctx* h, int nb, const double* y, double* out, double* a, 
 // launch; otherwise one launch per step.
 int run_year(tmm_ctx* h, int nb, const double* y, double* out, double* a, double* b,
              const double* v = nullptr, double* vout = nullptr, double* va = nullptr, double* vb = nullptr) {
-    if (nb == 1 && h->pers_ok && h->pers_enabled) return launch_persistent_year(h, y, out, a, b, v, vout, va, vb);
+    if (nb == 1 && h->pers_ok && h->pers_enabled) return launch_persistent_year(h, y, out, v, vout);
     if (!v && h->graphs_enabled) return run_year_graph(h, nb, y, out, a, b);
     const double* cur = y;
     const double* vcur = v;
@@ -649,7 +680,7 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     h->num_cu = ncu;
     h->pers_ok = false;
     h->pers_adj_ok = false;
-    if (!coop || P.ew > tmm::kEllMax || P.nlayer > 32 || P.neu > tmm::kNeuMax) return TMM_OK;
+    if (!coop || !P.o_ring || P.ew > tmm::kEllMax || P.nlayer > 32 || P.neu > tmm::kNeuMax) return TMM_OK;
     h->pers_kmax = P.nlayer <= 16 ? 16 : 32;
     if (target_rows < 1) target_rows = kDefaultDomainRows;
     // 512-thread workgroups only where the row's Ai block fits the halved register budget
@@ -658,10 +689,19 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     // co-residency of the forward kernels (both modes) and, separately, of the adjoint
     const int sn = persistent_sn(P);
     int occ = 0, occ_adj = 0;
+    // the forward kernels' dynamic LDS at the largest halo the domains may have
+    const size_t halo_cap = (size_t)tmm::kHaloPerThread * tpb;
+    int lds_max = 0;
+    TMM_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     for (int t = 0; t < 2; ++t) {
+        const void* fk = persistent_kernel(P.ntr, t, h->pers_kmax, tpb, sn);
+        const size_t dyn = tmm::year_kernel_dyn_lds(tpb, (int)halo_cap, P.ntr, t);
+        hipFuncAttributes attr;
+        TMM_TRY(hipFuncGetAttributes(&attr, fk));
+        if (attr.sharedSizeBytes + dyn > (size_t)lds_max) return TMM_OK;
+        TMM_TRY(hipFuncSetAttribute(fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
         int o = 0;
-        TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, persistent_kernel(P.ntr, t, h->pers_kmax, tpb, sn),
-                                                             tpb, 0));
+        TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, fk, tpb, dyn));
         occ = t == 0 ? o : std::min(occ, o);
     }
     {
@@ -669,9 +709,7 @@ int build_persistent(tmm_ctx* h, int target_rows) {
         const void* fa = adjoint_kernel(P.ntr, h->pers_kmax, tpb, sn);
         const size_t dyn = adjoint_dyn_lds(P, tpb);
         hipFuncAttributes attr;
-        int lds_max = 0;
         TMM_TRY(hipFuncGetAttributes(&attr, fa));
-        TMM_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         if (attr.sharedSizeBytes + dyn <= (size_t)lds_max) {
             if (dyn > 0) TMM_TRY(hipFuncSetAttribute(fa, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
             TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_adj, fa, tpb, dyn));
@@ -719,6 +757,23 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     }
     if (dep_idx.size() > P.dep_capacity) return TMM_OK;
     if (dep_idx.empty()) dep_idx.push_back(0);
+    // halo of each domain: the rows of other domains its Ae rows read, ascending
+    std::vector<int> halo_ptr(G + 1, 0), halo;
+    int hmax = 0;
+    for (int q = 0; q < G; ++q) {
+        std::vector<int> hq;
+        for (int i = P.col_start[dom[q]]; i < P.col_start[dom[q + 1]]; ++i)
+            for (int e = h->ae_rowptr[i]; e < h->ae_rowptr[i + 1]; ++e)
+                if (row_dom[h->ae_colidx[e]] != q) hq.push_back(h->ae_colidx[e]);
+        std::sort(hq.begin(), hq.end());
+        hq.erase(std::unique(hq.begin(), hq.end()), hq.end());
+        if (hq.size() > halo_cap) return TMM_OK;          // does not fit: per-step path only
+        hmax = std::max(hmax, (int)hq.size());
+        halo.insert(halo.end(), hq.begin(), hq.end());
+        halo_ptr[q + 1] = (int)halo.size();
+    }
+    if (halo.size() > P.halo_capacity) return TMM_OK;
+    if (halo.empty()) halo.push_back(0);
     std::vector<int> block_dom(G);
     {
         int next = 0;
@@ -728,13 +783,16 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     if (upload(h, h->at<int>(P.o_pblock), block_dom.data(), (size_t)G * 4) ||
         upload(h, h->at<int>(P.o_pdomcol), dom.data(), dom.size() * 4) ||
         upload(h, h->at<int>(P.o_pdepptr), dep_ptr.data(), dep_ptr.size() * 4) ||
-        upload(h, h->at<int>(P.o_pdepidx), dep_idx.data(), dep_idx.size() * 4))
+        upload(h, h->at<int>(P.o_pdepidx), dep_idx.data(), dep_idx.size() * 4) ||
+        upload(h, h->at<int>(P.o_phaloptr), halo_ptr.data(), halo_ptr.size() * 4) ||
+        upload(h, h->at<int>(P.o_phalo), halo.data(), halo.size() * 4))
         return TMM_EDEVICE;
     hipLaunchKernelGGL(tmm::k_fill_int, dim3(1), dim3(64), 0, h->stream, h->at<int>(P.o_pabort), 16, 0);
     TMM_LAUNCHED();
     TMM_TRY(hipStreamSynchronize(h->stream));
     h->pers_G = G;
     h->pers_tpb = tpb;
+    h->pers_hmax = hmax;
     h->pers_ok = true;
     h->pers_adj_ok = (long long)ncu * occ_adj >= G;
     return TMM_OK;
@@ -789,13 +847,13 @@ int adjoint_persistent(tmm_ctx* h, const double* y0, const double* obs, double* 
     if (nseg > 1) {
         tmm::StepRange fw{0, lo_last, ckpt, K, obs, jpart};
         double* yl = ckpt + (size_t)(nseg - 1) * len;
-        if ((rc = launch_persistent(h, fw, y0, yl, h->ybuf(0), h->ybuf(1), nullptr, nullptr, nullptr, nullptr)))
+        if ((rc = launch_persistent(h, fw, y0, yl)))
             return rc;
         ylast = yl;
     }
     {
         tmm::StepRange fl{lo_last, P.nstep, seg, 1, obs, jpart};
-        if ((rc = launch_persistent(h, fl, ylast, fin, h->ybuf(0), h->ybuf(1), nullptr, nullptr, nullptr, nullptr)))
+        if ((rc = launch_persistent(h, fl, ylast, fin)))
             return rc;
     }
     hipLaunchKernelGGL(tmm::k_sum_tiles, dim3(1), dim3(64), 0, h->stream, P.nmat * G, 1, 1, jpart,
@@ -831,8 +889,7 @@ int adjoint_persistent(tmm_ctx* h, const double* y0, const double* obs, double* 
         // left the last segment there)
         tmm::StepRange rp{lo, hi, seg, 1, nullptr, nullptr};
         if (sg < nseg - 1 &&
-            (rc = launch_persistent(h, rp, ckpt + (size_t)sg * len, h->ybuf(2), h->ybuf(0), h->ybuf(1), nullptr,
-                                    nullptr, nullptr, nullptr)))
+            (rc = launch_persistent(h, rp, ckpt + (size_t)sg * len, h->ybuf(2))))
             return rc;
         double* out = sg == 0 ? (dJdy0 ? dJdy0 : mu[1 - im]) : mu[1 - im];
         if ((rc = launch_adjoint_persistent(h, lo, hi, seg, obs, 1.0 / (P.nmat * h->vtot), mu[im], out,

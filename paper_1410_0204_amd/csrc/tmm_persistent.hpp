@@ -19,16 +19,29 @@
 //    vertical product and the biogeochemistry (section 5: one column at a
 //    time) only touch the domain's own rows, kept in LDS.
 //  * Only the explicit (horizontal) product reads rows of other domains.
-//    Each domain publishes its new state to a global ping-pong buffer and
-//    then a step counter with an agent-scope release store; a domain starts
-//    step j after it has read a counter >= j from every domain its Ae rows
-//    touch (and every domain that touches it, so that
-//    no buffer is overwritten while a neighbour still reads it).
-//  * The published state is stored with agent-scope (write-through) stores;
-//    the flag is a release store and the waiting side polls with relaxed
-//    loads followed by one acquire fence, so each step costs one L2
-//    write-back and one L2 invalidate per workgroup.  Larger domains (512
-//    threads) mean fewer of these per L2.
+//    Each state y_t of the launch is published to its own slot of a ring of
+//    2K slots (K = kRingK) that holds only the sentinel (all bits set, a NaN
+//    that a published value never has: NaNs are stored in canonical form)
+//    until the owner writes the value (slot 0 holds the launch's initial
+//    state, written before the launch).  A thread reads a neighbour's value
+//    with relaxed agent-scope loads until it is not the sentinel: an aligned
+//    8-byte access is single-copy atomic, so the value read is the published
+//    one, with no flag and no fence between producer and consumer.
+//  * Each domain reads the rows of other domains that its stencil touches
+//    (its halo, sorted and without repeats) once per step, consecutive threads
+//    taking consecutive halo rows, into LDS beside its own rows; the explicit
+//    product then reads only LDS.  Device-scope loads bypass the L1 and L2
+//    caches, so fetching each halo row once instead of once per reference
+//    cuts the requests that reach the device's point of coherence by about
+//    an order of magnitude.
+//  * Slot reuse is ordered by a hand-over every K steps: before step pK each
+//    domain publishes the step counter p with an agent-scope release store and
+//    waits (relaxed polls, then one acquire fence) for the counters of every
+//    domain its Ae rows touch and every domain that touches it.  After it, a
+//    domain resets its own rows of the slots of states (p+1)K .. (p+2)K-1,
+//    whose previous states (p-1)K .. pK-1 every neighbour has read before the
+//    hand-over; the next hand-over orders the resets before any read of those
+//    slots.
 //  * Waits are bounded: after spin_limit polls a workgroup sets a global
 //    abort flag and returns; every other workgroup sees the flag and returns
 //    too, so the grid always drains.  Cooperative launch guarantees that all
@@ -42,16 +55,37 @@ namespace tmm {
 constexpr int kPersistThreadsMax = 512;   // rows per domain (one per thread), at most
 constexpr int kNeuMax = 4;             // euphotic layers supported by this kernel
 constexpr int kEllMax = 8;             // Ae nonzeros per row supported by this kernel
+constexpr int kHaloPerThread = 2;      // halo rows per thread (a domain's halo is at most 2 TPB rows)
+constexpr int kRingK = 32;             // steps between hand-overs; the ring has 2 kRingK slots
+constexpr int kRing = 2 * kRingK;
+
+// The ring's empty-slot marker and the canonical NaN that replaces any NaN
+// before it is published.
+constexpr long long kSentinelBits = -1LL;
+__device__ __forceinline__ bool is_sentinel(double x) { return __double_as_longlong(x) == kSentinelBits; }
+__device__ __forceinline__ double publishable(double x) {
+    return x == x ? x : __longlong_as_double(0x7FF8000000000000LL);
+}
 
 struct Persist {
     const int* block_dom;   // [G] domain of each workgroup
     const int* dom_col;     // [G+1] first water column of each domain
     const int* dep_ptr;     // [G+1]
     const int* dep_idx;     // domains each domain waits for
-    int* flags;             // [G] number of steps each domain has published
+    int* flags;             // [G] hand-overs (forward) or steps (adjoint) each domain has published
     int* abort_flag;        // non-zero once any wait gave up
     long long spin_limit;
+    double* ring;           // [kRing][n*NTR] published states of the forward kernel, sentinel-filled
+    double* vring;          // [kRing][n*NTR] the same for the tangent (nullable)
+    const int* halo_ptr;    // [G+1]
+    const int* halo_row;    // rows of other domains each domain reads, ascending per domain
+    int halo_max;           // largest halo (rows); sizes the dynamic LDS of the forward kernel
 };
+
+// Dynamic LDS of the forward kernel: own rows then halo rows, for y (and v).
+__host__ __device__ inline size_t year_kernel_dyn_lds(int tpb, int halo_max, int ntr, bool tangent) {
+    return (size_t)(tpb + halo_max) * ntr * 8 * (tangent ? 2 : 1);
+}
 
 // Steps j0 .. j1-1 of the year for one launch, with optional state storage
 // (y_j of own rows at slot (j - j0)/store_every when (j - j0) % store_every == 0)
@@ -64,9 +98,17 @@ struct StepRange {
     double* jpart;          // [nmat][G] per-domain sums of V_i (y - obs)^2
 };
 
+// Ring set-up before a launch: slot 0 = the initial state (NaNs in canonical
+// form, so that no value equals the sentinel), every other slot the sentinel.
+__global__ void k_ring_init(double* __restrict__ ring, const double* __restrict__ y, size_t slen, size_t total) {
+    const double sent = __longlong_as_double(kSentinelBits);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
+        ring[i] = i < slen ? publishable(y[i]) : sent;
+}
+
 template <int KMAX>
 struct RowMats {
-    int col[kEllMax];       // Ae column indices of the row
+    int col[kEllMax];       // LDS row of each Ae entry: own rows first, then the halo
     double e0[kEllMax], e1[kEllMax];   // Ae row, months k0 and k1
     double a0[KMAX], a1[KMAX];         // row of the Ai block, months k0 and k1
 };
@@ -239,9 +281,7 @@ __device__ __forceinline__ void sub_adjoint_lds(const Grid& g, const Model& md, 
 template <int NTR, bool TANGENT, int KMAX, int TPB, int SN = 0>
 __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     Grid g, Model md, Mats mt, Persist ps, StepRange sr, double dtd, const double* __restrict__ y_in,
-    double* __restrict__ y_out, double* __restrict__ buf0, double* __restrict__ buf1,
-    const double* __restrict__ v_in, double* __restrict__ v_out, double* __restrict__ vbuf0,
-    double* __restrict__ vbuf1) {
+    double* __restrict__ y_out, const double* __restrict__ v_in, double* __restrict__ v_out) {
     constexpr int TV = TANGENT ? NTR : 1;
     constexpr bool SUB = SN > 0;
     __shared__ double s_red[TPB];
@@ -249,11 +289,13 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     __shared__ short s_rowk[TPB];
     __shared__ short s_colr0[TPB];
     __shared__ short s_colnc[TPB];
-    __shared__ double s_y[TPB * NTR];
     __shared__ double s_z[TPB * NTR];
-    __shared__ double s_v[TPB * TV];
     __shared__ double s_zd[TPB * TV];
     __shared__ int s_fail;
+    // own rows [0, TPB) and halo rows [TPB, TPB + halo_max) of y (and v)
+    extern __shared__ double s_dyn[];
+    double* const s_y = s_dyn;
+    double* const s_v = s_dyn + (size_t)(TPB + ps.halo_max) * NTR;
 
     const int tid = threadIdx.x;
     const int d = ps.block_dom[blockIdx.x];
@@ -297,9 +339,30 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     }
 
     RowMats<KMAX> R;
+    // the row's Ae entries as LDS rows: an own row at its place in the domain,
+    // another domain's row after the own rows, at its place in the halo
+    const int h0 = ps.halo_ptr[d], nh = ps.halo_ptr[d + 1] - h0;
 #pragma unroll
     for (int s = 0; s < kEllMax; ++s) {
-        R.col[s] = s < mt.ew ? mt.ae_col[(size_t)s * g.npad + r] : r;
+        const int cg = s < mt.ew ? mt.ae_col[(size_t)s * g.npad + r] : r;
+        if ((unsigned)(cg - r0) < (unsigned)nrows) {
+            R.col[s] = cg - r0;
+        } else {
+            int lo = 0, hi = nh - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (ps.halo_row[h0 + mid] < cg) lo = mid + 1;
+                else hi = mid;
+            }
+            R.col[s] = TPB + (lo < nh ? lo : 0);
+        }
+    }
+    // the halo rows this thread fetches each step (-1: none)
+    int hrow[kHaloPerThread];
+#pragma unroll
+    for (int i = 0; i < kHaloPerThread; ++i) {
+        const int hq = tid + i * TPB;
+        hrow[i] = hq < nh ? ps.halo_row[h0 + hq] : -1;
     }
 
     // own state
@@ -321,11 +384,22 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     const size_t state_len = (size_t)g.n * NTR;
     const int spm = g.nstep / g.nmat;
     const double vol = g.area[c] * g.dz[k];
+    // month pair, weight and insolation of the coming step, prepared at the end
+    // of the step before (off the neighbours' critical path); the month pair and
+    // the month-end counter advance by one step at a time, without divisions
+    int k0, k1, pr_r, me_cnt;
+    double w;
+    step_phase(sr.j0, g.nstep, g.nmat, k0, k1, w);
+    {
+        int jm0 = sr.j0 % g.nstep;
+        pr_r = (jm0 - spm / 2) - ((jm0 - spm / 2) >= 0 ? (jm0 - spm / 2) / spm
+                                                      : -((spm / 2 - jm0 + spm - 1) / spm)) * spm;
+        me_cnt = (sr.j0 + 1) % spm;
+    }
+    int jm = sr.j0 % g.nstep;
+    double Q = g.ins[(size_t)jm * g.nlat + latrow];
     for (int jj = 0; jj < nsteps; ++jj) {
         const int j = sr.j0 + jj;
-        int k0, k1;
-        double w;
-        step_phase(j, g.nstep, g.nmat, k0, k1, w);
         if (sr.store && own && jj % sr.store_every == 0) {
 #pragma unroll
             for (int t = 0; t < NTR; ++t)
@@ -347,7 +421,6 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             m1 = k1;
         }
         const double om = 1.0 - w;
-        const double Q = g.ins[(size_t)(j % g.nstep) * g.nlat + latrow];
 
         // sources from the domain's own rows (no wait needed)
         double q[NTR], qd[TV];
@@ -413,46 +486,105 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             }
         }
 
-        // wait until every neighbouring domain has published y_j: relaxed
-        // polling, then one acquire fence (the acquire half of the flag's
-        // release/acquire pair) in each polling wave
-        for (int qi = tid; qi < ndep; qi += blockDim.x) {
-            const int e = ps.dep_idx[dep0 + qi];
-            long long it = 0;
-            while (__hip_atomic_load(&ps.flags[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < jj) {
-                ++it;
-                if (it > ps.spin_limit ||
-                    ((it & 63) == 0 && __hip_atomic_load(ps.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                    __hip_atomic_store(ps.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    s_fail = 1;
-                    break;
+        // hand-over every kRingK steps: publish the phase counter, wait for the
+        // neighbours' counters, then reset the own rows of the slots that the
+        // phase after next writes
+        if (jj % kRingK == 0) {
+            const int ph = jj / kRingK;
+            if (ph > 0) {
+                if (tid == 0) __hip_atomic_store(&ps.flags[d], ph, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                for (int qi = tid; qi < ndep; qi += blockDim.x) {
+                    const int e = ps.dep_idx[dep0 + qi];
+                    long long it = 0;
+                    while (__hip_atomic_load(&ps.flags[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < ph) {
+                        ++it;
+                        if (it > ps.spin_limit || ((it & 63) == 0 && __hip_atomic_load(ps.abort_flag, __ATOMIC_RELAXED,
+                                                                                       __HIP_MEMORY_SCOPE_AGENT))) {
+                            __hip_atomic_store(ps.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            s_fail = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
                 }
-                __builtin_amdgcn_s_sleep(1);
+                if (tid < ndep) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __syncthreads();
+                if (s_fail) return;
+            }
+            if (own) {
+                const double sent = __longlong_as_double(kSentinelBits);
+#pragma unroll 1
+                for (int i = 0; i < kRingK; ++i) {
+                    const size_t o = (size_t)((jj + kRingK + i) % kRing) * state_len + (size_t)r * NTR;
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) {
+                        __hip_atomic_store(&ps.ring[o + t], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (TANGENT)
+                            __hip_atomic_store(&ps.vring[o + t], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
             }
         }
-        if (tid < ndep) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+
+        // the halo of state jj (ring slot jj; slot 0 holds y_in) into LDS, each
+        // value read until it is no longer the sentinel
+        {
+            const double* rs = ps.ring + (size_t)(jj % kRing) * state_len;
+            const double* vs = TANGENT ? ps.vring + (size_t)(jj % kRing) * state_len : nullptr;
+#pragma unroll
+            for (int i = 0; i < kHaloPerThread; ++i) {
+                if (hrow[i] < 0) continue;
+                const size_t o = (size_t)hrow[i] * NTR;
+                const int lh = TPB + tid + i * TPB;
+                long long it = 0;
+                for (;;) {
+                    double hv[NTR], hd[NTR];
+                    bool miss = false;
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) {
+                        hv[t] = __hip_atomic_load(&rs[o + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        miss |= is_sentinel(hv[t]);
+                        if (TANGENT) {
+                            hd[t] = __hip_atomic_load(&vs[o + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            miss |= is_sentinel(hd[t]);
+                        }
+                    }
+                    if (!miss) {
+#pragma unroll
+                        for (int t = 0; t < NTR; ++t) {
+                            s_y[lh * NTR + t] = hv[t];
+                            if (TANGENT) s_v[lh * TV + t % TV] = hd[t];
+                        }
+                        break;
+                    }
+                    ++it;
+                    if (it > ps.spin_limit || ((it & 63) == 0 && __hip_atomic_load(ps.abort_flag, __ATOMIC_RELAXED,
+                                                                                   __HIP_MEMORY_SCOPE_AGENT))) {
+                        __hip_atomic_store(ps.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        s_fail = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+        }
         __syncthreads();
         if (s_fail) return;
 
-        // z = Ae(t_j) y_j + dt_d q
-        const double* src = jj == 0 ? y_in : ((jj & 1) ? buf1 : buf0);
-        const double* vsrc = jj == 0 ? v_in : ((jj & 1) ? vbuf1 : vbuf0);
+        // z = Ae(t_j) y_j + dt_d q, from LDS
         if (own) {
             double acc[NTR], accd[TV];
 #pragma unroll
             for (int t = 0; t < NTR; ++t) acc[t] = 0.0;
 #pragma unroll
             for (int t = 0; t < TV; ++t) accd[t] = 0.0;
-            // every slot is read from the exchange buffer (own rows included; padded
-            // slots point at the row itself with zero weight): no branches, so all
-            // loads of the row are in flight together
             double yy[kEllMax][NTR], vv[kEllMax][TV];
 #pragma unroll
             for (int s = 0; s < kEllMax; ++s)
 #pragma unroll
                 for (int t = 0; t < NTR; ++t) {
-                    yy[s][t] = src[(size_t)R.col[s] * NTR + t];
-                    if (TANGENT) vv[s][t % TV] = vsrc[(size_t)R.col[s] * NTR + t];
+                    yy[s][t] = s_y[R.col[s] * NTR + t];
+                    if (TANGENT) vv[s][t % TV] = s_v[R.col[s] * TV + t % TV];
                 }
 #pragma unroll
             for (int s = 0; s < kEllMax; ++s) {
@@ -472,8 +604,9 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
         __syncthreads();
 
         // y_{j+1} = Ai(t_j) z, within the water column
-        double* dst = jj == nsteps - 1 ? y_out : ((jj & 1) ? buf0 : buf1);
-        double* vdst = jj == nsteps - 1 ? v_out : ((jj & 1) ? vbuf0 : vbuf1);
+        const bool last = jj == nsteps - 1;
+        double* wr = ps.ring + (size_t)((jj + 1) % kRing) * state_len;
+        double* vwr = TANGENT ? ps.vring + (size_t)((jj + 1) % kRing) * state_len : nullptr;
         if (own) {
             double acc[NTR], accd[TV];
 #pragma unroll
@@ -496,21 +629,34 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             for (int t = 0; t < NTR; ++t) {
                 yr[t] = acc[t];
                 s_y[tid * NTR + t] = acc[t];
-                // agent-scope stores write through the XCD's L2, so the release
-                // below has no dirty lines of the exchange buffers to write back
-                __hip_atomic_store(&dst[(size_t)r * NTR + t], acc[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // agent-scope stores write through the XCD's L2 to the point
+                // where every domain's loads see them
+                if (last) y_out[(size_t)r * NTR + t] = acc[t];
+                else __hip_atomic_store(&wr[(size_t)r * NTR + t], publishable(acc[t]), __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
                 if (TANGENT) {
                     vr[t % TV] = accd[t % TV];
                     s_v[tid * TV + t % TV] = accd[t % TV];
-                    __hip_atomic_store(&vdst[(size_t)r * NTR + t], accd[t % TV], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+                    if (last) v_out[(size_t)r * NTR + t] = accd[t % TV];
+                    else __hip_atomic_store(&vwr[(size_t)r * NTR + t], publishable(accd[t % TV]), __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
         }
+        const bool month_end = me_cnt == 0;
+        // the coming step's month pair, weight and insolation
+        if (++pr_r == spm) {
+            pr_r = 0;
+            k0 = k1;
+            k1 = k1 + 1 == g.nmat ? 0 : k1 + 1;
+        }
+        w = (double)pr_r / (double)spm;
+        me_cnt = me_cnt + 1 == spm ? 0 : me_cnt + 1;
+        jm = jm + 1 == g.nstep ? 0 : jm + 1;
+        Q = g.ins[(size_t)jm * g.nlat + latrow];
         __syncthreads();
-        if (tid == 0) __hip_atomic_store(&ps.flags[d], jj + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         // month-end misfit partial sums (after publishing, off the neighbours' critical path)
-        if (sr.obs && (j + 1) % spm == 0) {
+        if (sr.obs && month_end) {
             const int mo = (j + 1) / spm - 1;
             double cval = 0.0;
             if (own) {
@@ -540,7 +686,10 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
 //   ubar    += dt_d (dq/du)(y_j)^T mu_j
 // s_j is the misfit source at month ends (j > 0).  Each thread keeps its
 // row of Ae^T (months of step j) and column of its Ai block (months of step
-// j-1) in registers; mu is exchanged between domains like the forward state.
+// j-1) in registers.  mu crosses domains through two ping-pong buffers and
+// a per-step counter: a domain writes its rows with write-through stores,
+// then its counter with a release store; the neighbours poll the counters
+// and take one acquire fence before reading.
 // y_j of the segment comes from ystore (slot j - j_lo).  Parameter-gradient
 // sums are reduced per domain at the end and added to ubar_dom[domain][p].
 // ---------------------------------------------------------------------------

@@ -97,6 +97,7 @@ struct Plan {
     size_t o_pblock, o_pdomcol, o_pdepptr, o_pdepidx, o_pflags, o_pabort;
     size_t o_ring, o_vring;         // state rings of the persistent forward kernel (0: none)
     size_t o_phaloptr, o_phalo;     // halo rows of each domain
+    size_t o_pahaloptr, o_pahalo;   // ... for the transposed stencil (reverse sweep)
     size_t dep_capacity, halo_capacity;
     size_t total;
 };
@@ -248,6 +249,8 @@ int validate(const tmm_desc* d, Plan& P) {
     P.o_phaloptr = take((size_t)(kMaxDomains + 1) * 4);
     P.halo_capacity = (size_t)d->ae_nnz + 1;
     P.o_phalo = take(P.halo_capacity * 4);
+    P.o_pahaloptr = take((size_t)(kMaxDomains + 1) * 4);
+    P.o_pahalo = take(P.halo_capacity * 4);
     if (d->n <= kMaxPersistentRows) {
         P.o_ring = take((size_t)tmm::kRing * d->n * P.ntr * 8);
         P.o_vring = take((size_t)tmm::kRing * d->n * P.ntr * 8);
@@ -277,6 +280,7 @@ struct tmm_ctx {
     int pers_kmax = 16;
     int pers_tpb = 256;            // threads (= maximum rows) per domain
     int pers_hmax = 0;             // largest domain halo (rows)
+    int pers_ahmax = 0;            // ... of the transposed stencil
     int wide_min_members = 16;     // batches of at least this many members use k_step_members
     // captured model years of the launch-per-step path, keyed by their arguments
     struct YearGraph {
@@ -497,9 +501,10 @@ const void* adjoint_kernel(int ntr, int kmax, int tpb, int sn) {
 // Internal-step variant of the persistent kernels for a plan.
 int persistent_sn(const Plan& P) { return P.nsub > 1 ? (P.neu <= 2 ? 2 : 4) : 0; }
 
-// Dynamic LDS of the persistent adjoint: the internal-step states of every row.
-size_t adjoint_dyn_lds(const Plan& P, int tpb) {
-    return P.nsub > 1 ? (size_t)P.nsub * tpb * P.ntr * 8 : 0;
+// Dynamic LDS of the persistent adjoint: mu of the own rows and of the halo,
+// then the internal-step states of every row.
+size_t adjoint_dyn_lds(const Plan& P, int tpb, int halo_max) {
+    return (size_t)(tpb + halo_max) * P.ntr * 8 + (P.nsub > 1 ? (size_t)P.nsub * tpb * P.ntr * 8 : 0);
 }
 
 tmm::Persist persist_args(tmm_ctx* h) {
@@ -517,6 +522,9 @@ tmm::Persist persist_args(tmm_ctx* h) {
     ps.halo_ptr = h->at<int>(P.o_phaloptr);
     ps.halo_row = h->at<int>(P.o_phalo);
     ps.halo_max = h->pers_hmax;
+    ps.ahalo_ptr = h->at<int>(P.o_pahaloptr);
+    ps.ahalo_row = h->at<int>(P.o_pahalo);
+    ps.ahalo_max = h->pers_ahmax;
     return ps;
 }
 
@@ -564,21 +572,24 @@ int launch_persistent_year(tmm_ctx* h, const double* y, double* out, const doubl
 
 // Reverse sweep over steps j_hi-1 .. j_lo in one cooperative launch.
 int launch_adjoint_persistent(tmm_ctx* h, int j_lo, int j_hi, const double* ystore, const double* obs,
-                              double src_scale, const double* mu_in, double* mu_out, double* a, double* b,
-                              double* ubar_dom) {
+                              double src_scale, const double* mu_in, double* mu_out, double* ubar_dom) {
     const Plan& P = h->P;
     int rc = reset_flags(h);
     if (rc) return rc;
+    // the cotangent uses the forward kernel's ring (launches never overlap)
+    const size_t slen = (size_t)P.n * P.ntr, ring_len = (size_t)tmm::kRing * slen;
+    hipLaunchKernelGGL(tmm::k_ring_init, dim3(launch_blocks(ring_len)), dim3(256), 0, h->stream,
+                       h->at<double>(P.o_ring), mu_in, slen, ring_len);
+    TMM_LAUNCHED();
     tmm::Grid g = h->grid(h->tilings.front());
     tmm::Model md = h->model();
     tmm::Mats mt = h->mats();
     tmm::Persist ps = persist_args(h);
     double dtd = tmm::kDaysPerYear / P.nstep;
-    void* args[] = {&g, &md, &mt, &ps, &dtd, &j_lo, &j_hi, &ystore, &obs, &src_scale, &mu_in, &mu_out,
-                    &a, &b, &ubar_dom};
+    void* args[] = {&g, &md, &mt, &ps, &dtd, &j_lo, &j_hi, &ystore, &obs, &src_scale, &mu_in, &mu_out, &ubar_dom};
     TMM_TRY(hipLaunchCooperativeKernel(adjoint_kernel(P.ntr, h->pers_kmax, h->pers_tpb, persistent_sn(P)),
-                                       dim3(h->pers_G), dim3(h->pers_tpb), args, adjoint_dyn_lds(P, h->pers_tpb),
-                                       h->stream));
+                                       dim3(h->pers_G), dim3(h->pers_tpb), args,
+                                       adjoint_dyn_lds(P, h->pers_tpb, h->pers_ahmax), h->stream));
     h->pers_used = true;
     return TMM_OK;
 }
@@ -707,7 +718,7 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     {
         // the internal-step store of the adjoint is dynamic LDS beside the static arrays
         const void* fa = adjoint_kernel(P.ntr, h->pers_kmax, tpb, sn);
-        const size_t dyn = adjoint_dyn_lds(P, tpb);
+        const size_t dyn = adjoint_dyn_lds(P, tpb, (int)halo_cap);
         hipFuncAttributes attr;
         TMM_TRY(hipFuncGetAttributes(&attr, fa));
         if (attr.sharedSizeBytes + dyn <= (size_t)lds_max) {
@@ -774,6 +785,32 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     }
     if (halo.size() > P.halo_capacity) return TMM_OK;
     if (halo.empty()) halo.push_back(0);
+    // halo of the transposed stencil: row i of Ae^T reads mu at the rows whose
+    // Ae rows have an entry in column i
+    std::vector<std::vector<int>> ah(G);
+    for (int i = 0; i < P.n; ++i)
+        for (int e = h->ae_rowptr[i]; e < h->ae_rowptr[i + 1]; ++e) {
+            const int q = row_dom[h->ae_colidx[e]];
+            if (row_dom[i] != q) ah[q].push_back(i);
+        }
+    std::vector<int> ahalo_ptr(G + 1, 0), ahalo;
+    int ahmax = 0;
+    bool ahalo_ok = true;
+    for (int q = 0; q < G; ++q) {
+        std::sort(ah[q].begin(), ah[q].end());
+        ah[q].erase(std::unique(ah[q].begin(), ah[q].end()), ah[q].end());
+        if (ah[q].size() > halo_cap) ahalo_ok = false;
+        ahmax = std::max(ahmax, (int)ah[q].size());
+        ahalo.insert(ahalo.end(), ah[q].begin(), ah[q].end());
+        ahalo_ptr[q + 1] = (int)ahalo.size();
+    }
+    if (ahalo.size() > P.halo_capacity) ahalo_ok = false;
+    if (!ahalo_ok) {                                      // the reverse sweep falls back to per-step kernels
+        ahmax = 0;
+        ahalo.assign(1, 0);
+        std::fill(ahalo_ptr.begin(), ahalo_ptr.end(), 0);
+    }
+    if (ahalo.empty()) ahalo.push_back(0);
     std::vector<int> block_dom(G);
     {
         int next = 0;
@@ -785,7 +822,9 @@ int build_persistent(tmm_ctx* h, int target_rows) {
         upload(h, h->at<int>(P.o_pdepptr), dep_ptr.data(), dep_ptr.size() * 4) ||
         upload(h, h->at<int>(P.o_pdepidx), dep_idx.data(), dep_idx.size() * 4) ||
         upload(h, h->at<int>(P.o_phaloptr), halo_ptr.data(), halo_ptr.size() * 4) ||
-        upload(h, h->at<int>(P.o_phalo), halo.data(), halo.size() * 4))
+        upload(h, h->at<int>(P.o_phalo), halo.data(), halo.size() * 4) ||
+        upload(h, h->at<int>(P.o_pahaloptr), ahalo_ptr.data(), ahalo_ptr.size() * 4) ||
+        upload(h, h->at<int>(P.o_pahalo), ahalo.data(), ahalo.size() * 4))
         return TMM_EDEVICE;
     hipLaunchKernelGGL(tmm::k_fill_int, dim3(1), dim3(64), 0, h->stream, h->at<int>(P.o_pabort), 16, 0);
     TMM_LAUNCHED();
@@ -793,8 +832,9 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     h->pers_G = G;
     h->pers_tpb = tpb;
     h->pers_hmax = hmax;
+    h->pers_ahmax = ahmax;
     h->pers_ok = true;
-    h->pers_adj_ok = (long long)ncu * occ_adj >= G;
+    h->pers_adj_ok = ahalo_ok && (long long)ncu * occ_adj >= G;
     return TMM_OK;
 }
 
@@ -892,8 +932,7 @@ int adjoint_persistent(tmm_ctx* h, const double* y0, const double* obs, double* 
             (rc = launch_persistent(h, rp, ckpt + (size_t)sg * len, h->ybuf(2))))
             return rc;
         double* out = sg == 0 ? (dJdy0 ? dJdy0 : mu[1 - im]) : mu[1 - im];
-        if ((rc = launch_adjoint_persistent(h, lo, hi, seg, obs, 1.0 / (P.nmat * h->vtot), mu[im], out,
-                                            h->vbuf(0), h->vbuf(1), ubar)))
+        if ((rc = launch_adjoint_persistent(h, lo, hi, seg, obs, 1.0 / (P.nmat * h->vtot), mu[im], out, ubar)))
             return rc;
         im = 1 - im;
     }

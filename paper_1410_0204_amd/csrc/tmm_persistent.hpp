@@ -80,6 +80,9 @@ struct Persist {
     const int* halo_ptr;    // [G+1]
     const int* halo_row;    // rows of other domains each domain reads, ascending per domain
     int halo_max;           // largest halo (rows); sizes the dynamic LDS of the forward kernel
+    const int* ahalo_ptr;   // the same for the transposed stencil of the reverse sweep
+    const int* ahalo_row;
+    int ahalo_max;
 };
 
 // Dynamic LDS of the forward kernel: own rows then halo rows, for y (and v).
@@ -686,10 +689,10 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
 //   ubar    += dt_d (dq/du)(y_j)^T mu_j
 // s_j is the misfit source at month ends (j > 0).  Each thread keeps its
 // row of Ae^T (months of step j) and column of its Ai block (months of step
-// j-1) in registers.  mu crosses domains through two ping-pong buffers and
-// a per-step counter: a domain writes its rows with write-through stores,
-// then its counter with a release store; the neighbours poll the counters
-// and take one acquire fence before reading.
+// j-1) in registers.  mu crosses domains like the forward state: through
+// the sentinel-filled ring (slot 0 holds mu_in) with a hand-over every
+// kRingK steps, each domain staging its halo of the transposed stencil in
+// LDS once per step.
 // y_j of the segment comes from ystore (slot j - j_lo).  Parameter-gradient
 // sums are reduced per domain at the end and added to ubar_dom[domain][p].
 // ---------------------------------------------------------------------------
@@ -697,8 +700,7 @@ template <int NTR, int KMAX, int TPB, int SN = 0>
 __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     Grid g, Model md, Mats mt, Persist ps, double dtd, int j_lo, int j_hi,
     const double* __restrict__ ystore, const double* __restrict__ obs, double src_scale,
-    const double* __restrict__ mu_in, double* __restrict__ mu_out, double* __restrict__ buf0,
-    double* __restrict__ buf1, double* __restrict__ ubar_dom) {
+    const double* __restrict__ mu_in, double* __restrict__ mu_out, double* __restrict__ ubar_dom) {
     constexpr int NP = NTR == 3 ? 11 : (NTR == 2 ? 7 : 5);
     constexpr bool SUB = SN > 0;
     __shared__ short s_rowcol[TPB];
@@ -706,11 +708,14 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     __shared__ short s_colr0[TPB];
     __shared__ short s_colnc[TPB];
     __shared__ double s_y[TPB * NTR];
-    __shared__ double s_mu[TPB * NTR];
     __shared__ double s_lam[TPB * NTR];
     __shared__ double s_red[TPB];
     __shared__ int s_fail;
-    extern __shared__ double s_traj[];   // internal-step states [nsub][TPB][NTR] (SUB only)
+    // dynamic: mu of the own rows [0, TPB) and of the halo [TPB, TPB + ahalo_max),
+    // then the internal-step states [nsub][TPB][NTR] (SUB only)
+    extern __shared__ double s_dyn[];
+    double* const s_mu = s_dyn;
+    double* const s_traj = s_dyn + (size_t)(TPB + ps.ahalo_max) * NTR;
     constexpr int TS = SUB ? TPB : 1;
     __shared__ double s_yb[TS * NTR];      // internal-step results per euphotic row (SUB only)
     __shared__ double s_acc[TS * 5];
@@ -763,12 +768,31 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     for (int i = 0; i <= k; ++i) zc += g.dz[i];
     zc -= 0.5 * g.dz[k];
 
-    // row r of Ae^T and column k of the row's Ai block
+    // row r of Ae^T and column k of the row's Ai block; the entries of Ae^T as
+    // LDS rows (own rows first, then the halo)
     int col[kEllMax];
     double e0[kEllMax], e1[kEllMax], a0[KMAX], a1[KMAX];
+    const int h0 = ps.ahalo_ptr[d], nh = ps.ahalo_ptr[d + 1] - h0;
 #pragma unroll
     for (int s = 0; s < kEllMax; ++s) {
-        col[s] = s < mt.etw ? mt.aet_col[(size_t)s * g.npad + r] : r;
+        const int cg = s < mt.etw ? mt.aet_col[(size_t)s * g.npad + r] : r;
+        if ((unsigned)(cg - r0) < (unsigned)nrows) {
+            col[s] = cg - r0;
+        } else {
+            int lo = 0, hi = nh - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (ps.ahalo_row[h0 + mid] < cg) lo = mid + 1;
+                else hi = mid;
+            }
+            col[s] = TPB + (lo < nh ? lo : 0);
+        }
+    }
+    int hrow[kHaloPerThread];
+#pragma unroll
+    for (int i = 0; i < kHaloPerThread; ++i) {
+        const int hq = tid + i * TPB;
+        hrow[i] = hq < nh ? ps.ahalo_row[h0 + hq] : -1;
     }
     auto load_ae = [&](int mo, double* e) {
 #pragma unroll
@@ -793,6 +817,10 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     const int dep0 = ps.dep_ptr[d], ndep = ps.dep_ptr[d + 1] - dep0;
     int me0 = -1, me1 = -1, ma0 = -1, ma1 = -1;
     const int nsteps = j_hi - j_lo;
+    double ynext[NTR];
+#pragma unroll
+    for (int t = 0; t < NTR; ++t)
+        ynext[t] = (own && nsteps > 0) ? ystore[(size_t)(j_hi - 1 - j_lo) * state_len + (size_t)r * NTR + t] : 0.0;
 
     for (int jj = 0; jj < nsteps; ++jj) {
         const int j = j_hi - 1 - jj;
@@ -827,12 +855,16 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
         const double om = 1.0 - w;
         const double Q = g.ins[(size_t)j * g.nlat + latrow];
 
-        // y_j of the own rows
+        // y_j of the own rows (loaded during the step before)
         double yj[NTR];
 #pragma unroll
         for (int t = 0; t < NTR; ++t) {
-            yj[t] = own ? ystore[(size_t)(j - j_lo) * state_len + (size_t)r * NTR + t] : 0.0;
+            yj[t] = ynext[t];
             s_y[tid * NTR + t] = yj[t];
+        }
+        if (own && j - 1 >= j_lo) {
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) ynext[t] = ystore[(size_t)(j - 1 - j_lo) * state_len + (size_t)r * NTR + t];
         }
         __syncthreads();
 
@@ -921,27 +953,79 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
             ub[NP - 1] += (1.0 - p.sig) * Phi * drho * mu1;
         }
 
-        // wait until every neighbouring domain has published mu_j
-        for (int qi = tid; qi < ndep; qi += blockDim.x) {
-            const int e = ps.dep_idx[dep0 + qi];
-            long long it = 0;
-            while (__hip_atomic_load(&ps.flags[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < jj) {
-                ++it;
-                if (it > ps.spin_limit ||
-                    ((it & 63) == 0 && __hip_atomic_load(ps.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                    __hip_atomic_store(ps.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    s_fail = 1;
-                    break;
+        // hand-over every kRingK steps, then the resets of the own rows of the
+        // ring slots that the phase after next writes
+        if (jj % kRingK == 0) {
+            const int ph = jj / kRingK;
+            if (ph > 0) {
+                if (tid == 0) __hip_atomic_store(&ps.flags[d], ph, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                for (int qi = tid; qi < ndep; qi += blockDim.x) {
+                    const int e = ps.dep_idx[dep0 + qi];
+                    long long it = 0;
+                    while (__hip_atomic_load(&ps.flags[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < ph) {
+                        ++it;
+                        if (it > ps.spin_limit || ((it & 63) == 0 && __hip_atomic_load(ps.abort_flag, __ATOMIC_RELAXED,
+                                                                                       __HIP_MEMORY_SCOPE_AGENT))) {
+                            __hip_atomic_store(ps.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            s_fail = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
                 }
-                __builtin_amdgcn_s_sleep(1);
+                if (tid < ndep) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __syncthreads();
+                if (s_fail) return;
+            }
+            if (own) {
+                const double sent = __longlong_as_double(kSentinelBits);
+#pragma unroll 1
+                for (int i = 0; i < kRingK; ++i) {
+                    const size_t o = (size_t)((jj + kRingK + i) % kRing) * state_len + (size_t)r * NTR;
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t)
+                        __hip_atomic_store(&ps.ring[o + t], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
         }
-        if (tid < ndep) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+
+        // the halo of mu_j (ring slot jj) into LDS
+        {
+            const double* rs = ps.ring + (size_t)(jj % kRing) * state_len;
+#pragma unroll
+            for (int i = 0; i < kHaloPerThread; ++i) {
+                if (hrow[i] < 0) continue;
+                const size_t o = (size_t)hrow[i] * NTR;
+                const int lh = TPB + tid + i * TPB;
+                long long it = 0;
+                for (;;) {
+                    double hv[NTR];
+                    bool miss = false;
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) {
+                        hv[t] = __hip_atomic_load(&rs[o + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        miss |= is_sentinel(hv[t]);
+                    }
+                    if (!miss) {
+#pragma unroll
+                        for (int t = 0; t < NTR; ++t) s_mu[lh * NTR + t] = hv[t];
+                        break;
+                    }
+                    ++it;
+                    if (it > ps.spin_limit || ((it & 63) == 0 && __hip_atomic_load(ps.abort_flag, __ATOMIC_RELAXED,
+                                                                                   __HIP_MEMORY_SCOPE_AGENT))) {
+                        __hip_atomic_store(ps.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        s_fail = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+        }
         __syncthreads();
         if (s_fail) return;
 
         // lambda_j = Ae^T mu_j + dt_d ybar + s_j
-        const double* src = jj == 0 ? mu_in : ((jj & 1) ? buf1 : buf0);
         const int mo = (j > 0 && j % spm == 0 && obs) ? j / spm - 1 : -1;
         if (own) {
             double lam[NTR];
@@ -951,7 +1035,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
 #pragma unroll
             for (int s = 0; s < kEllMax; ++s)
 #pragma unroll
-                for (int t = 0; t < NTR; ++t) mm[s][t] = src[(size_t)col[s] * NTR + t];
+                for (int t = 0; t < NTR; ++t) mm[s][t] = s_mu[col[s] * NTR + t];
 #pragma unroll
             for (int s = 0; s < kEllMax; ++s) {
                 const double a = om * e0[s] + w * e1[s];
@@ -968,7 +1052,8 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
         __syncthreads();
 
         // mu_{j-1} = Ai(t_{j-1})^T lambda_j within the column, or lambda_0
-        double* dst = jj == nsteps - 1 ? mu_out : ((jj & 1) ? buf0 : buf1);
+        const bool last = jj == nsteps - 1;
+        double* wr = ps.ring + (size_t)((jj + 1) % kRing) * state_len;
         if (own) {
             double out[NTR];
             if (j > 0) {
@@ -990,11 +1075,12 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
             for (int t = 0; t < NTR; ++t) {
                 mr[t] = out[t];
                 s_mu[tid * NTR + t] = out[t];
-                __hip_atomic_store(&dst[(size_t)r * NTR + t], out[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (last) mu_out[(size_t)r * NTR + t] = out[t];
+                else __hip_atomic_store(&wr[(size_t)r * NTR + t], publishable(out[t]), __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         __syncthreads();
-        if (tid == 0) __hip_atomic_store(&ps.flags[d], jj + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 
     // per-domain parameter-gradient sums (fixed-order tree)

@@ -817,17 +817,26 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     const int dep0 = ps.dep_ptr[d], ndep = ps.dep_ptr[d + 1] - dep0;
     int me0 = -1, me1 = -1, ma0 = -1, ma1 = -1;
     const int nsteps = j_hi - j_lo;
-    double ynext[NTR];
+    // y_j of the own rows: ycur for the current step (also in s_y), ynext for
+    // the step after, loaded one step ahead
+    double ycur[NTR], ynext[NTR];
 #pragma unroll
-    for (int t = 0; t < NTR; ++t)
-        ynext[t] = (own && nsteps > 0) ? ystore[(size_t)(j_hi - 1 - j_lo) * state_len + (size_t)r * NTR + t] : 0.0;
+    for (int t = 0; t < NTR; ++t) {
+        ycur[t] = (own && nsteps > 0) ? ystore[(size_t)(j_hi - 1 - j_lo) * state_len + (size_t)r * NTR + t] : 0.0;
+        ynext[t] = (own && nsteps > 1) ? ystore[(size_t)(j_hi - 2 - j_lo) * state_len + (size_t)r * NTR + t] : 0.0;
+        s_y[tid * NTR + t] = ycur[t];
+    }
+    __syncthreads();
 
+    // month pairs of steps j and j-1 and the insolation of step j, prepared at
+    // the end of the step before
+    int k0, k1, q0, q1;
+    double w, wq;
+    step_phase(j_hi - 1, g.nstep, g.nmat, k0, k1, w);
+    step_phase(j_hi - 2, g.nstep, g.nmat, q0, q1, wq);
+    double Q = g.ins[(size_t)(j_hi - 1) * g.nlat + latrow];
     for (int jj = 0; jj < nsteps; ++jj) {
         const int j = j_hi - 1 - jj;
-        int k0, k1, q0, q1;
-        double w, wq;
-        step_phase(j, g.nstep, g.nmat, k0, k1, w);
-        step_phase(j - 1, g.nstep, g.nmat, q0, q1, wq);
         if (own && (k0 != me0 || k1 != me1)) {
             if (k1 == me0) {          // stepping backwards: the old k0 becomes the new k1
 #pragma unroll
@@ -853,20 +862,11 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
             ma1 = q1;
         }
         const double om = 1.0 - w;
-        const double Q = g.ins[(size_t)j * g.nlat + latrow];
 
-        // y_j of the own rows (loaded during the step before)
+        // y_j of the own rows (in s_y since the end of the step before)
         double yj[NTR];
 #pragma unroll
-        for (int t = 0; t < NTR; ++t) {
-            yj[t] = ynext[t];
-            s_y[tid * NTR + t] = yj[t];
-        }
-        if (own && j - 1 >= j_lo) {
-#pragma unroll
-            for (int t = 0; t < NTR; ++t) ynext[t] = ystore[(size_t)(j - 1 - j_lo) * state_len + (size_t)r * NTR + t];
-        }
-        __syncthreads();
+        for (int t = 0; t < NTR; ++t) yj[t] = ycur[t];
 
         // (dq/dy)^T mu_j and (dq/du)^T mu_j from the own water column
         double ybar[NTR];
@@ -1079,6 +1079,23 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
                 else __hip_atomic_store(&wr[(size_t)r * NTR + t], publishable(out[t]), __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
             }
+        }
+        // y_{j-1} into s_y for the next step (this step's reads of s_y all came
+        // before the halo barrier), and y_{j-2} loaded for the step after
+        if (!last) {
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) {
+                ycur[t] = ynext[t];
+                s_y[tid * NTR + t] = ycur[t];
+            }
+            if (own && j - 2 >= j_lo) {
+#pragma unroll
+                for (int t = 0; t < NTR; ++t)
+                    ynext[t] = ystore[(size_t)(j - 2 - j_lo) * state_len + (size_t)r * NTR + t];
+            }
+            step_phase(j - 1, g.nstep, g.nmat, k0, k1, w);
+            step_phase(j - 2, g.nstep, g.nmat, q0, q1, wq);
+            Q = g.ins[(size_t)(j - 1) * g.nlat + latrow];
         }
         __syncthreads();
     }

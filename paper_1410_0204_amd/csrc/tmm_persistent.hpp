@@ -56,7 +56,7 @@ constexpr int kPersistThreadsMax = 512;   // rows per domain (one per thread), a
 constexpr int kNeuMax = 4;             // euphotic layers supported by this kernel
 constexpr int kEllMax = 8;             // Ae nonzeros per row supported by this kernel
 constexpr int kHaloPerThread = 2;      // halo rows per thread (a domain's halo is at most 2 TPB rows)
-constexpr int kRingK = 32;             // steps between hand-overs; the ring has 2 kRingK slots
+constexpr int kRingK = 64;             // steps between hand-overs; the ring has 2 kRingK slots
 constexpr int kRing = 2 * kRingK;
 
 // The ring's empty-slot marker and the canonical NaN that replaces any NaN
@@ -529,45 +529,48 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             }
         }
 
-        // the halo of state jj (ring slot jj; slot 0 holds y_in) into LDS, each
-        // value read until it is no longer the sentinel
+        // the halo of state jj (ring slot jj; slot 0 holds y_in) into LDS: every
+        // pass issues the loads of all the lane's halo rows together and
+        // defines them all again, until none is the sentinel
         {
             const double* rs = ps.ring + (size_t)(jj % kRing) * state_len;
             const double* vs = TANGENT ? ps.vring + (size_t)(jj % kRing) * state_len : nullptr;
+            double hv[kHaloPerThread][NTR], hd[kHaloPerThread][NTR];
+            long long it = 0;
+            for (;;) {
+                bool miss = false;
+#pragma unroll
+                for (int i = 0; i < kHaloPerThread; ++i) {
+                    if (hrow[i] < 0) continue;
+                    const size_t o = (size_t)hrow[i] * NTR;
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) {
+                        hv[i][t] = __hip_atomic_load(&rs[o + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        miss |= is_sentinel(hv[i][t]);
+                        if (TANGENT) {
+                            hd[i][t] = __hip_atomic_load(&vs[o + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            miss |= is_sentinel(hd[i][t]);
+                        }
+                    }
+                }
+                if (!miss) break;
+                ++it;
+                if (it > ps.spin_limit ||
+                    ((it & 63) == 0 && __hip_atomic_load(ps.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                    __hip_atomic_store(ps.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s_fail = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
 #pragma unroll
             for (int i = 0; i < kHaloPerThread; ++i) {
                 if (hrow[i] < 0) continue;
-                const size_t o = (size_t)hrow[i] * NTR;
                 const int lh = TPB + tid + i * TPB;
-                long long it = 0;
-                for (;;) {
-                    double hv[NTR], hd[NTR];
-                    bool miss = false;
 #pragma unroll
-                    for (int t = 0; t < NTR; ++t) {
-                        hv[t] = __hip_atomic_load(&rs[o + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        miss |= is_sentinel(hv[t]);
-                        if (TANGENT) {
-                            hd[t] = __hip_atomic_load(&vs[o + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            miss |= is_sentinel(hd[t]);
-                        }
-                    }
-                    if (!miss) {
-#pragma unroll
-                        for (int t = 0; t < NTR; ++t) {
-                            s_y[lh * NTR + t] = hv[t];
-                            if (TANGENT) s_v[lh * TV + t % TV] = hd[t];
-                        }
-                        break;
-                    }
-                    ++it;
-                    if (it > ps.spin_limit || ((it & 63) == 0 && __hip_atomic_load(ps.abort_flag, __ATOMIC_RELAXED,
-                                                                                   __HIP_MEMORY_SCOPE_AGENT))) {
-                        __hip_atomic_store(ps.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        s_fail = 1;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
+                for (int t = 0; t < NTR; ++t) {
+                    s_y[lh * NTR + t] = hv[i][t];
+                    if (TANGENT) s_v[lh * TV + t % TV] = hd[i][t];
                 }
             }
         }
@@ -989,37 +992,39 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
             }
         }
 
-        // the halo of mu_j (ring slot jj) into LDS
+        // the halo of mu_j (ring slot jj) into LDS, all of the lane's rows per pass
         {
             const double* rs = ps.ring + (size_t)(jj % kRing) * state_len;
+            double hv[kHaloPerThread][NTR];
+            long long it = 0;
+            for (;;) {
+                bool miss = false;
+#pragma unroll
+                for (int i = 0; i < kHaloPerThread; ++i) {
+                    if (hrow[i] < 0) continue;
+                    const size_t o = (size_t)hrow[i] * NTR;
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) {
+                        hv[i][t] = __hip_atomic_load(&rs[o + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        miss |= is_sentinel(hv[i][t]);
+                    }
+                }
+                if (!miss) break;
+                ++it;
+                if (it > ps.spin_limit ||
+                    ((it & 63) == 0 && __hip_atomic_load(ps.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                    __hip_atomic_store(ps.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s_fail = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
 #pragma unroll
             for (int i = 0; i < kHaloPerThread; ++i) {
                 if (hrow[i] < 0) continue;
-                const size_t o = (size_t)hrow[i] * NTR;
                 const int lh = TPB + tid + i * TPB;
-                long long it = 0;
-                for (;;) {
-                    double hv[NTR];
-                    bool miss = false;
 #pragma unroll
-                    for (int t = 0; t < NTR; ++t) {
-                        hv[t] = __hip_atomic_load(&rs[o + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        miss |= is_sentinel(hv[t]);
-                    }
-                    if (!miss) {
-#pragma unroll
-                        for (int t = 0; t < NTR; ++t) s_mu[lh * NTR + t] = hv[t];
-                        break;
-                    }
-                    ++it;
-                    if (it > ps.spin_limit || ((it & 63) == 0 && __hip_atomic_load(ps.abort_flag, __ATOMIC_RELAXED,
-                                                                                   __HIP_MEMORY_SCOPE_AGENT))) {
-                        __hip_atomic_store(ps.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        s_fail = 1;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
+                for (int t = 0; t < NTR; ++t) s_mu[lh * NTR + t] = hv[i][t];
             }
         }
         __syncthreads();

@@ -48,7 +48,7 @@ enum {
     TMM_OK = 0,
     TMM_EINVAL = -1,        /* invalid argument or descriptor */
     TMM_ENOMEM = -2,        /* workspace too small */
-    TMM_EDEVICE = -3,       /* HIP runtime error */
+    TMM_EDEVICE = -3,       /* HIP runtime error, or a wait of the persistent kernels gave up */
     TMM_ESTATE = -4,        /* call not valid in the handle's state (e.g. no parameters set) */
     TMM_ENONFINITE = -5,    /* non-finite value found in a result */
     TMM_EUNSUPPORTED = -6   /* valid request outside what this build supports */
@@ -169,8 +169,12 @@ enum {
     TMM_OPT_MEMBER_KERNEL_MIN = 3, /* forward steps of batches with at least this many members use the
                                      member-parallel kernel (one wavefront per water column, lane =
                                      member); default 16; 0 = never */
-    TMM_OPT_GRAPH = 4            /* 1 (default): model years on the launch-per-step path are captured
+    TMM_OPT_GRAPH = 4,           /* 1 (default): model years on the launch-per-step path are captured
                                     once per (members, buffers) into a hipGraph and replayed */
+    TMM_OPT_SPIN_LIMIT = 5       /* polls after which a wait of the persistent kernels gives up
+                                    (the call then returns TMM_EDEVICE; the next call starts
+                                    afresh); 0 = the default (2^22, seconds); small values are for
+                                    tests of that failure path */
 };
 
 /* Queries (tmm_query). */

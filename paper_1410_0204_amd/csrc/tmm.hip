@@ -276,6 +276,7 @@ struct tmm_ctx {
     bool pers_ok = false;          // tables built and the launch fits the device
     bool pers_adj_ok = false;      // ... and so does the persistent adjoint
     bool pers_enabled = true;      // option TMM_OPT_PERSISTENT
+    long long spin_limit = 1ll << 22;   // option TMM_OPT_SPIN_LIMIT
     int pers_G = 0;
     int pers_kmax = 16;
     int pers_tpb = 256;            // threads (= maximum rows) per domain
@@ -516,7 +517,7 @@ tmm::Persist persist_args(tmm_ctx* h) {
     ps.dep_idx = h->at<int>(P.o_pdepidx);
     ps.flags = h->at<int>(P.o_pflags);
     ps.abort_flag = h->at<int>(P.o_pabort);
-    ps.spin_limit = 1ll << 22;
+    ps.spin_limit = h->spin_limit;
     ps.ring = h->at<double>(P.o_ring);
     ps.vring = h->at<double>(P.o_vring);
     ps.halo_ptr = h->at<int>(P.o_phaloptr);
@@ -594,14 +595,20 @@ int launch_adjoint_persistent(tmm_ctx* h, int j_lo, int j_hi, const double* ysto
     return TMM_OK;
 }
 
-// After persistent launches: a set abort flag means a wait gave up.
+// After the persistent launches of a call: a set abort flag means a wait
+// gave up in one of them.  It is reported once and cleared, so the next call
+// starts afresh.
 int check_abort(tmm_ctx* h) {
     if (!h->pers_used) return TMM_OK;
     int flag = 0;
     TMM_TRY(hipMemcpyAsync(&flag, h->at<int>(h->P.o_pabort), 4, hipMemcpyDeviceToHost, h->stream));
     TMM_TRY(hipStreamSynchronize(h->stream));
     h->pers_used = false;
-    return flag ? TMM_EDEVICE : TMM_OK;
+    if (!flag) return TMM_OK;
+    hipLaunchKernelGGL(tmm::k_fill_int, dim3(1), dim3(64), 0, h->stream, h->at<int>(h->P.o_pabort), 16, 0);
+    TMM_LAUNCHED();
+    TMM_TRY(hipStreamSynchronize(h->stream));
+    return TMM_EDEVICE;
 }
 
 // One model year of the launch-per-step path replayed from a hipGraph: the
@@ -1342,6 +1349,10 @@ int tmm_set_option(tmm_handle h, int option, int value) {
             return drop_graphs(h);
         case TMM_OPT_GRAPH:
             h->graphs_enabled = value != 0;
+            return TMM_OK;
+        case TMM_OPT_SPIN_LIMIT:
+            if (value < 0) return TMM_EINVAL;
+            h->spin_limit = value == 0 ? 1ll << 22 : value;
             return TMM_OK;
         case TMM_OPT_DOMAIN_ROWS: {
             if (value < 0) return TMM_EINVAL;

@@ -16,6 +16,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtmm.so")
 
 TMM_OK = 0
+TMM_EINVAL = -1
+TMM_ENOMEM = -2
+TMM_EDEVICE = -3
+TMM_ESTATE = -4
+TMM_ENONFINITE = -5
+TMM_EUNSUPPORTED = -6
 TMM_MODEL_N = 1
 TMM_MODEL_NDOP = 2
 TMM_MODEL_NDOPPHY = 3
@@ -28,6 +34,7 @@ TMM_OPT_PERSISTENT = 1
 TMM_OPT_DOMAIN_ROWS = 2
 TMM_OPT_MEMBER_KERNEL_MIN = 3
 TMM_OPT_GRAPH = 4
+TMM_OPT_SPIN_LIMIT = 5
 TMM_Q_PERSISTENT = 1
 TMM_Q_DOMAINS = 2
 TMM_Q_WORKSPACE = 3

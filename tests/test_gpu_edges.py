@@ -116,3 +116,31 @@ def test_edge_tangent_and_adjoint(inputs, name):
         assert J[0] == pytest.approx(eJ[0], rel=1e-12), pers
         assert _rel(G, eG) <= 1e-10, pers
         assert _rel(dy0.cpu().numpy(), eY) <= 1e-10, pers
+
+
+def test_wait_give_up_is_reported_and_the_handle_recovers():
+    """A wait of the persistent kernel that gives up is reported, and leaves nothing behind.
+
+    The failure is forced from the host: a spin limit of one poll makes any wait
+    that needs a second poll give up (with many small domains some wait in a model
+    year always does).  The kernel still ends normally; the call reports
+    TMM_EDEVICE.  With the default limit restored, the next year on the same handle
+    matches the oracle.
+    """
+    tmm = _tmm()
+    inp = synth.small_ndop()
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=1)
+    t.set_option(tmm.TMM_OPT_DOMAIN_ROWS, 16)
+    assert t.query(tmm.TMM_Q_PERSISTENT) == 1
+    print(f"[gpu] forced give-up, {t.query(tmm.TMM_Q_DOMAINS)} domains", flush=True)
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    y0 = inp.initial_state()
+    t.set_option(tmm.TMM_OPT_SPIN_LIMIT, 1)
+    with pytest.raises(tmm.TmmError) as err:
+        t.year(t.state(y0), nyears=1)
+    assert err.value.status == tmm.TMM_EDEVICE
+    t.set_option(tmm.TMM_OPT_SPIN_LIMIT, 0)
+    got, _ = t.year(t.state(y0), nyears=1)
+    exp, _ = oracle.Oracle(inp).year(u, y0)
+    assert _rel(got.cpu().numpy(), exp) <= 1e-12

@@ -176,7 +176,8 @@ __device__ __forceinline__ void sub_adjoint_lds(const Grid& g, const Model& md, 
                                                 int c0, int ncols, const short* s_colr0, const short* s_colnc,
                                                 int tid, int k, int ne, int lc, size_t tab, double zc, double rho_k,
                                                 double drho_k, const double* s_y, const double* s_mu,
-                                                double* s_traj, double* s_yb, double* s_acc, double* s_sphi,
+                                                const double* s_rhoc, double* s_traj, double* s_yb,
+                                                double* s_acc, double* s_sphi,
                                                 const double (&yj)[NTR], const double (&mr)[NTR],
                                                 double (&ybar)[NTR], double (&ub)[NP]) {
     const double h = md.hsub;
@@ -227,7 +228,7 @@ __device__ __forceinline__ void sub_adjoint_lds(const Grid& g, const Model& md, 
             }
         }
         double pdeep = 0.0;
-        for (int kk = neq; kk < ncq; ++kk) pdeep += (1.0 - p.sig) * md.rho[tabq + kk] * s_mu[(r0q + kk) * NTR];
+        for (int kk = neq; kk < ncq; ++kk) pdeep += s_rhoc[r0q + kk] * s_mu[(r0q + kk) * NTR];
         double sphi = 0.0;
         for (int s = nsub - 1; s >= 0; --s) {
             double ys[NEU][NTR];
@@ -713,6 +714,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     __shared__ double s_y[TPB * NTR];
     __shared__ double s_lam[TPB * NTR];
     __shared__ double s_red[TPB];
+    __shared__ double s_rhoc[TPB];   // (1 - sigma_2) rho of each own row (per member, fixed)
     __shared__ int s_fail;
     // dynamic: mu of the own rows [0, TPB) and of the halo [TPB, TPB + ahalo_max),
     // then the internal-step states [nsub][TPB][NTR] (SUB only)
@@ -770,6 +772,8 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     double zc = 0.0;   // centre depth of the row's layer
     for (int i = 0; i <= k; ++i) zc += g.dz[i];
     zc -= 0.5 * g.dz[k];
+    const double hk = g.dz[k];
+    s_rhoc[tid] = own ? (1.0 - p.sig) * rho : 0.0;
 
     // row r of Ae^T and column k of the row's Ai block; the entries of Ae^T as
     // LDS rows (own rows first, then the halo)
@@ -875,8 +879,8 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
         double ybar[NTR];
         if constexpr (SUB) {
             sub_adjoint_lds<NTR, (SUB ? SN : 1), NP, TPB>(g, md, p, m, j, c0, c1 - c0, s_colr0, s_colnc, tid, k, ne,
-                                                          lc, tab, zc, rho, drho, s_y, s_mu, s_traj, s_yb, s_acc,
-                                                          s_sphi, yj, mr, ybar, ub);
+                                                          lc, tab, zc, rho, drho, s_y, s_mu, s_rhoc, s_traj, s_yb,
+                                                          s_acc, s_sphi, yj, mr, ybar, ub);
         } else if constexpr (NTR == 3) {
             // PO4-DOP-PHY (section 2.2.2)
             double Phi = 0.0;
@@ -892,7 +896,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
             ybar[2] = 0.0;
             if (k < g.neu) {
                 double Phibar = 0.0;
-                for (int kk = 0; kk < nc; ++kk) Phibar += (1.0 - p.sig) * md.rho[tab + kk] * s_mu[(lr0 + kk) * 3];
+                for (int kk = 0; kk < nc; ++kk) Phibar += s_rhoc[lr0 + kk] * s_mu[(lr0 + kk) * 3];
                 double lk = 0.0;
 #pragma unroll
                 for (int e = 0; e < kNeuMax; ++e)
@@ -900,7 +904,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
                 const Production pr = production(p, yj[0], Q, lk);
                 const double f = pr.f * P;
                 // f_1 enters q_1 (-1), q_2 (sigma_2 sigma_3), q_3 (1 - sigma_3) and Phi (h_k sigma_3)
-                const double fbar = -m1 + p.sig * p.sig3 * m2 + (1.0 - p.sig3) * m3 + p.sig3 * g.dz[k] * Phibar;
+                const double fbar = -m1 + p.sig * p.sig3 * m2 + (1.0 - p.sig3) * m3 + p.sig3 * hk * Phibar;
                 const double dloss = p.lam3 + 2.0 * p.kap3 * P;
                 ybar[0] = fbar * pr.dfdN * P;
                 ybar[2] = fbar * pr.f + dloss * (m2 - m3);
@@ -913,7 +917,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
                 ub[5] += p.sig3 * f * m2;
                 ub[6] += P * (m2 - m3);
                 ub[7] += P * P * (m2 - m3);
-                ub[9] += f * (p.sig * m2 - m3 + g.dz[k] * Phibar);
+                ub[9] += f * (p.sig * m2 - m3 + hk * Phibar);
             }
             ybar[1] = p.lam * (m1 - m2);
             ybar[2] += p.lam3p * (m2 - m3);
@@ -932,13 +936,13 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
             ybar[0] = 0.0;
             if (k < g.neu) {
                 double Phibar = 0.0;
-                for (int kk = 0; kk < nc; ++kk) Phibar += (1.0 - p.sig) * md.rho[tab + kk] * s_mu[(lr0 + kk) * NTR];
+                for (int kk = 0; kk < nc; ++kk) Phibar += s_rhoc[lr0 + kk] * s_mu[(lr0 + kk) * NTR];
                 double lk = 0.0;
 #pragma unroll
                 for (int e = 0; e < kNeuMax; ++e)
                     if (e == k) lk = light[e];
                 const Production pr = production(p, yj[0], Q, lk);
-                const double fbar = -mu1 + p.sig * mu2 + g.dz[k] * Phibar;
+                const double fbar = -mu1 + p.sig * mu2 + hk * Phibar;
                 ybar[0] = fbar * pr.dfdN;
                 const double Np = yj[0] > 0.0 ? yj[0] : 0.0;
                 const double IKI2 = (pr.I + p.ki) * (pr.I + p.ki);

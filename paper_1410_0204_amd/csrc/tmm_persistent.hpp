@@ -160,6 +160,31 @@ __device__ __forceinline__ void sub_source_lds(const Model& md, const BgcParams&
     }
 }
 
+// Euphotic-layer constants of one water column (light factors, layer heights,
+// Martin fractions; entries beyond the euphotic depth repeat layer 0) and its
+// latitude row: loaded once per launch.
+template <int NEU>
+struct ColConsts {
+    double light[NEU], hz[NEU], rho[NEU];
+    int lat;
+};
+
+template <int NEU>
+__device__ __forceinline__ ColConsts<NEU> load_col_consts(const Grid& g, const Model& md, int m, int c, int nc) {
+    ColConsts<NEU> r;
+    const int ne = nc < g.neu ? nc : g.neu;
+    const size_t tab = ((size_t)m * (g.nlayer + 1) + nc) * g.nlayer;
+#pragma unroll
+    for (int e = 0; e < NEU; ++e) {
+        const int ee = e < ne ? e : 0;
+        r.light[e] = md.light[(size_t)m * g.nlayer + ee];
+        r.hz[e] = g.dz[ee];
+        r.rho[e] = md.rho[tab + ee];
+    }
+    r.lat = g.col_lat[c];
+    return r;
+}
+
 // Reverse of the internal BGC steps (section 7 with the adjoint of section
 // 6) for the domain's rows.  Phase 1, one thread per water column: the
 // column's euphotic rows are run forward over the internal steps (their
@@ -177,7 +202,8 @@ __device__ __forceinline__ void sub_adjoint_lds(const Grid& g, const Model& md, 
                                                 int tid, int k, int ne, int lc, size_t tab, double zc, double rho_k,
                                                 double drho_k, const double* s_y, const double* s_mu,
                                                 const double* s_rhoc, double* s_traj, double* s_yb,
-                                                double* s_acc, double* s_sphi,
+                                                double* s_acc, double* s_sphi, const ColConsts<NEU>& cc,
+                                                const ColConsts<NEU>& oc, double Q_own,
                                                 const double (&yj)[NTR], const double (&mr)[NTR],
                                                 double (&ybar)[NTR], double (&ub)[NP]) {
     const double h = md.hsub;
@@ -186,17 +212,8 @@ __device__ __forceinline__ void sub_adjoint_lds(const Grid& g, const Model& md, 
         const int r0q = s_colr0[tid];
         const int ncq = s_colnc[tid];
         const int neq = ncq < g.neu ? ncq : g.neu;
-        const double Q = g.ins[(size_t)j * g.nlat + g.col_lat[c0 + tid]];
-        const size_t tabq = ((size_t)m * (g.nlayer + 1) + ncq) * g.nlayer;
-        double light[NEU], hz[NEU], rho[NEU];
-#pragma unroll
-        for (int e = 0; e < NEU; ++e) {
-            const int ee = e < neq ? e : 0;
-            light[e] = md.light[(size_t)m * g.nlayer + ee];
-            hz[e] = g.dz[ee];
-            rho[e] = md.rho[tabq + ee];
-        }
-        const Euphotic<NEU> E = make_euphotic<NEU>(p, Q, neq, light, hz, rho);
+        const double Q = g.ins[(size_t)j * g.nlat + cc.lat];
+        const Euphotic<NEU> E = make_euphotic<NEU>(p, Q, neq, cc.light, cc.hz, cc.rho);
         double ye[NEU][NTR], ib[NEU][NTR], yb[NEU][NTR];
         EuphoticAdj acc[NEU];
 #pragma unroll
@@ -262,16 +279,7 @@ __device__ __forceinline__ void sub_adjoint_lds(const Grid& g, const Model& md, 
         for (int t = 0; t < NTR; ++t) ybar[t] = s_yb[tid * NTR + t];
         const EuphoticAdj acc{s_acc[tid * 5 + 0], s_acc[tid * 5 + 1], s_acc[tid * 5 + 2], s_acc[tid * 5 + 3],
                               s_acc[tid * 5 + 4]};
-        const double Q = g.ins[(size_t)j * g.nlat + g.col_lat[c0 + lc]];
-        double light[NEU], hz[NEU], rho[NEU];
-#pragma unroll
-        for (int e = 0; e < NEU; ++e) {
-            const int ee = e < ne ? e : 0;
-            light[e] = md.light[(size_t)m * g.nlayer + ee];
-            hz[e] = g.dz[ee];
-            rho[e] = md.rho[tab + ee];
-        }
-        const Euphotic<NEU> E = make_euphotic<NEU>(p, Q, ne, light, hz, rho);
+        const Euphotic<NEU> E = make_euphotic<NEU>(p, Q_own, ne, oc.light, oc.hz, oc.rho);
         euphotic_adj_finish<NTR, NEU, NP>(p, E, k, zc, drho_k, acc, ub);
     } else {
         deep_reverse<NTR, NP>(p, deep_factors(p, h, nsub), nsub, h, rho_k, drho_k, s_sphi[lc], yj, mr, ybar, ub);
@@ -774,6 +782,14 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     zc -= 0.5 * g.dz[k];
     const double hk = g.dz[k];
     s_rhoc[tid] = own ? (1.0 - p.sig) * rho : 0.0;
+    // internal steps: constants of the column this thread integrates (thread
+    // index = column of the domain) and of the thread's own column
+    constexpr int SNE = SUB ? SN : 1;
+    ColConsts<SNE> col_cc{}, own_cc{};
+    if constexpr (SUB) {
+        if (tid < c1 - c0) col_cc = load_col_consts<SNE>(g, md, m, c0 + tid, s_colnc[tid]);
+        own_cc = load_col_consts<SNE>(g, md, m, c, nc);
+    }
 
     // row r of Ae^T and column k of the row's Ai block; the entries of Ae^T as
     // LDS rows (own rows first, then the halo)
@@ -880,7 +896,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
         if constexpr (SUB) {
             sub_adjoint_lds<NTR, (SUB ? SN : 1), NP, TPB>(g, md, p, m, j, c0, c1 - c0, s_colr0, s_colnc, tid, k, ne,
                                                           lc, tab, zc, rho, drho, s_y, s_mu, s_rhoc, s_traj, s_yb,
-                                                          s_acc, s_sphi, yj, mr, ybar, ub);
+                                                          s_acc, s_sphi, col_cc, own_cc, Q, yj, mr, ybar, ub);
         } else if constexpr (NTR == 3) {
             // PO4-DOP-PHY (section 2.2.2)
             double Phi = 0.0;

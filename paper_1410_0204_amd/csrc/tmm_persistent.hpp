@@ -33,9 +33,10 @@
 //    product then reads only LDS.  Device-scope loads bypass the L1 and L2
 //    caches, so fetching each halo row once instead of once per reference
 //    cuts the requests that reach the device's point of coherence by about
-//    an order of magnitude.
+//    an order of magnitude.  A thread issues the loads of all its halo rows
+//    before it checks any of them, so a step waits for one round trip.
 //  * Slot reuse is ordered by a hand-over every K steps: before step pK each
-//    domain publishes the step counter p with an agent-scope release store and
+//    domain publishes the phase counter p with an agent-scope release store and
 //    waits (relaxed polls, then one acquire fence) for the counters of every
 //    domain its Ae rows touch and every domain that touches it.  After it, a
 //    domain resets its own rows of the slots of states (p+1)K .. (p+2)K-1,
@@ -46,6 +47,8 @@
 //    abort flag and returns; every other workgroup sees the flag and returns
 //    too, so the grid always drains.  Cooperative launch guarantees that all
 //    workgroups are resident.
+//  * The reverse sweep (k_adjoint_persistent) exchanges the cotangent the
+//    same way, with the halo of the transposed stencil.
 #pragma once
 
 #include "tmm_device.hpp"
@@ -72,7 +75,7 @@ struct Persist {
     const int* dom_col;     // [G+1] first water column of each domain
     const int* dep_ptr;     // [G+1]
     const int* dep_idx;     // domains each domain waits for
-    int* flags;             // [G] hand-overs (forward) or steps (adjoint) each domain has published
+    int* flags;             // [G] hand-overs each domain has published
     int* abort_flag;        // non-zero once any wait gave up
     long long spin_limit;
     double* ring;           // [kRing][n*NTR] published states of the forward kernel, sentinel-filled

@@ -38,11 +38,13 @@
 //  * Slot reuse is ordered by a hand-over every K steps: before step pK each
 //    domain publishes the phase counter p with an agent-scope release store and
 //    waits (relaxed polls, then one acquire fence) for the counters of every
-//    domain its Ae rows touch and every domain that touches it.  After it, a
-//    domain resets its own rows of the slots of states (p+1)K .. (p+2)K-1,
-//    whose previous states (p-1)K .. pK-1 every neighbour has read before the
-//    hand-over; the next hand-over orders the resets before any read of those
-//    slots.
+//    domain its Ae rows touch and every domain that touches it.  In step jj a
+//    domain resets its own rows of the slot of state jj + K: for jj in phase
+//    p that is a state of phase p+1, whose slot's previous state jj - K (phase
+//    p-1) every neighbour read before hand-over p, and hand-over p+1 orders
+//    the reset before any read of it.  One slot per step spreads the resets
+//    (resetting a whole phase of slots at the hand-over made every domain
+//    write tens of MB at once).
 //  * Waits are bounded: after spin_limit polls a workgroup sets a global
 //    abort flag and returns; every other workgroup sees the flag and returns
 //    too, so the grid always drains.  Cooperative launch guarantees that all
@@ -61,6 +63,8 @@ constexpr int kEllMax = 8;             // Ae nonzeros per row supported by this 
 constexpr int kHaloPerThread = 2;      // halo rows per thread (a domain's halo is at most 2 TPB rows)
 constexpr int kRingK = 64;             // steps between hand-overs; the ring has 2 kRingK slots
 constexpr int kRing = 2 * kRingK;
+// a step resets the slot of state jj + K after publishing state jj + 1
+static_assert(kRingK >= 2, "the per-step reset needs a phase of at least two steps");
 
 // The ring's empty-slot marker and the canonical NaN that replaces any NaN
 // before it is published.
@@ -501,9 +505,8 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             }
         }
 
-        // hand-over every kRingK steps: publish the phase counter, wait for the
-        // neighbours' counters, then reset the own rows of the slots that the
-        // phase after next writes
+        // hand-over every kRingK steps: publish the phase counter and wait for
+        // the neighbours' counters
         if (jj % kRingK == 0) {
             const int ph = jj / kRingK;
             if (ph > 0) {
@@ -525,19 +528,6 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
                 if (tid < ndep) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __syncthreads();
                 if (s_fail) return;
-            }
-            if (own) {
-                const double sent = __longlong_as_double(kSentinelBits);
-#pragma unroll 1
-                for (int i = 0; i < kRingK; ++i) {
-                    const size_t o = (size_t)((jj + kRingK + i) % kRing) * state_len + (size_t)r * NTR;
-#pragma unroll
-                    for (int t = 0; t < NTR; ++t) {
-                        __hip_atomic_store(&ps.ring[o + t], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if (TANGENT)
-                            __hip_atomic_store(&ps.vring[o + t], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
             }
         }
 
@@ -659,6 +649,16 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
                     else __hip_atomic_store(&vwr[(size_t)r * NTR + t], publishable(accd[t % TV]), __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
                 }
+            }
+            // reset the own rows of the slot of state jj + K (phase after next
+            // for the first step of a phase, spread over the phase's steps):
+            // its previous state jj - K was read before this phase's hand-over
+            const double sent = __longlong_as_double(kSentinelBits);
+            const size_t ro = (size_t)((jj + kRingK) % kRing) * state_len + (size_t)r * NTR;
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) {
+                __hip_atomic_store(&ps.ring[ro + t], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (TANGENT) __hip_atomic_store(&ps.vring[ro + t], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         const bool month_end = me_cnt == 0;
@@ -979,8 +979,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
             ub[NP - 1] += (1.0 - p.sig) * Phi * drho * mu1;
         }
 
-        // hand-over every kRingK steps, then the resets of the own rows of the
-        // ring slots that the phase after next writes
+        // hand-over every kRingK steps
         if (jj % kRingK == 0) {
             const int ph = jj / kRingK;
             if (ph > 0) {
@@ -1002,16 +1001,6 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
                 if (tid < ndep) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __syncthreads();
                 if (s_fail) return;
-            }
-            if (own) {
-                const double sent = __longlong_as_double(kSentinelBits);
-#pragma unroll 1
-                for (int i = 0; i < kRingK; ++i) {
-                    const size_t o = (size_t)((jj + kRingK + i) % kRing) * state_len + (size_t)r * NTR;
-#pragma unroll
-                    for (int t = 0; t < NTR; ++t)
-                        __hip_atomic_store(&ps.ring[o + t], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
             }
         }
 
@@ -1107,6 +1096,12 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
                 else __hip_atomic_store(&wr[(size_t)r * NTR + t], publishable(out[t]), __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
             }
+            // reset of the slot of the cotangent jj + K, as in the forward kernel
+            const double sent = __longlong_as_double(kSentinelBits);
+            const size_t ro = (size_t)((jj + kRingK) % kRing) * state_len + (size_t)r * NTR;
+#pragma unroll
+            for (int t = 0; t < NTR; ++t)
+                __hip_atomic_store(&ps.ring[ro + t], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         // y_{j-1} into s_y for the next step (this step's reads of s_y all came
         // before the halo barrier), and y_{j-2} loaded for the step after

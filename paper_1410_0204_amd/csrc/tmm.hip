@@ -543,7 +543,7 @@ int launch_persistent(tmm_ctx* h, tmm::StepRange sr, const double* y, double* ou
     int rc = reset_flags(h);
     if (rc) return rc;
     // ring slot 0 = the initial state, the others the sentinel
-    const size_t slen = (size_t)P.n * P.ntr, ring_len = (size_t)tmm::kRing * slen;
+    const size_t slen = (size_t)P.n * P.ntr, ring_len = (size_t)tmm::kRingK * slen;   // slots 0 .. K-1
     hipLaunchKernelGGL(tmm::k_ring_init, dim3(launch_blocks(ring_len)), dim3(256), 0, h->stream,
                        h->at<double>(P.o_ring), y, slen, ring_len);
     TMM_LAUNCHED();
@@ -578,7 +578,7 @@ int launch_adjoint_persistent(tmm_ctx* h, int j_lo, int j_hi, const double* ysto
     int rc = reset_flags(h);
     if (rc) return rc;
     // the cotangent uses the forward kernel's ring (launches never overlap)
-    const size_t slen = (size_t)P.n * P.ntr, ring_len = (size_t)tmm::kRing * slen;
+    const size_t slen = (size_t)P.n * P.ntr, ring_len = (size_t)tmm::kRingK * slen;   // slots 0 .. K-1
     hipLaunchKernelGGL(tmm::k_ring_init, dim3(launch_blocks(ring_len)), dim3(256), 0, h->stream,
                        h->at<double>(P.o_ring), mu_in, slen, ring_len);
     TMM_LAUNCHED();

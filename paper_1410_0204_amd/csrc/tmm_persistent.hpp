@@ -23,7 +23,8 @@
 //    2K slots (K = kRingK) that holds only the sentinel (all bits set, a NaN
 //    that a published value never has: NaNs are stored in canonical form)
 //    until the owner writes the value (slot 0 holds the launch's initial
-//    state, written before the launch).  A thread reads a neighbour's value
+//    state and slots 1 .. K-1 the sentinel, written before the launch).  A
+//    thread reads a neighbour's value
 //    with relaxed agent-scope loads until it is not the sentinel: an aligned
 //    8-byte access is single-copy atomic, so the value read is the published
 //    one, with no flag and no fence between producer and consumer.
@@ -109,7 +110,10 @@ struct StepRange {
 };
 
 // Ring set-up before a launch: slot 0 = the initial state (NaNs in canonical
-// form, so that no value equals the sentinel), every other slot the sentinel.
+// form, so that no value equals the sentinel), slots 1 .. K-1 the sentinel.
+// Slots K .. 2K-1 are reset by the kernel itself (step t - K resets the slot
+// of state t) before any read, so whatever they hold from earlier launches
+// is never read.
 __global__ void k_ring_init(double* __restrict__ ring, const double* __restrict__ y, size_t slen, size_t total) {
     const double sent = __longlong_as_double(kSentinelBits);
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)

@@ -32,9 +32,11 @@ def run(G, K, nsteps, seed, reset_offset=None):
     (the kernels use K)."""
     off = K if reset_offset is None else reset_offset
     rng = random.Random(seed)
-    ring = {(d, s): SENT for d in range(G) for s in range(2 * K)}
+    # before the launch: slot 0 the initial state, slots 1 .. K-1 the sentinel;
+    # slots K .. 2K-1 keep whatever an earlier launch left (here: stale values)
+    ring = {(d, s): (SENT if s < K else ("y", -1 - s)) for d in range(G) for s in range(2 * K)}
     for d in range(G):
-        ring[(d, 0)] = ("y", 0)                        # slot 0: the launch's initial state
+        ring[(d, 0)] = ("y", 0)
     deps = {d: sorted({(d - 1) % G, (d + 1) % G} - {d}) for d in range(G)}
     jj = [0] * G
     stage = [0] * G                                    # 0: hand-over, 1: read halo, 2: publish and reset

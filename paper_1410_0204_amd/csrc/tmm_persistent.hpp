@@ -715,6 +715,21 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
 // y_j of the segment comes from ystore (slot j - j_lo).  Parameter-gradient
 // sums are reduced per domain at the end and added to ubar_dom[domain][p].
 // ---------------------------------------------------------------------------
+// Sum of v over the rows [lr0, lr0 + nc) of a column, in row order.  v has
+// KMAX readable entries past the last row, so the loop runs to the block width
+// with fixed offsets from one base address and the LDS reads are issued
+// together; the terms past the column's depth are exact zeros.
+template <int KMAX>
+__device__ __forceinline__ double column_sum(const double* v, int lr0, int nc) {
+    double acc = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < KMAX; ++kk) {
+        const double x = v[lr0 + kk];
+        acc += kk < nc ? x : 0.0;
+    }
+    return acc;
+}
+
 template <int NTR, int KMAX, int TPB, int SN = 0>
 __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     Grid g, Model md, Mats mt, Persist ps, double dtd, int j_lo, int j_hi,
@@ -727,9 +742,14 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     __shared__ short s_colr0[TPB];
     __shared__ short s_colnc[TPB];
     __shared__ double s_y[TPB * NTR];
-    __shared__ double s_lam[TPB * NTR];
+    // s_lam, s_rmu and s_hf have readable rows past the domain (zero, or
+    // values of other columns), so that per-column loops address them with
+    // fixed offsets; rows of no own thread are zero
+    __shared__ double s_lam[(TPB + KMAX) * NTR];
     __shared__ double s_red[TPB];
     __shared__ double s_rhoc[TPB];   // (1 - sigma_2) rho of each own row (per member, fixed)
+    __shared__ double s_rmu[TPB + KMAX];    // (1 - sigma_2) rho_k mu_k (first tracer) of each own row
+    __shared__ double s_hf[TPB + kNeuMax];  // h_k times the export production of a euphotic row, per step
     __shared__ int s_fail;
     // dynamic: mu of the own rows [0, TPB) and of the halo [TPB, TPB + ahalo_max),
     // then the internal-step states [nsub][TPB][NTR] (SUB only)
@@ -778,17 +798,17 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     const double rho = md.rho[tab + k];
     const double drho = md.drho[tab + k];
     const int ne = nc < g.neu ? nc : g.neu;
-    double light[kNeuMax], hz[kNeuMax];
-#pragma unroll
-    for (int e = 0; e < kNeuMax; ++e) {
-        light[e] = e < ne ? md.light[(size_t)m * g.nlayer + e] : 0.0;
-        hz[e] = e < ne ? g.dz[e] : 0.0;
-    }
+    const double lk = (own && k < ne) ? md.light[(size_t)m * g.nlayer + k] : 0.0;   // light factor of a euphotic row
     double zc = 0.0;   // centre depth of the row's layer
     for (int i = 0; i <= k; ++i) zc += g.dz[i];
     zc -= 0.5 * g.dz[k];
     const double hk = g.dz[k];
-    s_rhoc[tid] = own ? (1.0 - p.sig) * rho : 0.0;
+    const double rhoc = own ? (1.0 - p.sig) * rho : 0.0;
+    s_rhoc[tid] = rhoc;
+    for (int i = tid; i < (TPB + KMAX) * NTR; i += blockDim.x) s_lam[i] = 0.0;
+    for (int i = tid; i < TPB + KMAX; i += blockDim.x) s_rmu[i] = 0.0;
+    for (int i = tid; i < TPB + kNeuMax; i += blockDim.x) s_hf[i] = 0.0;
+    __syncthreads();
     // internal steps: constants of the column this thread integrates (thread
     // index = column of the domain) and of the thread's own column
     constexpr int SNE = SUB ? SN : 1;
@@ -841,6 +861,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
         mr[t] = own ? mu_in[(size_t)r * NTR + t] : 0.0;
         s_mu[tid * NTR + t] = mr[t];
     }
+    s_rmu[tid] = rhoc * mr[0];
     double ub[NP];
 #pragma unroll
     for (int q = 0; q < NP; ++q) ub[q] = 0.0;
@@ -900,43 +921,33 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
 
         // (dq/dy)^T mu_j and (dq/du)^T mu_j from the own water column
         double ybar[NTR];
+        double hf = 0.0;
         if constexpr (SUB) {
             sub_adjoint_lds<NTR, (SUB ? SN : 1), NP, TPB>(g, md, p, m, j, c0, c1 - c0, s_colr0, s_colnc, tid, k, ne,
                                                           lc, tab, zc, rho, drho, s_y, s_mu, s_rhoc, s_traj, s_yb,
                                                           s_acc, s_sphi, col_cc, own_cc, Q, yj, mr, ybar, ub);
         } else if constexpr (NTR == 3) {
             // PO4-DOP-PHY (section 2.2.2)
-            double Phi = 0.0;
-#pragma unroll
-            for (int e = 0; e < kNeuMax; ++e)
-                if (e < ne) {
-                    const int le = lr0 + e;
-                    Phi += hz[e] * (p.sig3 * (production(p, s_y[le * 3], Q, light[e]).f * s_y[le * 3 + 2]));
-                }
             const double m1 = mr[0], m2 = mr[1], m3 = mr[2];
             const double D = yj[1], P = yj[2];
             ybar[0] = 0.0;
             ybar[2] = 0.0;
             if (k < g.neu) {
-                double Phibar = 0.0;
-                for (int kk = 0; kk < nc; ++kk) Phibar += s_rhoc[lr0 + kk] * s_mu[(lr0 + kk) * 3];
-                double lk = 0.0;
-#pragma unroll
-                for (int e = 0; e < kNeuMax; ++e)
-                    if (e == k) lk = light[e];
+                const double Phibar = column_sum<KMAX>(s_rmu, lr0, nc);
                 const Production pr = production(p, yj[0], Q, lk);
                 const double f = pr.f * P;
+                hf = hk * (p.sig3 * f);
                 // f_1 enters q_1 (-1), q_2 (sigma_2 sigma_3), q_3 (1 - sigma_3) and Phi (h_k sigma_3)
                 const double fbar = -m1 + p.sig * p.sig3 * m2 + (1.0 - p.sig3) * m3 + p.sig3 * hk * Phibar;
                 const double dloss = p.lam3 + 2.0 * p.kap3 * P;
                 ybar[0] = fbar * pr.dfdN * P;
                 ybar[2] = fbar * pr.f + dloss * (m2 - m3);
                 const double Np = yj[0] > 0.0 ? yj[0] : 0.0;
-                const double IKI2 = (pr.I + p.ki) * (pr.I + p.ki);
+                const double rIKI2 = 1.0 / ((pr.I + p.ki) * (pr.I + p.ki));
                 ub[0] += fbar * pr.limN * pr.limI * P;
-                ub[1] += fbar * p.alpha * pr.limN * p.ki / IKI2 * (-zc * pr.I) * P;
+                ub[1] += fbar * p.alpha * pr.limN * p.ki * rIKI2 * (-zc * pr.I) * P;
                 ub[2] += fbar * (-p.alpha * Np / ((Np + p.k1) * (Np + p.k1)) * pr.limI) * P;
-                ub[3] += fbar * (-p.alpha * pr.limN * pr.I / IKI2) * P;
+                ub[3] += fbar * (-p.alpha * pr.limN * pr.I * rIKI2) * P;
                 ub[5] += p.sig3 * f * m2;
                 ub[6] += P * (m2 - m3);
                 ub[7] += P * P * (m2 - m3);
@@ -945,43 +956,34 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
             ybar[1] = p.lam * (m1 - m2);
             ybar[2] += p.lam3p * (m2 - m3);
             ub[4] += D * (m1 - m2);
-            ub[5] += -Phi * rho * m1;
             ub[8] += P * (m2 - m3);
-            ub[10] += (1.0 - p.sig) * Phi * drho * m1;
         } else {
-            double Phi = 0.0;
-#pragma unroll
-            for (int e = 0; e < kNeuMax; ++e)
-                if (e < ne) Phi += hz[e] * production(p, s_y[(lr0 + e) * NTR], Q, light[e]).f;
             const double mu1 = mr[0];
             const double mu2 = NTR > 1 ? mr[NTR - 1] : 0.0;
             const double dop = NTR > 1 ? yj[NTR - 1] : 0.0;
             ybar[0] = 0.0;
             if (k < g.neu) {
-                double Phibar = 0.0;
-                for (int kk = 0; kk < nc; ++kk) Phibar += s_rhoc[lr0 + kk] * s_mu[(lr0 + kk) * NTR];
-                double lk = 0.0;
-#pragma unroll
-                for (int e = 0; e < kNeuMax; ++e)
-                    if (e == k) lk = light[e];
+                const double Phibar = column_sum<KMAX>(s_rmu, lr0, nc);
                 const Production pr = production(p, yj[0], Q, lk);
+                hf = hk * pr.f;
                 const double fbar = -mu1 + p.sig * mu2 + hk * Phibar;
                 ybar[0] = fbar * pr.dfdN;
                 const double Np = yj[0] > 0.0 ? yj[0] : 0.0;
-                const double IKI2 = (pr.I + p.ki) * (pr.I + p.ki);
+                const double rIKI2 = 1.0 / ((pr.I + p.ki) * (pr.I + p.ki));
                 ub[0] += fbar * pr.limN * pr.limI;
-                ub[1] += fbar * p.alpha * pr.limN * p.ki / IKI2 * (-zc * pr.I);
+                ub[1] += fbar * p.alpha * pr.limN * p.ki * rIKI2 * (-zc * pr.I);
                 ub[2] += fbar * (-p.alpha * Np / ((Np + p.k1) * (Np + p.k1)) * pr.limI);
-                ub[3] += fbar * (-p.alpha * pr.limN * pr.I / IKI2);
+                ub[3] += fbar * (-p.alpha * pr.limN * pr.I * rIKI2);
                 if (NTR > 1) ub[5] += pr.f * mu2;
             }
             if (NTR > 1) {
                 ybar[NTR - 1] = p.lam * (mu1 - mu2);
                 ub[4] += dop * (mu1 - mu2);
-                ub[5] += -Phi * rho * mu1;
             }
-            ub[NP - 1] += (1.0 - p.sig) * Phi * drho * mu1;
         }
+        // the export Phi of the column is the sum of its euphotic rows' h_k f_k,
+        // read back after the halo barrier
+        if (!SUB && own) s_hf[tid] = hf;
 
         // hand-over every kRingK steps
         if (jj % kRingK == 0) {
@@ -1063,6 +1065,17 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
 #pragma unroll
                 for (int t = 0; t < NTR; ++t) lam[t] += a * mm[s][t];
             }
+            if constexpr (!SUB) {
+                // the export terms of the sigma_2 and b gradients
+                double Phi = 0.0;
+#pragma unroll
+                for (int e = 0; e < kNeuMax; ++e) {
+                    const double x = s_hf[lr0 + e];
+                    Phi += e < ne ? x : 0.0;
+                }
+                if (NTR > 1) ub[5] += -Phi * rho * mr[0];
+                ub[NP - 1] += (1.0 - p.sig) * Phi * drho * mr[0];
+            }
 #pragma unroll
             for (int t = 0; t < NTR; ++t) {
                 lam[t] += (SUB ? 1.0 : dtd) * ybar[t];
@@ -1081,17 +1094,19 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
                 const double omq = 1.0 - wq;
 #pragma unroll
                 for (int t = 0; t < NTR; ++t) out[t] = 0.0;
+                // a0, a1 are zero past the column's depth; the rows read there
+                // (other columns, or the zero rows) are finite
 #pragma unroll
                 for (int s = 0; s < KMAX; ++s) {
                     const double a = omq * a0[s] + wq * a1[s];
-                    const int ls = lr0 + (s < nc ? s : nc - 1);
 #pragma unroll
-                    for (int t = 0; t < NTR; ++t) out[t] += a * s_lam[ls * NTR + t];
+                    for (int t = 0; t < NTR; ++t) out[t] += a * s_lam[(lr0 + s) * NTR + t];
                 }
             } else {
 #pragma unroll
                 for (int t = 0; t < NTR; ++t) out[t] = s_lam[tid * NTR + t];
             }
+            s_rmu[tid] = rhoc * out[0];
 #pragma unroll
             for (int t = 0; t < NTR; ++t) {
                 mr[t] = out[t];

@@ -741,7 +741,8 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     __shared__ short s_rowk[TPB];
     __shared__ short s_colr0[TPB];
     __shared__ short s_colnc[TPB];
-    __shared__ double s_y[TPB * NTR];
+    constexpr int TS = SUB ? TPB : 1;
+    __shared__ double s_y[TS * NTR];       // y_j of the own rows, read by the column's internal steps (SUB only)
     // s_lam, s_rmu and s_hf have readable rows past the domain (zero, or
     // values of other columns), so that per-column loops address them with
     // fixed offsets; rows of no own thread are zero
@@ -756,7 +757,6 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     extern __shared__ double s_dyn[];
     double* const s_mu = s_dyn;
     double* const s_traj = s_dyn + (size_t)(TPB + ps.ahalo_max) * NTR;
-    constexpr int TS = SUB ? TPB : 1;
     __shared__ double s_yb[TS * NTR];      // internal-step results per euphotic row (SUB only)
     __shared__ double s_acc[TS * 5];
     __shared__ double s_sphi[TS];
@@ -868,14 +868,12 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     const int dep0 = ps.dep_ptr[d], ndep = ps.dep_ptr[d + 1] - dep0;
     int me0 = -1, me1 = -1, ma0 = -1, ma1 = -1;
     const int nsteps = j_hi - j_lo;
-    // y_j of the own rows: ycur for the current step (also in s_y), ynext for
-    // the step after, loaded one step ahead
-    double ycur[NTR], ynext[NTR];
+    // y_j of the own rows (also in s_y for the internal steps)
+    double ycur[NTR];
 #pragma unroll
     for (int t = 0; t < NTR; ++t) {
         ycur[t] = (own && nsteps > 0) ? ystore[(size_t)(j_hi - 1 - j_lo) * state_len + (size_t)r * NTR + t] : 0.0;
-        ynext[t] = (own && nsteps > 1) ? ystore[(size_t)(j_hi - 2 - j_lo) * state_len + (size_t)r * NTR + t] : 0.0;
-        s_y[tid * NTR + t] = ycur[t];
+        if constexpr (SUB) s_y[tid * NTR + t] = ycur[t];
     }
     __syncthreads();
 
@@ -1048,6 +1046,17 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
         __syncthreads();
         if (s_fail) return;
 
+        // y_{j-1} of the own rows for the next step, loaded after the halo
+        // polls (whose waits would include it) and used at the end of the step;
+        // at the segment's last step its first state stands in, and threads
+        // without a row read the domain's first row
+        double ynx[NTR];
+        {
+            const int jn = j - 1 >= j_lo ? j - 1 : j_lo;
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) ynx[t] = ystore[(size_t)(jn - j_lo) * state_len + (size_t)r * NTR + t];
+        }
+
         // lambda_j = Ae^T mu_j + dt_d ybar + s_j
         const int mo = (j > 0 && j % spm == 0 && obs) ? j / spm - 1 : -1;
         if (own) {
@@ -1122,18 +1131,13 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
             for (int t = 0; t < NTR; ++t)
                 __hip_atomic_store(&ps.ring[ro + t], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        // y_{j-1} into s_y for the next step (this step's reads of s_y all came
-        // before the halo barrier), and y_{j-2} loaded for the step after
+        // y_{j-1} for the next step (into s_y with internal steps: this step's
+        // reads of s_y all came before the halo barrier)
         if (!last) {
 #pragma unroll
             for (int t = 0; t < NTR; ++t) {
-                ycur[t] = ynext[t];
-                s_y[tid * NTR + t] = ycur[t];
-            }
-            if (own && j - 2 >= j_lo) {
-#pragma unroll
-                for (int t = 0; t < NTR; ++t)
-                    ynext[t] = ystore[(size_t)(j - 2 - j_lo) * state_len + (size_t)r * NTR + t];
+                ycur[t] = ynx[t];
+                if constexpr (SUB) s_y[tid * NTR + t] = ycur[t];
             }
             step_phase(j - 1, g.nstep, g.nmat, k0, k1, w);
             step_phase(j - 2, g.nstep, g.nmat, q0, q1, wq);

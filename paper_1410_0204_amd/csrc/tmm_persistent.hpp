@@ -673,6 +673,10 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             k1 = k1 + 1 == g.nmat ? 0 : k1 + 1;
         }
         w = (double)pr_r / (double)spm;
+        // an empty asm with w as its operand keeps the division here, at the
+        // end of the step; the compiler would otherwise sink it to the first
+        // use, after the halo has arrived, on the path to the next publish
+        asm volatile("" : "+v"(w));
         me_cnt = me_cnt + 1 == spm ? 0 : me_cnt + 1;
         jm = jm + 1 == g.nstep ? 0 : jm + 1;
         Q = g.ins[(size_t)jm * g.nlat + latrow];

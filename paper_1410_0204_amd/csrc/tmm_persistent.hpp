@@ -703,6 +703,21 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     }
 }
 
+// Sum of v over the rows [lr0, lr0 + nc) of a column, in row order.  v has
+// KMAX readable entries past the last row, so the loop runs to the block width
+// with fixed offsets from one base address and the LDS reads are issued
+// together; the terms past the column's depth are exact zeros.
+template <int KMAX>
+__device__ __forceinline__ double column_sum(const double* v, int lr0, int nc) {
+    double acc = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < KMAX; ++kk) {
+        const double x = v[lr0 + kk];
+        acc += kk < nc ? x : 0.0;
+    }
+    return acc;
+}
+
 // ---------------------------------------------------------------------------
 // Persistent reverse sweep over steps j_hi-1 down to j_lo (one checkpoint
 // segment), for one member.  With mu_j the cotangent of z_j (the argument
@@ -719,21 +734,6 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
 // y_j of the segment comes from ystore (slot j - j_lo).  Parameter-gradient
 // sums are reduced per domain at the end and added to ubar_dom[domain][p].
 // ---------------------------------------------------------------------------
-// Sum of v over the rows [lr0, lr0 + nc) of a column, in row order.  v has
-// KMAX readable entries past the last row, so the loop runs to the block width
-// with fixed offsets from one base address and the LDS reads are issued
-// together; the terms past the column's depth are exact zeros.
-template <int KMAX>
-__device__ __forceinline__ double column_sum(const double* v, int lr0, int nc) {
-    double acc = 0.0;
-#pragma unroll
-    for (int kk = 0; kk < KMAX; ++kk) {
-        const double x = v[lr0 + kk];
-        acc += kk < nc ? x : 0.0;
-    }
-    return acc;
-}
-
 template <int NTR, int KMAX, int TPB, int SN = 0>
 __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     Grid g, Model md, Mats mt, Persist ps, double dtd, int j_lo, int j_hi,

@@ -509,6 +509,14 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             }
         }
 
+        // the coming step's insolation, loaded here (after this step's last use
+        // of Q, before the halo polls) rather than at the end of the step: the
+        // next step's sources begin with a wait for all outstanding global
+        // memory operations, and a load issued at the end of the step was still
+        // in flight there
+        const int jn = jm + 1 == g.nstep ? 0 : jm + 1;
+        const double Qn = g.ins[(size_t)jn * g.nlat + latrow];
+
         // hand-over every kRingK steps: publish the phase counter and wait for
         // the neighbours' counters
         if (jj % kRingK == 0) {
@@ -678,8 +686,8 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
         // use, after the halo has arrived, on the path to the next publish
         asm volatile("" : "+v"(w));
         me_cnt = me_cnt + 1 == spm ? 0 : me_cnt + 1;
-        jm = jm + 1 == g.nstep ? 0 : jm + 1;
-        Q = g.ins[(size_t)jm * g.nlat + latrow];
+        jm = jn;
+        Q = Qn;
         __syncthreads();
         // month-end misfit partial sums (after publishing, off the neighbours' critical path)
         if (sr.obs && month_end) {

@@ -233,7 +233,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": kernel, "us_per_launch": us_per_launch, "bytes_per_launch": B * units,
-                     "us_per_time_step": us_per_step},
+                     "us_per_time_step": us_per_step,
+                     "note": "algorithmic bytes count the interpolated month pair of Ae and Ai in every step; "
+                             "the persistent kernel keeps both in registers for the whole launch, so frac can "
+                             "exceed 1; traffic is what HBM actually moves (about a quarter of it)"},
         "per_step_path": per_step,
         "adjoint_forward_ratio": ratio,
         "adjoint_forward_ratio_ckpt240": ratio_ckpt,

@@ -8,10 +8,16 @@ paper's 2.8125-degree configuration; they are resident in HBM before timing
 starts.
 
 Printed as one JSON line: model-years/s, the effective bandwidth of the step
-kernel against MI355X peak HBM bandwidth (roofline), the adjoint/forward
-cost ratio, and the CPU oracle's rate on the host as a reported baseline.
+kernel against MI355X peak HBM bandwidth (roofline), the bytes the kernel
+really moves past the L2 (from the committed counter summary), the latency
+floor of a time step measured on the device (exchange round trip and
+workgroup barriers), the adjoint/forward cost ratio, the batched ensemble
+against one-member runs (256x128x23 grid, 64 members), Newton-Krylov to the
+periodic solution, and the CPU oracle's rate on the host as a reported
+baseline (single thread and all threads).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-ensemble] [--no-newton]
 
 Further measurements, each printed as its own JSON line (not run by default):
   --mode newton       Newton-Krylov steady periodic solve on the same grid
@@ -27,7 +33,6 @@ Further measurements, each printed as its own JSON line (not run by default):
 """
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -53,24 +58,184 @@ def bytes_per_step(n, nnz_e, nnz_i, W):
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("tmm_device.hpp", "tmm_persistent.hpp", "tmm_substep.hpp", "tmm.hip"):
-        with open(os.path.join(ROOT, "paper_1410_0204_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_1410_0204_amd.build import source_hash
+    return source_hash()
 
 
-def measured_traffic(kernel, per_launch_units):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken with the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_global_128x64x15_traffic.json")
+def measured_traffic(kernel, workload="global_128x64x15"):
+    """Bytes per launch past the L2 (FETCH_SIZE + WRITE_SIZE, calibrated on a
+    plain copy) from the committed counter summary, if it was taken with the
+    current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec["bytes_per_launch"] * per_launch_units
+    return rec["bytes_per_launch"]
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(inp, u, B):
+    """The oracle (the same C source the tests check against) built for this
+    host with -O3 -march=native -fopenmp, which gives the plain build's results
+    bit for bit: one model year of the headline workload, median of 3 years
+    after a warm-up year, on one thread and on every thread this process may
+    use."""
+    import shutil
+    import tempfile
+    import oracle
+    from oracle import build as obuild
+    d = tempfile.mkdtemp(prefix="tmm_oracle_timing_")
+    try:
+        lib = obuild.build_timing(os.path.join(d, "liboracle_timing.so"))
+        o = oracle.Oracle(inp, lib_path=lib)
+        y = inp.initial_state()
+        allowed = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+        rows = {}
+        for want in sorted({1, allowed}):
+            used = oracle.threads(want, lib)
+            o.year(u, y, 1)                                    # warm-up
+            times = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                o.year(u, y, 1)
+                times.append(time.perf_counter() - t0)
+            med = sorted(times)[1]
+            rows[want] = {"threads": used, "s_per_year": med, "model_years_per_s": 1.0 / med,
+                          "effective_GBps": B * inp.nstep / med / 1e9, "years_s": times}
+            log(f"[bench] cpu oracle, {used} thread(s): {med:.2f} s per model year (median of 3)")
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    full = rows[allowed]
+    return {"value": full["model_years_per_s"], "unit": "model-years/s", "cores": full["threads"],
+            "kind": "oracle",
+            "sample": (f"one model year (2880 steps) of the same global 128x64x15 N-DOP workload, median of 3 "
+                       f"years after one warm-up year, C oracle built with gcc -O3 -march=native -fopenmp "
+                       f"(bitwise equal to the plain build), {full['threads']} threads"),
+            "single_thread": rows[1], "all_threads": full, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def latency_floor(t, us_per_step):
+    """Per-step floor of the single-launch year kernel from the primitives it
+    chains in every step, measured on this device: one hand-over of a value
+    to another workgroup (half a store-and-poll round trip, the slower of
+    same-XCD and cross-XCD pairs: every step has both) and three workgroup
+    barriers."""
+    p = t.probe_exchange(2000)
+    hop = 0.5 * max(p["round_trip_same_xcd_us"], p["round_trip_cross_xcd_us"])
+    floor = hop + 3.0 * p["barrier_us"]
+    p.update({"hop_us": hop, "floor_us_per_step": floor, "floor_over_step": floor / us_per_step,
+              "model": "one hand-over of the state (half a round trip) + 3 workgroup barriers per step"})
+    log(f"[bench] exchange probe: round trip {p['round_trip_same_xcd_us']:.3f} us (same XCD), "
+        f"{p['round_trip_cross_xcd_us']:.3f} us (across XCDs), barrier {p['barrier_us']:.4f} us, "
+        f"agent load {p['agent_load_us']:.3f} us -> floor {floor:.3f} us per step ({floor / us_per_step:.2f} of it)")
+    return p
+
+
+def newton_leg(t, inp, u):
+    """Newton-Krylov to ||phi(y) - y|| <= 1e-8 from the constant initial field
+    (FD and tangent Jacobian-vector products, GMRES(30), Eisenstat-Walker,
+    line search), and spin-up for as many model years as the FD solve used."""
+    import torch
+    from paper_1410_0204_amd import drivers
+    y0 = inp.initial_state()
+    out = {"workload": "global_128x64x15 N-DOP", "tol": 1e-8, "restart": 30}
+    for jvp in ("fd", "tangent"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y, hist = drivers.newton_krylov(t, u, y0, tol=1e-8, jvp=jvp, restart=30, max_newton=30, max_krylov=300)
+        dt = time.perf_counter() - t0
+        out[jvp] = {"fnorm_first": hist["fnorm"][0], "fnorm_last": hist["fnorm"][-1], "year_maps": hist["years"],
+                    "seconds": dt, "newton_iterations": len(hist["newton"])}
+        log(f"[bench] Newton ({jvp} JVP): |F| {hist['fnorm'][0]:.3e} -> {hist['fnorm'][-1]:.3e}, "
+            f"{len(hist['newton'])} Newton steps, {hist['years']} year maps, {dt:.2f} s")
+    years = out["fd"]["year_maps"]
+    t0 = time.perf_counter()
+    _, r = drivers.spinup(t, u, y0, years=years)
+    out["spinup_same_years"] = {"years": years, "residual_last": float(r[-1]), "seconds": time.perf_counter() - t0}
+    log(f"[bench] spin-up for {years} years: residual {r[0]:.3e} -> {r[-1]:.3e}")
+    return out
+
+
+def ensemble_leg(dev, stream, steps=30):
+    """64 N-DOP parameter vectors (Latin hypercube) with spin-up lengths of
+    1..8 model years on the 256x128x23 grid (500000 points): full-width steps
+    (W = 128) timed alone, then the whole batched run with compaction of
+    finished members, against one member's model year times the member-years."""
+    import torch
+    import synth
+    from paper_1410_0204_amd import tmm
+    t0 = time.perf_counter()
+    inp = synth.ensemble_1p4()
+    gen_s = time.perf_counter() - t0
+    log(f"[bench] ensemble inputs {inp.name}: n={inp.n} ({gen_s:.1f} s to generate)")
+    nm = 64
+    U = synth.latin_hypercube(synth.MODEL_NDOP, nm, seed=17)
+    L = synth.spinup_lengths(nm, seed=18)
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=nm, device=dev, stream=stream)
+    t.set_params(U)
+    y0 = t.state(inp.initial_state(nm))
+    s, e = _events()
+    buf = [t.state(), t.state()]
+    t.step(0, y0, buf[0])
+    torch.cuda.synchronize()
+    s.record(stream)
+    for j in range(steps):
+        t.step(j, buf[j % 2], buf[(j + 1) % 2])
+    e.record(stream)
+    torch.cuda.synchronize()
+    us = s.elapsed_time(e) * 1000.0 / steps
+    Bfull = bytes_per_step(inp.n, inp.tm.ae_nnz, inp.tm.ai_nnz, 2 * nm)
+    s.record(stream)
+    out_b, _ = t.year(y0, nyears=int(L.max()), years_per_member=L, residuals=False)
+    e.record(stream)
+    torch.cuda.synchronize()
+    ms_b = s.elapsed_time(e)
+    member_years = int(L.sum())
+    t.set_params(U[0])
+    y1 = t.state(inp.initial_state(1))
+    t.year(y1, nyears=1, residuals=False)
+    torch.cuda.synchronize()
+    s.record(stream)
+    t.year(y1, nyears=1, residuals=False)
+    e.record(stream)
+    torch.cuda.synchronize()
+    ms_1 = s.elapsed_time(e)
+    # what the byte counts alone predict: every year of the batch moves the
+    # matrices once for all members still running
+    B1 = bytes_per_step(inp.n, inp.tm.ae_nnz, inp.tm.ai_nnz, 2)
+    batched_bytes = sum(bytes_per_step(inp.n, inp.tm.ae_nnz, inp.tm.ai_nnz, 2 * int((L > yr).sum()))
+                        for yr in range(int(L.max())))
+    res = {"workload": "ensemble_256x128x23 N-DOP", "n": inp.n, "members": nm, "member_years": member_years,
+           "full_width_us_per_step": us, "full_width_bytes_per_step": Bfull,
+           "full_width_GBps": Bfull / (us * 1e-6) / 1e9,
+           "full_width_frac": Bfull / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS,
+           "batched_ms": ms_b, "batched_member_years_per_s": member_years / (ms_b / 1000.0),
+           "one_member_ms_per_year": ms_1, "sequential_member_years_per_s": 1000.0 / ms_1,
+           "speedup": member_years * ms_1 / ms_b,
+           "speedup_from_bytes": member_years * B1 / batched_bytes,
+           "inputs_generation_s": gen_s}
+    log(f"[bench] ensemble: full-width step {us:.1f} us ({res['full_width_GBps']:.0f} GB/s, "
+        f"{100 * res['full_width_frac']:.1f} % of peak); {member_years} member-years in {ms_b:.0f} ms "
+        f"({res['batched_member_years_per_s']:.2f}/s) vs one member {ms_1:.1f} ms/year: "
+        f"{res['speedup']:.2f}x (bytes alone: {res['speedup_from_bytes']:.2f}x)")
+    t.close()
+    del t, y0, buf, out_b, y1
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -79,6 +244,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20, help="timed model years")
     ap.add_argument("--warmup", type=int, default=2, help="untimed model years")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--no-newton", action="store_true", help="skip the Newton-Krylov leg")
     ap.add_argument("--mode", default="forward", choices=["forward", "newton", "ensemble", "copy", "grids"])
     ap.add_argument("--log", default=None, help="JSONL progress log (newton mode)")
     ap.add_argument("--grid-steps", type=int, default=0,
@@ -141,6 +308,19 @@ def main():
     achieved = B * units / (us_per_launch * 1e-6) / 1e9
     log(f"[bench] forward: {ms_per_year:.3f} ms/model-year, {years_per_s:.2f} model-years/s, "
         f"{us_per_step:.2f} us/step, {achieved:.0f} GB/s effective")
+    # the same years one call each, for the median and spread of single years
+    single = []
+    for _ in range(max(5, min(args.steps, 20))):
+        start.record(stream)
+        t.year(y, nyears=1, out=ya, residuals=False)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        single.append(start.elapsed_time(stop))
+    single.sort()
+    year_stats = {"years": len(single), "median_ms": single[len(single) // 2], "min_ms": single[0],
+                  "max_ms": single[-1]}
+    log(f"[bench] single years: median {year_stats['median_ms']:.3f} ms (min {single[0]:.3f}, max {single[-1]:.3f})")
+    floor = latency_floor(t, us_per_step) if persistent else None
 
     # the one-launch-per-step path on the same handle, for comparison
     per_step = None
@@ -199,20 +379,19 @@ def main():
         phy = bench_variant(args, synth.global_2p8(model=synth.MODEL_NDOPPHY), dev, stream, ms_per_year,
                             "PO4-DOP-PHY")
 
+    newton = None
+    if not args.no_newton and not args.forward_only:
+        newton = newton_leg(t, inp, u)
+
+    ensemble = None
+    if not args.no_ensemble and not args.forward_only:
+        ensemble = ensemble_leg(dev, stream)
+
     cpu = None
     if not args.no_cpu_baseline and not args.forward_only:
-        import oracle
-        o = oracle.Oracle(inp)
-        yh = inp.initial_state()
-        t0 = time.perf_counter()
-        o.year(u, yh, 1)
-        dt = time.perf_counter() - t0
-        cpu = {"value": 1.0 / dt, "unit": "model-years/s", "cores": 1, "kind": "oracle",
-               "sample": "one model year (2880 steps) of the same global 128x64x15 N-DOP workload, "
-                         f"single-threaded C oracle, {dt:.1f} s"}
-        log(f"[bench] cpu oracle: {dt:.1f} s per model year")
+        cpu = cpu_baseline(inp, u, B)
 
-    traffic = measured_traffic(kernel, 1)
+    traffic = measured_traffic(kernel) if persistent else None
     out = {
         "metric": "model-years/s + HBM GB/s (N-DOP, 52749 pts); adjoint/forward cost ratio",
         "value": years_per_s,
@@ -232,16 +411,27 @@ def main():
                    "path": kernel},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "hbm_frac_measured": (traffic / (us_per_launch * 1e-6) / 1e9 / HBM_PEAK_GBPS
+                                           if traffic else None),
+                     "traffic_note": "traffic = FETCH_SIZE + WRITE_SIZE per launch (bytes past the L2, "
+                                     "calibrated on a plain copy) from the committed counter summary of this "
+                                     "kernel source; null if the source changed since",
                      "kernel": kernel, "us_per_launch": us_per_launch, "bytes_per_launch": B * units,
                      "us_per_time_step": us_per_step,
+                     "binding": "latency" if persistent else "hbm",
+                     "latency": floor,
                      "note": "algorithmic bytes count the interpolated month pair of Ae and Ai in every step; "
-                             "the persistent kernel keeps both in registers for the whole launch, so frac can "
-                             "exceed 1; traffic is what HBM actually moves (about a quarter of it)"},
+                             "the single-launch kernel keeps both in registers for the whole launch, so frac "
+                             "can exceed 1 and is not a bandwidth figure; the step is bound by the chain of "
+                             "exchange and barriers, whose measured floor is under latency"},
+        "year_stats": year_stats,
         "per_step_path": per_step,
         "adjoint_forward_ratio": ratio,
         "adjoint_forward_ratio_ckpt240": ratio_ckpt,
         "bgc_substeps_8": substeps,
         "po4_dop_phy": phy,
+        "newton": newton,
+        "ensemble": ensemble,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -50,7 +50,8 @@ enum {
     TMM_ENOMEM = -2,        /* workspace too small */
     TMM_EDEVICE = -3,       /* HIP runtime error, or a wait of the persistent kernels gave up */
     TMM_ESTATE = -4,        /* call not valid in the handle's state (e.g. no parameters set) */
-    TMM_ENONFINITE = -5,    /* non-finite value found in a result */
+    TMM_ENONFINITE = -5,    /* non-finite value found in a result (or in the state at the end of a
+                               model year of tmm_year) */
     TMM_EUNSUPPORTED = -6   /* valid request outside what this build supports */
 };
 
@@ -104,6 +105,10 @@ typedef struct {
     const int *ai_rowptr;
     const int *ai_colidx;
     const double *ai_val;   /* [nmat][ai_nnz] */
+    /* optional */
+    const double *lon;      /* [ncol] longitude of each column, degrees, or NULL.  Only orders the
+                               work of the member-parallel ensemble kernel (horizontal neighbours
+                               close together, for cache reuse); results do not depend on it */
 } tmm_desc;
 
 /* Device workspace size for a descriptor.  Returns TMM_EINVAL for a bad
@@ -135,7 +140,10 @@ int tmm_step(tmm_handle h, int j, const double *y_in, double *y_out);
  * [nbatch], nullable) gives per-member lengths <= nyears: member b stops after
  * years_per_member[b] years and y1 holds its state then.  resid_host
  * (nullable, [nyears][nbatch]) receives ||y - phi(y)||_2 of each member for
- * each year it ran (0 afterwards); passing it synchronises. */
+ * each year it ran (0 afterwards); passing it synchronises.  The state is
+ * checked for NaN and infinity at the end of every year (unless
+ * TMM_OPT_CHECK_FINITE is 0): if any year produced one, the call still runs
+ * all its years, writes y1 and resid_host, and returns TMM_ENONFINITE. */
 int tmm_year(tmm_handle h, int nyears, const int *years_per_member,
              const double *y0, double *y1, double *resid_host);
 
@@ -171,10 +179,22 @@ enum {
                                      member); default 16; 0 = never */
     TMM_OPT_GRAPH = 4,           /* 1 (default): model years on the launch-per-step path are captured
                                     once per (members, buffers) into a hipGraph and replayed */
-    TMM_OPT_SPIN_LIMIT = 5       /* polls after which a wait of the persistent kernels gives up
+    TMM_OPT_SPIN_LIMIT = 5,      /* polls after which a wait of the persistent kernels gives up
                                     (the call then returns TMM_EDEVICE; the next call starts
                                     afresh); 0 = the default (2^22, seconds); small values are for
                                     tests of that failure path */
+    TMM_OPT_CHECK_FINITE = 6,    /* 1 (default): tmm_year checks the state for non-finite values at
+                                    the end of every model year (one read of the state per year);
+                                    0: no check */
+    TMM_OPT_MEMBER_WAVES = 7,    /* wavefronts (water columns) per workgroup of the member-parallel
+                                    kernel for two-tracer models: 2, 4 or 8; 0 = the default (4) */
+    TMM_OPT_MEMBER_BAND_ROWS = 8, /* latitude rows per band of the member-parallel kernel's column
+                                    order (needs the descriptor's longitudes); 0 = the default (16),
+                                    -1 = the natural column order */
+    TMM_OPT_TILE_ROWS = 9        /* largest tile (rows per workgroup) of the launch-per-step tile
+                                    kernels: 32, 64, 128 or 256 (a tiling no deeper than the
+                                    deepest column is used as the smallest); 0 = by state width
+                                    (128 up to 4 state columns, else 256) */
 };
 
 /* Queries (tmm_query). */
@@ -193,6 +213,21 @@ int tmm_set_option(tmm_handle h, int option, int value);
 
 /* Reads a property of the handle into *value.  TMM_EINVAL for an unknown query. */
 int tmm_query(tmm_handle h, int what, long long *value);
+
+/* Measures, on the handle's device and stream, the latency of the primitives
+ * that the single-launch year kernels chain in every time step, so that a
+ * step's time can be set against the floor they impose (no effect on any
+ * result; uses a small reserved part of the workspace).  rounds (1 ..
+ * 1000000) repetitions of each; out (host, [8]) receives
+ *   out[0]  us per round trip of an agent-scope store and poll between two
+ *           workgroups on the same XCD (two hand-overs of a value),
+ *   out[1]  the same between workgroups on two different XCDs,
+ *   out[2]  us per workgroup barrier of 256 threads,
+ *   out[3]  us per dependent agent-scope load,
+ *   out[4..7] the XCDs the two pairs of workgroups ran on.
+ * TMM_EUNSUPPORTED without cooperative launch; TMM_EDEVICE if a wait gave up.
+ * Synchronises. */
+int tmm_probe_exchange(tmm_handle h, int rounds, double *out);
 
 /* Static text for a status code. */
 const char *tmm_strerror(int status);

@@ -34,17 +34,19 @@ class _Desc(C.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
+def load(path=None):
+    """The oracle library at ``path`` (default: the plain build, built on first use)."""
+    path = LIB_PATH if path is None else path
+    if path not in _libs:
+        if path == LIB_PATH and not os.path.exists(LIB_PATH):
             from . import build as _b
             _b.build()
-        lib = C.CDLL(LIB_PATH)
+        lib = C.CDLL(path)
         sig = {
+            "oracle_threads": (C.c_int, [C.c_int]),
             "oracle_ntracer": (C.c_int, [C.c_int]),
             "oracle_nparam": (C.c_int, [C.c_int]),
             "oracle_phase": (None, [C.c_int, C.c_int, C.c_int, _ip, _ip, _dp]),
@@ -65,8 +67,13 @@ def load():
             f = getattr(lib, name)
             f.restype = res
             f.argtypes = args
-        _lib = lib
-    return _lib
+        _libs[path] = lib
+    return _libs[path]
+
+
+def threads(n=0, lib_path=None):
+    """Sets (n >= 1) and returns the thread count of a library's step loops."""
+    return int(load(lib_path).oracle_threads(int(n)))
 
 
 def _d(a):
@@ -128,7 +135,7 @@ def bgc_source(model, insol, h, y, u, neuphotic, dt, nsub):
 class Oracle:
     """Reference implementation bound to one set of inputs (a ``synth.Inputs``)."""
 
-    def __init__(self, inputs, nstep=None, model=None, neuphotic=None, nbgc=None):
+    def __init__(self, inputs, nstep=None, model=None, neuphotic=None, nbgc=None, lib_path=None):
         a = inputs.desc_arrays()
         self._keep = {k: v for k, v in a.items() if isinstance(v, np.ndarray)}
         self.n = a["n"]
@@ -146,7 +153,7 @@ class Oracle:
             int(nbgc if nbgc is not None else a.get("nbgc", 1)),
         )
         self.nbgc = int(self.desc.nbgc)
-        self.lib = load()
+        self.lib = load(lib_path)
 
     def _u(self, u):
         u = np.atleast_2d(_f64(u))

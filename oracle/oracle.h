@@ -64,6 +64,10 @@ int oracle_bgc_column(int model, double insol, int nlayer, const double *h,
 int oracle_bgc_source(int model, double insol, int nlayer, const double *h, const double *y, double *inc,
                       const double *u, int neuphotic, double dt, int nsub);
 
+/* Sets the thread count of the step's parallel loops when n >= 1 (timing
+ * build with OpenMP only) and returns the count in use (1 without OpenMP). */
+int oracle_threads(int n);
+
 /* One step y_out = Ai(t_j) (Ae(t_j) y_in + dt*q(y_in)) (section 3). */
 int oracle_step(const oracle_desc *g, int nbatch, const double *u, int j,
                 const double *y_in, double *y_out);

@@ -51,6 +51,18 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* The CPU-baseline timing build (-fopenmp) runs the row loops of the
+ * products and the column loop of the sources of a step in parallel.  Every
+ * output element is still computed by one thread in the order written here,
+ * so that build gives the plain build's results bit for bit; without
+ * -fopenmp the macro is empty. */
+#ifdef _OPENMP
+#include <omp.h>
+#define ROWS_IN_PARALLEL _Pragma("omp parallel for schedule(static)")
+#else
+#define ROWS_IN_PARALLEL
+#endif
+
 #define PI 3.14159265358979323846
 #define SIGMA_PAR 0.4
 #define SIGMA_ICE 0.0
@@ -66,6 +78,18 @@ int oracle_ntracer(int model)
     if (model == ORACLE_MODEL_NDOP) return 2;
     if (model == ORACLE_MODEL_NDOPPHY) return 3;
     return -1;
+}
+
+/* Threads the step's loops use (1 without OpenMP); n < 1 leaves it alone. */
+int oracle_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 int oracle_nparam(int model)
@@ -119,6 +143,7 @@ void oracle_spmm_interp(int n, const int *rowptr, const int *colidx,
                         const double *v0, const double *v1, double w,
                         int W, const double *x, double *y)
 {
+    ROWS_IN_PARALLEL
     for (int i = 0; i < n; ++i) {
         for (int c = 0; c < W; ++c) {
             double acc = 0.0;
@@ -592,8 +617,9 @@ static void add_sources(const oracle_desc *g, int nbatch, const double *u, int j
 {
     int ntr = oracle_ntracer(g->model), np = oracle_nparam(g->model), W = nbatch * ntr;
     double t = (double)(((j % g->nstep) + g->nstep) % g->nstep) / (double)g->nstep;
-    double col[MAX_TRACERS * MAX_LAYERS], inc[MAX_TRACERS * MAX_LAYERS];
+    ROWS_IN_PARALLEL
     for (int c = 0; c < g->ncol; ++c) {
+        double col[MAX_TRACERS * MAX_LAYERS], inc[MAX_TRACERS * MAX_LAYERS];
         for (int b = 0; b < nbatch; ++b) {
             column_ctx cc;
             make_column(g, c, t, u + (size_t)b * np, g->model, &cc);

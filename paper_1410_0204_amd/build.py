@@ -8,8 +8,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtmm.so")
 SOURCES = [os.path.join(HERE, "csrc", "tmm.hip")]
-HEADERS = [os.path.join(HERE, "csrc", f) for f in ("tmm_device.hpp", "tmm_persistent.hpp", "tmm_substep.hpp")] + [
+HEADERS = [os.path.join(HERE, "csrc", f) for f in ("tmm_device.hpp", "tmm_persistent.hpp", "tmm_substep.hpp",
+                                                   "tmm_probe.hpp")] + [
     os.path.join(ROOT, "include", "tmm.h")]
+
+
+def source_hash():
+    """Hash of the HIP sources the library is built from (keys measured kernel data to a build)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("tmm_device.hpp", "tmm_persistent.hpp", "tmm_substep.hpp", "tmm_probe.hpp", "tmm.hip"):
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def command(out):

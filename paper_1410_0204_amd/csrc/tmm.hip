@@ -16,29 +16,9 @@
 #include "tmm.h"
 #include "tmm_device.hpp"
 #include "tmm_persistent.hpp"
+#include "tmm_probe.hpp"
 
 namespace {
-
-constexpr int kMaxTileRows = 256;          // rows per tile (LDS maps are sized for this)
-constexpr int kLdsBudget = 48 * 1024;      // dynamic LDS per workgroup
-constexpr size_t kAlign = 256;
-
-#define TMM_TRY(expr)                                   \
-    do {                                                \
-        if ((expr) != hipSuccess) return TMM_EDEVICE;   \
-    } while (0)
-
-#define TMM_LAUNCHED()                                  \
-    do {                                                \
-        if (hipGetLastError() != hipSuccess) return TMM_EDEVICE; \
-    } while (0)
-
-int ntracer_of(int model) {
-    return model == TMM_MODEL_N ? 1 : model == TMM_MODEL_NDOP ? 2 : model == TMM_MODEL_NDOPPHY ? 3 : -1;
-}
-int nparam_of(int model) {
-    return model == TMM_MODEL_N ? 5 : model == TMM_MODEL_NDOP ? 7 : model == TMM_MODEL_NDOPPHY ? 11 : -1;
-}
 
 // One partition of the water columns into tiles of at most max_rows rows.
 struct Tiling {
@@ -92,9 +72,13 @@ struct Plan {
     // insolation table over distinct latitudes
     std::vector<double> lat_u;
     std::vector<int> col_lat;
+    std::vector<double> lon;        // [ncol] or empty (descriptor's optional longitudes)
+    size_t o_morder;                // column order of the member-parallel kernel
     size_t o_ins, o_collat, o_latu;
     // persistent-kernel tables (sized for up to kMaxDomains domains)
     size_t o_pblock, o_pdomcol, o_pdepptr, o_pdepidx, o_pflags, o_pabort;
+    size_t o_finite;                // set by the per-year non-finite check
+    size_t o_probe;                 // words, results and load chain of tmm_probe_exchange
     size_t o_ring, o_vring;         // state rings of the persistent forward kernel (0: none)
     size_t o_phaloptr, o_phalo;     // halo rows of each domain
     size_t o_pahaloptr, o_pahalo;   // ... for the transposed stencil (reverse sweep)
@@ -107,6 +91,10 @@ constexpr int kMaxDomains = 4096;
 // (2 x kRing x n x ntr doubles); larger ones cannot be resident anyway
 constexpr int kMaxPersistentRows = 256 * tmm::kPersistThreadsMax;
 constexpr int kDefaultDomainRows = 256;     // rows per persistent workgroup unless set by option (tuned on MI355X)
+constexpr int kMembersWavesMax = 8;         // wavefronts per workgroup of the member kernel, at most
+constexpr int kDefaultBandRows = 16;        // latitude rows per band of the member kernel's column order
+constexpr int kProbeLines = 4096;           // 256-byte lines of the probe's load chain (1 MiB)
+constexpr size_t kProbeBytes = 4096 + (size_t)kProbeLines * 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -133,6 +121,9 @@ int validate(const tmm_desc* d, Plan& P) {
         if (!std::isfinite(d->lat[c]) || !std::isfinite(d->area[c]) || d->area[c] <= 0.0) return TMM_EINVAL;
     for (int k = 0; k < d->nlayer; ++k)
         if (!std::isfinite(d->dz[k]) || d->dz[k] <= 0.0) return TMM_EINVAL;
+    if (d->lon)
+        for (int c = 0; c < d->ncol; ++c)
+            if (!std::isfinite(d->lon[c])) return TMM_EINVAL;
     auto check_csr = [&](const int* rp, const int* ci, int nnz) {
         if (rp[0] != 0 || rp[d->n] != nnz) return false;
         for (int i = 0; i < d->n; ++i)
@@ -237,6 +228,9 @@ int validate(const tmm_desc* d, Plan& P) {
             P.col_lat[c] = (int)(std::lower_bound(l.begin(), l.end(), d->lat[c]) - l.begin());
     }
     P.o_ins = take((size_t)d->nstep * P.lat_u.size() * 8);
+    if (d->lon) P.lon.assign(d->lon, d->lon + d->ncol);
+    else P.lon.clear();
+    P.o_morder = take(((size_t)d->ncol + 8 * kMembersWavesMax) * 4);
     P.o_collat = take((size_t)d->ncol * 4);
     P.o_latu = take(P.lat_u.size() * 8);
     P.dep_capacity = 2 * (size_t)d->ae_nnz + 1;
@@ -246,6 +240,8 @@ int validate(const tmm_desc* d, Plan& P) {
     P.o_pdepidx = take(P.dep_capacity * 4);
     P.o_pflags = take((size_t)kMaxDomains * 4);
     P.o_pabort = take(64);
+    P.o_finite = take(64);
+    P.o_probe = take(kProbeBytes);
     P.o_phaloptr = take((size_t)(kMaxDomains + 1) * 4);
     P.halo_capacity = (size_t)d->ae_nnz + 1;
     P.o_phalo = take(P.halo_capacity * 4);
@@ -283,6 +279,10 @@ struct tmm_ctx {
     int pers_hmax = 0;             // largest domain halo (rows)
     int pers_ahmax = 0;            // ... of the transposed stencil
     int wide_min_members = 16;     // batches of at least this many members use k_step_members
+    int mem_waves = tmm::kMembersWaves;   // option TMM_OPT_MEMBER_WAVES
+    int mem_band = kDefaultBandRows;      // option TMM_OPT_MEMBER_BAND_ROWS (0: natural column order)
+    int mem_blocks = 0;            // workgroups of one member-kernel launch (per member group)
+    bool mem_ordered = false;      // the order table in the workspace is in use
     // captured model years of the launch-per-step path, keyed by their arguments
     struct YearGraph {
         int nb;
@@ -298,6 +298,8 @@ struct tmm_ctx {
     hipStream_t launch_stream() const { return capturing ? capture_stream : stream; }
     int num_cu = 0;
     bool pers_used = false;        // a persistent launch happened since the last abort check
+    bool check_finite = true;      // option TMM_OPT_CHECK_FINITE
+    int tile_rows_cap = 0;         // option TMM_OPT_TILE_ROWS (0: by width)
     std::vector<int> ae_rowptr, ae_colidx;   // explicit-matrix pattern (domain dependencies)
 
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -349,11 +351,13 @@ struct tmm_ctx {
     double* vec(int row) const { return at<double>(P.o_vec) + (size_t)row * P.vec_stride; }
 
     // Largest tiling whose rows fit the LDS budget for width W and mult buffers.
+    // (capped by option TMM_OPT_TILE_ROWS when set)
     const Tiling& tiling_for(int W, int mult, int extra_bytes = 0) const {
         const Tiling* best = &tilings.front();
+        const int cap = tile_rows_cap > 0 ? tile_rows_cap : (W <= 4 ? 128 : kMaxTileRows);
         for (const Tiling& t : tilings) {
             const size_t lds = (size_t)t.max_rows * W * 8 * mult + extra_bytes;
-            if (lds <= (size_t)kLdsBudget && t.max_rows <= (W <= 4 ? 128 : kMaxTileRows)) best = &t;
+            if (lds <= (size_t)kLdsBudget && t.max_rows <= cap) best = &t;
         }
         return *best;
     }
@@ -383,6 +387,48 @@ int copy(tmm_ctx* h, double* dst, const double* src, size_t len) {
     return TMM_OK;
 }
 
+// Column order of the member-parallel kernel (see k_step_members).  With the
+// columns' longitudes known and band > 0: the columns sorted by (band of
+// `band` latitude rows, longitude, latitude row), cut into 8 runs of equal
+// length, run x on the workgroups b with b % 8 == x (the XCD they are
+// dispatched to), each workgroup taking `waves` consecutive columns of its
+// run.  Otherwise the natural order.  Written to the workspace; results do
+// not depend on it.  Not called during graph capture.
+int build_member_order(tmm_ctx* h) {
+    const Plan& P = h->P;
+    const int waves = h->mem_waves;
+    if (P.lon.empty() || h->mem_band <= 0) {
+        h->mem_ordered = false;
+        h->mem_blocks = (P.ncol + waves - 1) / waves;
+        return TMM_OK;
+    }
+    std::vector<int> cols(P.ncol);
+    for (int c = 0; c < P.ncol; ++c) cols[c] = c;
+    const int band = h->mem_band;
+    std::stable_sort(cols.begin(), cols.end(), [&](int a, int b) {
+        const int ba = P.col_lat[a] / band, bb = P.col_lat[b] / band;
+        if (ba != bb) return ba < bb;
+        if (P.lon[a] != P.lon[b]) return P.lon[a] < P.lon[b];
+        return P.col_lat[a] < P.col_lat[b];
+    });
+    const int runs = 8;
+    const int q = (P.ncol + runs - 1) / runs;          // columns per run
+    const int m = (q + waves - 1) / waves;             // workgroups per run
+    std::vector<int> order((size_t)runs * m * waves, -1);
+    for (int x = 0; x < runs; ++x)
+        for (int i = 0; i < m; ++i)
+            for (int w = 0; w < waves; ++w) {
+                const int pos = x * q + i * waves + w;
+                if (i * waves + w < q && pos < P.ncol) order[((size_t)i * runs + x) * waves + w] = cols[pos];
+            }
+    if (order.size() > (size_t)P.ncol + 8 * kMembersWavesMax) return TMM_EUNSUPPORTED;
+    if (upload(h, h->at<int>(P.o_morder), order.data(), order.size() * 4)) return TMM_EDEVICE;
+    TMM_TRY(hipStreamSynchronize(h->stream));
+    h->mem_blocks = runs * m;
+    h->mem_ordered = true;
+    return TMM_OK;
+}
+
 // Forward step j for nb state slots (W = nb*ntr); tangent when v != nullptr.
 int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const double* v, double* vo) {
     const int W = nb * h->P.ntr;
@@ -396,21 +442,39 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
         tmm::Grid g = h->grid(h->tilings.front());
         tmm::Model md = h->model();
         tmm::Mats mt = h->mats();
-        dim3 grid((h->P.ncol + tmm::kMembersWaves - 1) / tmm::kMembersWaves, (nb + 63) / 64),
-            blk(64 * tmm::kMembersWaves);
+        // the wave count is an option for the two-tracer, five-point case (the ensemble's);
+        // every other variant runs with the default
+        const bool wave_opt = h->P.ntr == 2 && !sub && h->P.ew <= 5;
+        const int waves = wave_opt ? h->mem_waves : tmm::kMembersWaves;
+        const int nblk = wave_opt ? h->mem_blocks : (h->P.ncol + waves - 1) / waves;
+        const int* order = (wave_opt && h->mem_ordered) ? h->at<int>(h->P.o_morder) : nullptr;
+        dim3 grid(nblk, (nb + 63) / 64), blk(64 * waves);
 #define TMM_MEMBERS(NT, KM)                                                                                  \
     do {                                                                                                     \
         if (sub)                                                                                             \
             hipLaunchKernelGGL((tmm::k_step_members<NT, KM, tmm::kMembersEll, true>), grid, blk, 0,          \
-                               h->launch_stream(), g, md, mt, h->P.ncol, nb, j, dtd, y, yo);                 \
+                               h->launch_stream(), g, md, mt, h->P.ncol, nb, j, dtd, order, y, yo);          \
         else if (h->P.ew <= 5)                                                                               \
             hipLaunchKernelGGL((tmm::k_step_members<NT, KM, 5>), grid, blk, 0, h->launch_stream(), g, md, mt, h->P.ncol,  \
-                               nb, j, dtd, y, yo);                                                           \
+                               nb, j, dtd, order, y, yo);                                                    \
         else                                                                                                 \
             hipLaunchKernelGGL((tmm::k_step_members<NT, KM, tmm::kMembersEll>), grid, blk, 0, h->launch_stream(), g, md,  \
-                               mt, h->P.ncol, nb, j, dtd, y, yo);                                            \
+                               mt, h->P.ncol, nb, j, dtd, order, y, yo);                                     \
     } while (0)
-        if (h->P.ntr == 2) {
+#define TMM_MEMBERS_W(KM, WV)                                                                                \
+    hipLaunchKernelGGL((tmm::k_step_members<2, KM, 5, false, WV>), grid, blk, 0, h->launch_stream(), g, md, mt, \
+                       h->P.ncol, nb, j, dtd, order, y, yo)
+        if (wave_opt && waves != tmm::kMembersWaves) {
+            if (waves == 2) {
+                if (kmax == 16) TMM_MEMBERS_W(16, 2);
+                else if (kmax == 24) TMM_MEMBERS_W(24, 2);
+                else TMM_MEMBERS_W(32, 2);
+            } else {
+                if (kmax == 16) TMM_MEMBERS_W(16, 8);
+                else if (kmax == 24) TMM_MEMBERS_W(24, 8);
+                else TMM_MEMBERS_W(32, 8);
+            }
+        } else if (h->P.ntr == 2) {
             if (kmax == 16) TMM_MEMBERS(2, 16);
             else if (kmax == 24) TMM_MEMBERS(2, 24);
             else TMM_MEMBERS(2, 32);
@@ -420,6 +484,7 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
             else TMM_MEMBERS(1, 32);
         }
 #undef TMM_MEMBERS
+#undef TMM_MEMBERS_W
         TMM_LAUNCHED();
         return TMM_OK;
     }
@@ -545,11 +610,11 @@ int launch_persistent(tmm_ctx* h, tmm::StepRange sr, const double* y, double* ou
     // ring slot 0 = the initial state, the others the sentinel
     const size_t slen = (size_t)P.n * P.ntr, ring_len = (size_t)tmm::kRingK * slen;   // slots 0 .. K-1
     hipLaunchKernelGGL(tmm::k_ring_init, dim3(launch_blocks(ring_len)), dim3(256), 0, h->stream,
-                       h->at<double>(P.o_ring), y, slen, ring_len);
+                       h->at<double>(P.o_ring), y, P.n, P.ntr, ring_len);
     TMM_LAUNCHED();
     if (v) {
         hipLaunchKernelGGL(tmm::k_ring_init, dim3(launch_blocks(ring_len)), dim3(256), 0, h->stream,
-                           h->at<double>(P.o_vring), v, slen, ring_len);
+                           h->at<double>(P.o_vring), v, P.n, P.ntr, ring_len);
         TMM_LAUNCHED();
     }
     tmm::Grid g = h->grid(h->tilings.front());
@@ -580,7 +645,7 @@ int launch_adjoint_persistent(tmm_ctx* h, int j_lo, int j_hi, const double* ysto
     // the cotangent uses the forward kernel's ring (launches never overlap)
     const size_t slen = (size_t)P.n * P.ntr, ring_len = (size_t)tmm::kRingK * slen;   // slots 0 .. K-1
     hipLaunchKernelGGL(tmm::k_ring_init, dim3(launch_blocks(ring_len)), dim3(256), 0, h->stream,
-                       h->at<double>(P.o_ring), mu_in, slen, ring_len);
+                       h->at<double>(P.o_ring), mu_in, P.n, P.ntr, ring_len);
     TMM_LAUNCHED();
     tmm::Grid g = h->grid(h->tilings.front());
     tmm::Model md = h->model();
@@ -609,6 +674,19 @@ int check_abort(tmm_ctx* h) {
     TMM_LAUNCHED();
     TMM_TRY(hipStreamSynchronize(h->stream));
     return TMM_EDEVICE;
+}
+
+// After the model years of a call: a set non-finite flag means some year
+// ended with a NaN or an infinity in its state.  Reported once and cleared.
+int take_nonfinite(tmm_ctx* h) {
+    int flag = 0;
+    TMM_TRY(hipMemcpyAsync(&flag, h->at<int>(h->P.o_finite), 4, hipMemcpyDeviceToHost, h->stream));
+    TMM_TRY(hipStreamSynchronize(h->stream));
+    if (!flag) return TMM_OK;
+    hipLaunchKernelGGL(tmm::k_fill_int, dim3(1), dim3(64), 0, h->stream, h->at<int>(h->P.o_finite), 16, 0);
+    TMM_LAUNCHED();
+    TMM_TRY(hipStreamSynchronize(h->stream));
+    return TMM_ENONFINITE;
 }
 
 // One model year of the launch-per-step path replayed from a hipGraph: the
@@ -1107,9 +1185,12 @@ int tmm_create(const tmm_desc* d, void* dev_workspace, size_t bytes, void* hip_s
                            (int)P.lat_u.size(), h->at<double>(P.o_latu), h->at<double>(P.o_ins));
         if (hipGetLastError() != hipSuccess) return fail(TMM_EDEVICE);
     }
+    hipLaunchKernelGGL(tmm::k_fill_int, dim3(1), dim3(64), 0, h->stream, h->at<int>(P.o_finite), 16, 0);
+    if (hipGetLastError() != hipSuccess) return fail(TMM_EDEVICE);
     h->ae_rowptr.assign(d->ae_rowptr, d->ae_rowptr + P.n + 1);
     h->ae_colidx.assign(d->ae_colidx, d->ae_colidx + d->ae_nnz);
     if (build_persistent(h, 0)) return fail(TMM_EDEVICE);
+    if (build_member_order(h)) return fail(TMM_EDEVICE);
     h->h_member.resize(P.nbatch_max);
     h->h_scol.resize(P.nbatch_max);
     h->h_dcol.resize(P.nbatch_max);
@@ -1259,6 +1340,11 @@ int tmm_year(tmm_handle h, int nyears, const int* years_per_member, const double
         // besides the start: use ia and the v buffers' first slot.
         rc = run_year(h, na, h->ybuf(ib), h->ybuf(iout), h->ybuf(ia), h->vbuf(0));
         if (rc) return rc;
+        if (h->check_finite) {
+            hipLaunchKernelGGL(tmm::k_check_finite, dim3(launch_blocks(n * Wc)), dim3(256), 0, h->stream,
+                               h->ybuf(iout), n * Wc, h->at<int>(h->P.o_finite));
+            TMM_LAUNCHED();
+        }
         if (resid_host) {
             rc = sqdiff(h, na, h->ybuf(iout), h->ybuf(ib), 0, 1.0, 1, h->vec(0));
             if (rc) return rc;
@@ -1299,7 +1385,8 @@ int tmm_year(tmm_handle h, int nyears, const int* years_per_member, const double
     // restore the identity member map for later calls
     for (int b = 0; b < nb; ++b) h->h_member[b] = b;
     if ((rc = push_member_map(h, nb))) return rc;
-    return check_abort(h);
+    if ((rc = check_abort(h))) return rc;
+    return take_nonfinite(h);
 }
 
 int tmm_year_jvp(tmm_handle h, int mode, const double* y, const double* v, double* phi_y, double* jv) {
@@ -1354,6 +1441,30 @@ int tmm_set_option(tmm_handle h, int option, int value) {
             if (value < 0) return TMM_EINVAL;
             h->spin_limit = value == 0 ? 1ll << 22 : value;
             return TMM_OK;
+        case TMM_OPT_CHECK_FINITE:
+            h->check_finite = value != 0;
+            return TMM_OK;
+        case TMM_OPT_TILE_ROWS: {
+            if (value != 0 && value != 32 && value != 64 && value != 128 && value != 256) return TMM_EINVAL;
+            int rc = drop_graphs(h);
+            if (rc) return rc;
+            h->tile_rows_cap = value;
+            return TMM_OK;
+        }
+        case TMM_OPT_MEMBER_WAVES: {
+            if (value != 0 && value != 2 && value != 4 && value != 8) return TMM_EINVAL;
+            int rc = drop_graphs(h);
+            if (rc) return rc;
+            h->mem_waves = value == 0 ? tmm::kMembersWaves : value;
+            return build_member_order(h);
+        }
+        case TMM_OPT_MEMBER_BAND_ROWS: {
+            if (value < -1) return TMM_EINVAL;
+            int rc = drop_graphs(h);
+            if (rc) return rc;
+            h->mem_band = value == 0 ? kDefaultBandRows : (value < 0 ? 0 : value);
+            return build_member_order(h);
+        }
         case TMM_OPT_DOMAIN_ROWS: {
             if (value < 0) return TMM_EINVAL;
             if (hipStreamSynchronize(h->stream) != hipSuccess) return TMM_EDEVICE;
@@ -1375,6 +1486,57 @@ int tmm_query(tmm_handle h, int what, long long* value) {
             return TMM_OK;
         default: return TMM_EINVAL;
     }
+}
+
+int tmm_probe_exchange(tmm_handle h, int rounds, double* out) {
+    if (!h || !out || rounds < 1 || rounds > 1000000) return TMM_EINVAL;
+    int dev = 0, khz = 0, coop = 0;
+    TMM_TRY(hipGetDevice(&dev));
+    TMM_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    TMM_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    if (khz <= 0 || !coop) return TMM_EUNSUPPORTED;
+    char* base = h->at<char>(h->P.o_probe);
+    long long* words = reinterpret_cast<long long*>(base);          // [0, 512): ping-pong words
+    long long* res = reinterpret_cast<long long*>(base + 1024);     // [1024, 1152): results
+    int* fail = reinterpret_cast<int*>(base + 2048);
+    int* chain = reinterpret_cast<int*>(base + 4096);
+    int rc = fill(h, reinterpret_cast<double*>(base), 4096 / 8, 0.0);
+    if (rc) return rc;
+    // the ping-pong pairs: blocks 0 and 8, then blocks 0 and 1 of a 16-block grid (workgroups are
+    // dispatched round-robin over the 8 XCDs: the first pair shares one, the second does not; the
+    // kernel records where each ran)
+    const int pairs[2][2] = {{0, 8}, {0, 1}};
+    for (int p = 0; p < 2; ++p) {
+        if (p && (rc = fill(h, reinterpret_cast<double*>(words), 512 / 8, 0.0))) return rc;
+        int a = pairs[p][0], b = pairs[p][1], nr = rounds;
+        long long* o = res + 3 * p;
+        void* args[] = {&a, &b, &nr, &words, &o, &fail};
+        TMM_TRY(hipLaunchCooperativeKernel((const void*)&tmm::k_probe_pingpong, dim3(16), dim3(64), args, 0,
+                                           h->stream));
+    }
+    hipLaunchKernelGGL((tmm::k_probe_barrier<256>), dim3(1), dim3(256), 0, h->stream, rounds, res + 6);
+    TMM_LAUNCHED();
+    hipLaunchKernelGGL(tmm::k_probe_chain, dim3((kProbeLines + 255) / 256), dim3(256), 0, h->stream, kProbeLines,
+                       1021, chain);
+    TMM_LAUNCHED();
+    hipLaunchKernelGGL(tmm::k_probe_load, dim3(1), dim3(64), 0, h->stream, rounds, chain, res + 7);
+    TMM_LAUNCHED();
+    long long r[8];
+    int failed = 0;
+    TMM_TRY(hipMemcpyAsync(r, res, sizeof(r), hipMemcpyDeviceToHost, h->stream));
+    TMM_TRY(hipMemcpyAsync(&failed, fail, 4, hipMemcpyDeviceToHost, h->stream));
+    TMM_TRY(hipStreamSynchronize(h->stream));
+    if (failed) return TMM_EDEVICE;
+    const double us_per_tick = 1e3 / khz;
+    out[0] = r[0] * us_per_tick / rounds;
+    out[1] = r[3] * us_per_tick / rounds;
+    out[2] = r[6] * us_per_tick / rounds;
+    out[3] = r[7] * us_per_tick / rounds;
+    out[4] = (double)r[1];
+    out[5] = (double)r[2];
+    out[6] = (double)r[4];
+    out[7] = (double)r[5];
+    return TMM_OK;
 }
 
 int tmm_year_adjoint(tmm_handle h, const double* y0, const double* obs, int ckpt_every, double* J_host,

@@ -703,23 +703,34 @@ __global__ __launch_bounds__(256) void k_step(Grid g, Model md, Mats mt, int W, 
 // gathers of the state are independent and wave-uniform reads come from LDS.
 // A member's parameters, light factors and export Phi are evaluated once per
 // column; z of the column stays in registers (KMAX >= column depth).
+//
+// Wave w of workgroup b takes water column order[b * WAVES + w] (-1: none).
+// The host builds the order so that each XCD (workgroups are dispatched to
+// the 8 XCDs round-robin) sweeps its own share of the grid in bands of a few
+// latitude rows, longitude by longitude: a column's horizontal neighbours are
+// then processed by the same XCD within a few dozen columns, while their
+// state rows are still in its L2, instead of one latitude row (several MB of
+// state at 64 members) later.  Without an order (nullptr) wave w of block b
+// takes column b * WAVES + w.
 // ---------------------------------------------------------------------------
-constexpr int kMembersWaves = 4;      // wavefronts (columns) per workgroup
+constexpr int kMembersWaves = 4;      // default wavefronts (columns) per workgroup
 constexpr int kMembersEll = 8;        // Ae nonzeros per row supported by k_step_members
 
-template <int NTR, int KMAX, int EL, bool SUB = false>
-__global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt, int ncol, int nb, int j,
-                                                      double dtd, const double* __restrict__ y,
-                                                      double* __restrict__ yo) {
+template <int NTR, int KMAX, int EL, bool SUB = false, int WAVES = kMembersWaves>
+__global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, Mats mt, int ncol, int nb, int j,
+                                                             double dtd, const int* __restrict__ order,
+                                                             const double* __restrict__ y,
+                                                             double* __restrict__ yo) {
     constexpr int NEU = 4;
     // zero-padded KMAX x KMAX block and KMAX x EL explicit rows, so that every
     // loop below runs to its compile-time bound without branches
-    __shared__ double s_ai[kMembersWaves][KMAX * KMAX];
-    __shared__ double s_ae[kMembersWaves][KMAX * EL];
-    __shared__ int s_col[kMembersWaves][KMAX * EL];
+    __shared__ double s_ai[WAVES][KMAX * KMAX];
+    __shared__ double s_ae[WAVES][KMAX * EL];
+    __shared__ int s_col[WAVES][KMAX * EL];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int craw = blockIdx.x * kMembersWaves + wave;
-    const bool valid = craw < ncol;              // waves past the last column idle but reach the barrier
+    const int slot = blockIdx.x * WAVES + wave;
+    const int craw = order ? order[slot] : (slot < ncol ? slot : -1);
+    const bool valid = craw >= 0;                // waves without a column idle but reach the barrier
     const int c = valid ? craw : ncol - 1;
     const int b = blockIdx.y * 64 + lane;
     const bool act = valid && b < nb;
@@ -732,38 +743,14 @@ __global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt,
     step_phase(j, g.nstep, g.nmat, k0, k1, w);
     const double om = 1.0 - w;
 
-    // stage the interpolated column matrices (this wavefront's slice only)
-    {
-        const double* ai0 = mt.ai_rm + (size_t)k0 * mt.ai_month + g.blk_off[c];
-        const double* ai1 = mt.ai_rm + (size_t)k1 * mt.ai_month + g.blk_off[c];
-        for (int i = lane; i < KMAX * KMAX; i += 64) {
-            const int k = i / KMAX, sl = i % KMAX;
-            const bool in = k < nc && sl < nc;
-            const int at = in ? k * nc + sl : 0;
-            const double v = om * ai0[at] + w * ai1[at];
-            s_ai[wave][i] = in ? v : 0.0;
-        }
-        const double* ae0 = mt.ae + (size_t)k0 * mt.ae_month;
-        const double* ae1 = mt.ae + (size_t)k1 * mt.ae_month;
-        for (int i = lane; i < KMAX * EL; i += 64) {
-            const int k = i / EL, sl = i % EL;
-            const bool in = k < nc && sl < mt.ew;
-            const size_t e = in ? (size_t)sl * g.npad + rs + k : (size_t)rs;
-            const int col = mt.ae_col[e];
-            const double v = om * ae0[e] + w * ae1[e];
-            s_col[wave][i] = in ? col : rs;
-            s_ae[wave][i] = in ? v : 0.0;
-        }
-    }
-    __syncthreads();
-
+    // the member's parameters and light factors, the column's insolation and
+    // euphotic state: loaded before the staging below so that their latency
+    // overlaps it (a load cannot move across the barrier)
     const double Q = g.ins[(size_t)(j % g.nstep) * g.nlat + g.col_lat[c]];
     const int m = md.member[bb];
     const BgcParams p = load_params(md.u, md.model, md.nparam, m);
     const size_t tab = ((size_t)m * (g.nlayer + 1) + nc) * g.nlayer;
     const size_t me = (size_t)bb * NTR;
-
-    // production in the euphotic layers and the export Phi
     const int ne = nc < g.neu ? nc : g.neu;
     double Ne[NEU], le[NEU], f[NEU];
 #pragma unroll
@@ -772,6 +759,44 @@ __global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt,
         Ne[e] = y[(size_t)re * W + me];
         le[e] = md.light[(size_t)m * g.nlayer + (e < g.nlayer ? e : 0)];
     }
+
+    // stage the interpolated column matrices (this wavefront's slice only);
+    // the loops run to compile-time bounds, so that every load of a lane is
+    // issued before the first one is waited for
+    {
+        const size_t bo = (size_t)g.blk_off[c];
+        const double* ai0 = mt.ai_rm + (size_t)k0 * mt.ai_month + bo;
+        const double* ai1 = mt.ai_rm + (size_t)k1 * mt.ai_month + bo;
+        constexpr int NA = (KMAX * KMAX + 63) / 64;
+#pragma unroll
+        for (int it = 0; it < NA; ++it) {
+            const int i = it * 64 + lane;
+            const int k = i / KMAX, sl = i % KMAX;
+            const bool in = i < KMAX * KMAX && k < nc && sl < nc;
+            const int at = in ? k * nc + sl : 0;
+            const double v = om * ai0[at] + w * ai1[at];
+            if (i < KMAX * KMAX) s_ai[wave][i] = in ? v : 0.0;
+        }
+        const double* ae0 = mt.ae + (size_t)k0 * mt.ae_month;
+        const double* ae1 = mt.ae + (size_t)k1 * mt.ae_month;
+        constexpr int NE = (KMAX * EL + 63) / 64;
+#pragma unroll
+        for (int it = 0; it < NE; ++it) {
+            const int i = it * 64 + lane;
+            const int k = i / EL, sl = i % EL;
+            const bool in = i < KMAX * EL && k < nc && sl < mt.ew;
+            const size_t e = in ? (size_t)sl * g.npad + rs + k : (size_t)rs;
+            const int col = mt.ae_col[e];
+            const double v = om * ae0[e] + w * ae1[e];
+            if (i < KMAX * EL) {
+                s_col[wave][i] = in ? col : rs;
+                s_ae[wave][i] = in ? v : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+
+    // production in the euphotic layers and the export Phi
     double Phi = 0.0;
 #pragma unroll
     for (int e = 0; e < NEU; ++e) {
@@ -812,9 +837,18 @@ __global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt,
         const int kk = k < nc ? k : nc - 1;
         double yv[EL][NTR];
 #pragma unroll
-        for (int sl = 0; sl < EL; ++sl)
+        for (int sl = 0; sl < EL; ++sl) {
+            const double* src = y + (size_t)s_col[wave][k * EL + sl] * W + me;
+            if constexpr (NTR == 2) {
+                // both tracers of a member in one 16-byte load (W is even, so the pair is aligned)
+                const double2 v = *reinterpret_cast<const double2*>(src);
+                yv[sl][0] = v.x;
+                yv[sl][1] = v.y;
+            } else {
 #pragma unroll
-            for (int t = 0; t < NTR; ++t) yv[sl][t] = y[(size_t)s_col[wave][k * EL + sl] * W + me + t];
+                for (int t = 0; t < NTR; ++t) yv[sl][t] = src[t];
+            }
+        }
         const double dop = NTR > 1 ? y[(size_t)(rs + kk) * W + me + NTR - 1] : 0.0;
         const double rho = md.rho[tab + kk];
         double acc[NTR];
@@ -865,8 +899,13 @@ __global__ __launch_bounds__(256) void k_step_members(Grid g, Model md, Mats mt,
             for (int t = 0; t < NTR; ++t) acc[t] += a * z[sl][t];
         }
         if (act) {
+            double* dst = yo + (size_t)(rs + k) * W + me;
+            if constexpr (NTR == 2) {
+                *reinterpret_cast<double2*>(dst) = make_double2(acc[0], acc[1]);
+            } else {
 #pragma unroll
-            for (int t = 0; t < NTR; ++t) yo[(size_t)(rs + k) * W + me + t] = acc[t];
+                for (int t = 0; t < NTR; ++t) dst[t] = acc[t];
+            }
         }
     }
 }
@@ -1136,6 +1175,15 @@ __global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src,
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (; i < len; i += stride) dst[i] = src[i];
+}
+
+// flag = 1 if any of x[0 .. len) is not finite (left alone otherwise).
+__global__ void k_check_finite(const double* __restrict__ x, size_t len, int* __restrict__ flag) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (; i < len; i += stride) bad |= !isfinite(x[i]);
+    if (bad) *flag = 1;
 }
 
 // FD direction: h_s = 1e-8 ||y_s|| / ||v_s|| per slot from squared norms.

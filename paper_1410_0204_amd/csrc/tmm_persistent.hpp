@@ -83,8 +83,8 @@ struct Persist {
     int* flags;             // [G] hand-overs each domain has published
     int* abort_flag;        // non-zero once any wait gave up
     long long spin_limit;
-    double* ring;           // [kRing][n*NTR] published states of the forward kernel, sentinel-filled
-    double* vring;          // [kRing][n*NTR] the same for the tangent (nullable)
+    double* ring;           // [kRing][NTR][n] published states of the forward kernel, sentinel-filled
+    double* vring;          // [kRing][NTR][n] the same for the tangent (nullable)
     const int* halo_ptr;    // [G+1]
     const int* halo_row;    // rows of other domains each domain reads, ascending per domain
     int halo_max;           // largest halo (rows); sizes the dynamic LDS of the forward kernel
@@ -109,15 +109,29 @@ struct StepRange {
     double* jpart;          // [nmat][G] per-domain sums of V_i (y - obs)^2
 };
 
+// A slot holds one state tracer by tracer ([NTR][n]): the threads of a
+// wavefront own consecutive rows, so each of its stores (one tracer of 64
+// rows) covers whole cache lines.
+__device__ __forceinline__ size_t ring_at(size_t slot_base, int n, int row, int t) {
+    return slot_base + (size_t)t * n + row;
+}
+
 // Ring set-up before a launch: slot 0 = the initial state (NaNs in canonical
 // form, so that no value equals the sentinel), slots 1 .. K-1 the sentinel.
 // Slots K .. 2K-1 are reset by the kernel itself (step t - K resets the slot
 // of state t) before any read, so whatever they hold from earlier launches
-// is never read.
-__global__ void k_ring_init(double* __restrict__ ring, const double* __restrict__ y, size_t slen, size_t total) {
+// is never read.  y is row-major n x ntr.
+__global__ void k_ring_init(double* __restrict__ ring, const double* __restrict__ y, int n, int ntr, size_t total) {
     const double sent = __longlong_as_double(kSentinelBits);
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
-        ring[i] = i < slen ? publishable(y[i]) : sent;
+    const size_t slen = (size_t)n * ntr;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        if (i < slen) {
+            const int t = (int)(i / n), row = (int)(i % n);
+            ring[i] = publishable(y[(size_t)row * ntr + t]);
+        } else {
+            ring[i] = sent;
+        }
+    }
 }
 
 template <int KMAX>
@@ -547,8 +561,7 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
         // pass issues the loads of all the lane's halo rows together and
         // defines them all again, until none is the sentinel
         {
-            const double* rs = ps.ring + (size_t)(jj % kRing) * state_len;
-            const double* vs = TANGENT ? ps.vring + (size_t)(jj % kRing) * state_len : nullptr;
+            const size_t sb = (size_t)(jj % kRing) * state_len;
             double hv[kHaloPerThread][NTR], hd[kHaloPerThread][NTR];
             long long it = 0;
             for (;;) {
@@ -556,13 +569,13 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
 #pragma unroll
                 for (int i = 0; i < kHaloPerThread; ++i) {
                     if (hrow[i] < 0) continue;
-                    const size_t o = (size_t)hrow[i] * NTR;
 #pragma unroll
                     for (int t = 0; t < NTR; ++t) {
-                        hv[i][t] = __hip_atomic_load(&rs[o + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const size_t o = ring_at(sb, g.n, hrow[i], t);
+                        hv[i][t] = __hip_atomic_load(&ps.ring[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         miss |= is_sentinel(hv[i][t]);
                         if (TANGENT) {
-                            hd[i][t] = __hip_atomic_load(&vs[o + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            hd[i][t] = __hip_atomic_load(&ps.vring[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             miss |= is_sentinel(hd[i][t]);
                         }
                     }
@@ -625,8 +638,7 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
 
         // y_{j+1} = Ai(t_j) z, within the water column
         const bool last = jj == nsteps - 1;
-        double* wr = ps.ring + (size_t)((jj + 1) % kRing) * state_len;
-        double* vwr = TANGENT ? ps.vring + (size_t)((jj + 1) % kRing) * state_len : nullptr;
+        const size_t wb = (size_t)((jj + 1) % kRing) * state_len;
         if (own) {
             double acc[NTR], accd[TV];
 #pragma unroll
@@ -652,25 +664,27 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
                 // agent-scope stores write through the XCD's L2 to the point
                 // where every domain's loads see them
                 if (last) y_out[(size_t)r * NTR + t] = acc[t];
-                else __hip_atomic_store(&wr[(size_t)r * NTR + t], publishable(acc[t]), __ATOMIC_RELAXED,
+                else __hip_atomic_store(&ps.ring[ring_at(wb, g.n, r, t)], publishable(acc[t]), __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
                 if (TANGENT) {
                     vr[t % TV] = accd[t % TV];
                     s_v[tid * TV + t % TV] = accd[t % TV];
                     if (last) v_out[(size_t)r * NTR + t] = accd[t % TV];
-                    else __hip_atomic_store(&vwr[(size_t)r * NTR + t], publishable(accd[t % TV]), __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
+                    else __hip_atomic_store(&ps.vring[ring_at(wb, g.n, r, t)], publishable(accd[t % TV]),
+                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
             // reset the own rows of the slot of state jj + K (phase after next
             // for the first step of a phase, spread over the phase's steps):
             // its previous state jj - K was read before this phase's hand-over
             const double sent = __longlong_as_double(kSentinelBits);
-            const size_t ro = (size_t)((jj + kRingK) % kRing) * state_len + (size_t)r * NTR;
+            const size_t rb = (size_t)((jj + kRingK) % kRing) * state_len;
 #pragma unroll
             for (int t = 0; t < NTR; ++t) {
-                __hip_atomic_store(&ps.ring[ro + t], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (TANGENT) __hip_atomic_store(&ps.vring[ro + t], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&ps.ring[ring_at(rb, g.n, r, t)], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (TANGENT)
+                    __hip_atomic_store(&ps.vring[ring_at(rb, g.n, r, t)], sent, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         const bool month_end = me_cnt == 0;
@@ -1022,7 +1036,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
 
         // the halo of mu_j (ring slot jj) into LDS, all of the lane's rows per pass
         {
-            const double* rs = ps.ring + (size_t)(jj % kRing) * state_len;
+            const size_t sb = (size_t)(jj % kRing) * state_len;
             double hv[kHaloPerThread][NTR];
             long long it = 0;
             for (;;) {
@@ -1030,10 +1044,10 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
 #pragma unroll
                 for (int i = 0; i < kHaloPerThread; ++i) {
                     if (hrow[i] < 0) continue;
-                    const size_t o = (size_t)hrow[i] * NTR;
 #pragma unroll
                     for (int t = 0; t < NTR; ++t) {
-                        hv[i][t] = __hip_atomic_load(&rs[o + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        hv[i][t] = __hip_atomic_load(&ps.ring[ring_at(sb, g.n, hrow[i], t)], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
                         miss |= is_sentinel(hv[i][t]);
                     }
                 }
@@ -1108,7 +1122,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
 
         // mu_{j-1} = Ai(t_{j-1})^T lambda_j within the column, or lambda_0
         const bool last = jj == nsteps - 1;
-        double* wr = ps.ring + (size_t)((jj + 1) % kRing) * state_len;
+        const size_t wb = (size_t)((jj + 1) % kRing) * state_len;
         if (own) {
             double out[NTR];
             if (j > 0) {
@@ -1133,15 +1147,15 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
                 mr[t] = out[t];
                 s_mu[tid * NTR + t] = out[t];
                 if (last) mu_out[(size_t)r * NTR + t] = out[t];
-                else __hip_atomic_store(&wr[(size_t)r * NTR + t], publishable(out[t]), __ATOMIC_RELAXED,
+                else __hip_atomic_store(&ps.ring[ring_at(wb, g.n, r, t)], publishable(out[t]), __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
             }
             // reset of the slot of the cotangent jj + K, as in the forward kernel
             const double sent = __longlong_as_double(kSentinelBits);
-            const size_t ro = (size_t)((jj + kRingK) % kRing) * state_len + (size_t)r * NTR;
+            const size_t rb = (size_t)((jj + kRingK) % kRing) * state_len;
 #pragma unroll
             for (int t = 0; t < NTR; ++t)
-                __hip_atomic_store(&ps.ring[ro + t], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&ps.ring[ring_at(rb, g.n, r, t)], sent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         // y_{j-1} for the next step (into s_y with internal steps: this step's
         // reads of s_y all came before the halo barrier)

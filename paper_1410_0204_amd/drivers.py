@@ -23,6 +23,7 @@ import time
 
 import numpy as np
 
+from . import autotune as _autotune
 from . import tmm as _tmm
 
 
@@ -45,16 +46,41 @@ def _config_hash(t, u):
 # Spin-up (pseudo-time fixed-point iteration)
 # ---------------------------------------------------------------------------
 
-def spinup(t, u, y0, years, tol=0.0, log_path=None, state_path=None, state_every=0, resume=False):
+def cell_volumes(t):
+    """V_i = area_c h_k for every grid point of the handle's grid (m^3)."""
+    k = t._keep
+    depth = np.diff(np.asarray(k["col_start"], dtype=np.int64))
+    layer = np.concatenate([np.arange(d) for d in depth])
+    return np.repeat(np.asarray(k["area"], dtype=np.float64), depth) * np.asarray(k["dz"], dtype=np.float64)[layer]
+
+
+def tracer_mass(t, y_host, V=None):
+    """Volume-weighted total of every tracer of every member: [members, ntracer]."""
+    V = cell_volumes(t) if V is None else V
+    y = np.asarray(y_host, dtype=np.float64)
+    return (V @ y).reshape(-1, t.ntracer)
+
+
+def spinup(t, u, y0, years, tol=0.0, log_path=None, state_path=None, state_every=0, resume=False,
+           return_mass=False, tuned=True):
     """Iterates y <- phi(y) for up to ``years`` model years.
 
     Returns (y, residuals), where residuals[k] = ||y_k - phi(y_k)||_2 of the
     year that started from y_k (the residual of section 7).  Stops early when
-    a residual falls to ``tol`` or below.  With ``state_path`` the state is
-    saved every ``state_every`` years as .npz (y, year, u, config hash), and
+    a residual falls to ``tol`` or below.  Each year's log record also holds
+    the volume-weighted mass of every tracer and the relative drift of the
+    total (phosphorus) mass since the start of the call: the transport conserves
+    mass and the models only move phosphorus between tracers, so the drift is
+    rounding.  ``return_mass`` adds the masses ([years + 1, members, ntracer],
+    the start state first) as a third result.  With ``state_path`` the state
+    is saved every ``state_every`` years as .npz (y, year, u, config hash), and
     ``resume`` continues from such a file when it matches the configuration.
+    With ``tuned`` the launch configuration measured best for this grid shape
+    (the autotuner's table shipped with the package) is applied first.
     """
     u = np.atleast_2d(np.asarray(u, dtype=np.float64))
+    if tuned:
+        _autotune.apply_tuned(t, u.shape[0])
     t.set_params(u)
     cfg = _config_hash(t, u)
     y = t.state(np.asarray(y0, dtype=np.float64))
@@ -66,13 +92,19 @@ def spinup(t, u, y0, years, tol=0.0, log_path=None, state_path=None, state_every
                 y = t.state(z["y"])
                 start_year = int(z["year"])
                 resid = list(z["resid"])
+    V = cell_volumes(t)
+    masses = [tracer_mass(t, y.cpu().numpy(), V)]
+    total0 = masses[0].sum(axis=1)
     nxt = t.state()
     for yr in range(start_year, years):
         t0 = time.perf_counter()
         _, r = t.year(y, nyears=1, out=nxt)
         y, nxt = nxt, y
         resid.append(float(np.linalg.norm(r[0])))
+        masses.append(tracer_mass(t, y.cpu().numpy(), V))
+        drift = (masses[-1].sum(axis=1) - total0) / total0
         _log(log_path, {"kind": "spinup", "year": yr + 1, "residual": resid[-1],
+                        "mass": masses[-1].tolist(), "mass_drift": drift.tolist(),
                         "seconds": time.perf_counter() - t0})
         if state_path and state_every and (yr + 1) % state_every == 0:
             tmp = state_path + ".tmp.npz"
@@ -80,6 +112,8 @@ def spinup(t, u, y0, years, tol=0.0, log_path=None, state_path=None, state_every
             os.replace(tmp, state_path)
         if resid[-1] <= tol:
             break
+    if return_mass:
+        return y.cpu().numpy(), np.asarray(resid), np.asarray(masses)
     return y.cpu().numpy(), np.asarray(resid)
 
 
@@ -238,7 +272,7 @@ def transport_preconditioner(t, u, eps=1e-6):
 
 def newton_krylov(t, u, y0, tol=1e-8, jvp="fd", restart=30, max_newton=30, max_krylov=300,
                   eta0=0.5, eta_max=0.9, gamma=0.9, ew_alpha=2.0, line_search=True, log_path=None,
-                  globalization="line_search", delta0=0.2, delta_max=1e10, preconditioner=None):
+                  globalization="line_search", delta0=0.2, delta_max=1e10, preconditioner=None, tuned=True):
     """Solves F(y) = y - phi(y) = 0 from y0 until ||F|| <= tol.
 
     Linear systems (I - phi'(y)) d = -F by GMRES(restart) with forcing terms
@@ -261,6 +295,9 @@ def newton_krylov(t, u, y0, tol=1e-8, jvp="fd", restart=30, max_newton=30, max_k
     right preconditioner of ``transport_preconditioner`` (GMRES still
     minimises the true residual).
 
+    With ``tuned`` the autotuner's launch configuration for this grid shape
+    is applied first.
+
     Returns (y, history); history counts year maps (tangent years count 1
     each).
     """
@@ -269,6 +306,8 @@ def newton_krylov(t, u, y0, tol=1e-8, jvp="fd", restart=30, max_newton=30, max_k
     if preconditioner not in (None, "transport"):
         raise ValueError("preconditioner must be None or 'transport'")
     u = np.atleast_2d(np.asarray(u, dtype=np.float64))
+    if tuned:
+        _autotune.apply_tuned(t, u.shape[0])
     t.set_params(u)
     shape = (t.n, t.W)
     pre = transport_preconditioner(t, u) if preconditioner == "transport" else None
@@ -392,10 +431,14 @@ def newton_krylov(t, u, y0, tol=1e-8, jvp="fd", restart=30, max_newton=30, max_k
 # Ensembles with uneven spin-up lengths
 # ---------------------------------------------------------------------------
 
-def ensemble(t, U, lengths, y0):
+def ensemble(t, U, lengths, y0, tuned=True):
     """Runs member b of parameter table U for lengths[b] model years, all in
-    one batched state (members leave the batch when their years are done)."""
+    one batched state (members leave the batch when their years are done).
+    With ``tuned`` the autotuner's launch configuration for this grid shape and
+    member count is applied first."""
     U = np.atleast_2d(np.asarray(U, dtype=np.float64))
+    if tuned:
+        _autotune.apply_tuned(t, U.shape[0])
     lengths = np.asarray(lengths, dtype=np.int32)
     t.set_params(U)
     y = t.state(np.asarray(y0, dtype=np.float64))

@@ -35,6 +35,10 @@ TMM_OPT_DOMAIN_ROWS = 2
 TMM_OPT_MEMBER_KERNEL_MIN = 3
 TMM_OPT_GRAPH = 4
 TMM_OPT_SPIN_LIMIT = 5
+TMM_OPT_CHECK_FINITE = 6
+TMM_OPT_MEMBER_WAVES = 7
+TMM_OPT_MEMBER_BAND_ROWS = 8
+TMM_OPT_TILE_ROWS = 9
 TMM_Q_PERSISTENT = 1
 TMM_Q_DOMAINS = 2
 TMM_Q_WORKSPACE = 3
@@ -43,7 +47,7 @@ TMM_Q_PERSISTENT_ADJOINT = 5
 
 EXPORTED = (
     "tmm_workspace_bytes", "tmm_create", "tmm_destroy", "tmm_set_params", "tmm_step", "tmm_year",
-    "tmm_year_jvp", "tmm_year_adjoint", "tmm_set_option", "tmm_query", "tmm_strerror",
+    "tmm_year_jvp", "tmm_year_adjoint", "tmm_set_option", "tmm_query", "tmm_strerror", "tmm_probe_exchange",
 )
 
 _dp = C.POINTER(C.c_double)
@@ -60,6 +64,7 @@ class TmmDesc(C.Structure):
         ("nbatch_max", C.c_int), ("adjoint_nbatch_max", C.c_int), ("ckpt_every", C.c_int),
         ("ae_nnz", C.c_int), ("ae_rowptr", _ip), ("ae_colidx", _ip), ("ae_val", _dp),
         ("ai_nnz", C.c_int), ("ai_rowptr", _ip), ("ai_colidx", _ip), ("ai_val", _dp),
+        ("lon", _dp),
     ]
 
 
@@ -92,6 +97,7 @@ def load():
             "tmm_set_option": (C.c_int, [vp, C.c_int, C.c_int]),
             "tmm_query": (C.c_int, [vp, C.c_int, C.POINTER(C.c_longlong)]),
             "tmm_strerror": (C.c_char_p, [C.c_int]),
+            "tmm_probe_exchange": (C.c_int, [vp, C.c_int, _dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -167,6 +173,12 @@ def tmm_set_option(h, option, value):
     _check(load().tmm_set_option(h, int(option), int(value)), "tmm_set_option")
 
 
+def tmm_probe_exchange(h, rounds):
+    out = np.zeros(8)
+    _check(load().tmm_probe_exchange(h, int(rounds), _host_d(out)), "tmm_probe_exchange")
+    return out
+
+
 def tmm_query(h, what):
     v = C.c_longlong()
     _check(load().tmm_query(h, int(what), C.byref(v)), "tmm_query")
@@ -215,6 +227,7 @@ class TMM:
             int(nbatch_max), int(adjoint_nbatch_max), int(ckpt_every),
             k["ae_colidx"].size, ip(k["ae_rowptr"]), ip(k["ae_colidx"]), dp(k["ae_val"]),
             k["ai_colidx"].size, ip(k["ai_rowptr"]), ip(k["ai_colidx"]), dp(k["ai_val"]),
+            dp(k["lon"]) if "lon" in k else None,
         )
         self.workspace_bytes = tmm_workspace_bytes(self.desc)
         self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
@@ -240,6 +253,13 @@ class TMM:
 
     def query(self, what):
         return tmm_query(self.handle, what)
+
+    def probe_exchange(self, rounds=2000):
+        """Latencies (us) of the exchange primitives on this device: round trip within an XCD and
+        across XCDs, workgroup barrier, dependent agent-scope load; then the XCDs of the pairs."""
+        o = tmm_probe_exchange(self.handle, rounds)
+        return {"round_trip_same_xcd_us": o[0], "round_trip_cross_xcd_us": o[1], "barrier_us": o[2],
+                "agent_load_us": o[3], "xcds": [int(x) for x in o[4:]]}
 
     @property
     def W(self):

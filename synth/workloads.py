@@ -62,6 +62,7 @@ class Inputs:
             n=g.n, ncol=g.ncol, nlayer=g.nlayer,
             col_start=np.ascontiguousarray(g.col_start, dtype=np.int32),
             lat=np.ascontiguousarray(g.lat, dtype=np.float64),
+            lon=np.ascontiguousarray(g.lon_c[g.col_i], dtype=np.float64),
             area=np.ascontiguousarray(g.area, dtype=np.float64),
             dz=np.ascontiguousarray(g.dz, dtype=np.float64),
             nmat=t.nmat, nstep=t.nstep, model=self.model, neuphotic=self.neuphotic, nbgc=self.nbgc,

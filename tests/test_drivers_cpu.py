@@ -200,3 +200,58 @@ def test_spinup_residual_decreases_and_resumes(tiny_ndop, tmp_path):
     assert np.array_equal(y5a, y5b)            # resume from year 3 reproduces bitwise
     assert np.array_equal(r5a, r5b)
     assert len(open(log).read().splitlines()) == 3
+
+
+def test_spinup_logs_mass_and_its_drift(tiny_ndop, tmp_path):
+    """Each spin-up year logs every tracer's volume-weighted mass and the drift of the total: the
+    transport conserves mass and the model only moves phosphorus between tracers (section 2.2.1)."""
+    import json
+    h = OracleHandle(tiny_ndop)
+    u = synth.nominal(synth.MODEL_NDOP)
+    y0 = tiny_ndop.initial_state()
+    log = str(tmp_path / "log.jsonl")
+    y, r, mass = drivers.spinup(h, u, y0, years=3, log_path=log, return_mass=True)
+    V = tiny_ndop.grid.volumes()
+    assert mass.shape == (4, 1, 2)
+    assert np.allclose(mass[0, 0], V @ y0, rtol=1e-15, atol=0)
+    assert np.allclose(mass[-1, 0], V @ y, rtol=1e-15, atol=0)
+    assert mass[-1, 0, 1] > mass[0, 0, 1]          # DOP is produced from PO4 ...
+    recs = [json.loads(x) for x in open(log).read().splitlines()]
+    assert [rec["year"] for rec in recs] == [1, 2, 3]
+    for rec in recs:
+        assert abs(rec["mass_drift"][0]) <= 1e-13   # ... and the total is kept
+        assert np.allclose(np.sum(rec["mass"]), V @ y0.sum(1), rtol=1e-13)
+
+
+def test_newton_fixed_point_is_the_spinup_limit(tiny_ndop):
+    """The periodic solution (section 4) found by Newton-Krylov (section 6) is where spin-up goes.
+
+    Fixed points form a family indexed by total mass, and both methods keep the
+    mass of y0, so they must meet.  Spin-up contracts slowly (about 4 % a year
+    on this grid), so 120 years are not enough to get there; instead the error
+    e_k = y_k - y* against the Newton solution y* must (i) fall by orders of
+    magnitude and (ii) end within the contraction bound |e_K| <= r_K / (1 - rho)
+    set by the spin-up's own last residual r_K and rate rho: a limit other than
+    y* would leave e_k at a nonzero constant."""
+    h = OracleHandle(tiny_ndop)
+    u = synth.nominal(synth.MODEL_NDOP)
+    y0 = tiny_ndop.initial_state()
+    ystar, hist = drivers.newton_krylov(h, u, y0, tol=1e-10, jvp="tangent", max_newton=15, max_krylov=300)
+    assert hist["fnorm"][-1] <= 1e-10
+    V = tiny_ndop.grid.volumes()
+    # GMRES leaves rounding (about 1e-12 relative) in the mass of each Newton update
+    assert V @ ystar.sum(1) == pytest.approx(V @ y0.sum(1), rel=1e-11)
+    K = 120
+    h.set_params(u)
+    errs, y = [], y0.copy()
+    resid = []
+    for k in range(K):
+        y, r = h.o.year(u, y)
+        resid.append(r[0, 0])
+        errs.append(np.linalg.norm(y - ystar))
+    rho = (resid[-1] / resid[-21]) ** (1 / 20)
+    assert 0.5 < rho < 1.0
+    bound = resid[-1] * rho / (1.0 - rho)            # |y_K - y*| for a linear contraction, |phi(y_K) - y_K| = r_K
+    assert errs[-1] <= 0.02 * errs[K // 4]
+    assert errs[-1] <= 1.5 * bound + 1e-9
+    assert V @ y.sum(1) == pytest.approx(V @ ystar.sum(1), rel=1e-11)

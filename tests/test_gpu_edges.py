@@ -22,6 +22,7 @@ import pytest
 
 import oracle
 import synth
+from tolerances import ADJOINT, MISFIT, STEP, TANGENT, YEAR, columnwise, componentwise, pointwise
 
 pytestmark = pytest.mark.gpu
 
@@ -39,10 +40,6 @@ CKPT = {"short_year": 4, "one_matrix": 1}
 def _tmm():
     from paper_1410_0204_amd import tmm
     return tmm
-
-
-def _rel(a, b):
-    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
 @pytest.fixture(scope="module")
@@ -74,7 +71,8 @@ def test_edge_steps_and_years(inputs, name):
     rng = np.random.default_rng(7)
     y = inp.initial_state() * rng.uniform(0.5, 1.5, size=(inp.n, inp.ntracer))
     for j in sorted({0, 1, inp.nstep // 2, inp.nstep - 1}):
-        assert _rel(t.step(j, t.state(y)).cpu().numpy(), o.step(u, j, y)) <= 1e-14, j
+        assert pointwise(t.step(j, t.state(y)).cpu().numpy(), o.step(u, j, y), inp.ntracer,
+                         f"{name} step {j}") <= STEP, j
     exp, re = o.year(u, y, 2)
     paths = [1, 0] if t.query(tmm.TMM_Q_PERSISTENT) else [0]
     if name == "deep24":
@@ -84,7 +82,7 @@ def test_edge_steps_and_years(inputs, name):
     for pers in paths:
         t.set_option(tmm.TMM_OPT_PERSISTENT, pers)
         got, r = t.year(t.state(y), nyears=2)
-        assert _rel(got.cpu().numpy(), exp) <= 1e-12, pers
+        assert pointwise(got.cpu().numpy(), exp, inp.ntracer, f"{name} two years, path {pers}") <= YEAR, pers
         # a residual near zero is rounding noise: compare it against the state's size
         assert np.abs(r - re).max() <= 1e-9 * np.abs(re).max() + 1e-12 * np.linalg.norm(exp), pers
     same, _ = t.year(t.state(y), nyears=0)
@@ -111,11 +109,11 @@ def test_edge_tangent_and_adjoint(inputs, name):
     for pers in paths:
         t.set_option(tmm.TMM_OPT_PERSISTENT, pers)
         _, jv = t.year_jvp(t.state(y), t.state(v), mode=tmm.TMM_JVP_TANGENT)
-        assert _rel(jv.cpu().numpy(), ejv) <= 1e-11, pers
+        assert columnwise(jv.cpu().numpy(), ejv, inp.ntracer, f"{name} tangent, path {pers}") <= TANGENT, pers
         J, G, dy0 = t.year_adjoint(t.state(inp.initial_state()), torch.as_tensor(obs).cuda())
-        assert J[0] == pytest.approx(eJ[0], rel=1e-12), pers
-        assert _rel(G, eG) <= 1e-10, pers
-        assert _rel(dy0.cpu().numpy(), eY) <= 1e-10, pers
+        assert componentwise(J, eJ, f"{name} J, path {pers}") <= MISFIT, pers
+        assert componentwise(G, eG, f"{name} dJ/du, path {pers}") <= ADJOINT, pers
+        assert columnwise(dy0.cpu().numpy(), eY, inp.ntracer, f"{name} dJ/dy0, path {pers}") <= ADJOINT, pers
 
 
 def test_wait_give_up_is_reported_and_the_handle_recovers():
@@ -143,4 +141,44 @@ def test_wait_give_up_is_reported_and_the_handle_recovers():
     t.set_option(tmm.TMM_OPT_SPIN_LIMIT, 0)
     got, _ = t.year(t.state(y0), nyears=1)
     exp, _ = oracle.Oracle(inp).year(u, y0)
-    assert _rel(got.cpu().numpy(), exp) <= 1e-12
+    assert pointwise(got.cpu().numpy(), exp, inp.ntracer, "after the give-up") <= YEAR
+
+
+@pytest.mark.parametrize("persistent", [1, 0])
+def test_nonfinite_year_is_reported(persistent):
+    """A NaN in the initial state makes tmm_year return TMM_ENONFINITE (the per-year check of the
+    state), once: the next finite year on the same handle is clean and matches the oracle.  With
+    the check off the same call succeeds.  The kernels run to completion either way (a NaN is
+    never the persistent kernel's empty-slot marker)."""
+    tmm = _tmm()
+    inp = synth.small_ndop()
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=1)
+    t.set_option(tmm.TMM_OPT_PERSISTENT, persistent)
+    print(f"[gpu] NaN input, persistent={persistent}", flush=True)
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    y0 = inp.initial_state()
+    bad = y0.copy()
+    bad[100, 1] = np.nan
+    with pytest.raises(tmm.TmmError) as err:
+        t.year(t.state(bad))
+    assert err.value.status == tmm.TMM_ENONFINITE
+    got, _ = t.year(t.state(y0))
+    exp, _ = oracle.Oracle(inp).year(u, y0)
+    assert pointwise(got.cpu().numpy(), exp, 2, f"after a NaN year, path {persistent}") <= YEAR
+    t.set_option(tmm.TMM_OPT_CHECK_FINITE, 0)
+    out, _ = t.year(t.state(bad))
+    assert np.isnan(out.cpu().numpy()).any()
+
+
+def test_exchange_probe():
+    """The latency probe runs its bounded ping-pong, barrier and load chains to the end and reports
+    positive, finite latencies (and where its workgroups ran)."""
+    tmm = _tmm()
+    inp = synth.tiny()
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=1)
+    p = t.probe_exchange(500)
+    print(f"[gpu] probe: {p}", flush=True)
+    for k in ("round_trip_same_xcd_us", "round_trip_cross_xcd_us", "barrier_us", "agent_load_us"):
+        assert 0.0 < p[k] < 1000.0, k
+    assert all(0 <= x < 16 for x in p["xcds"])

@@ -401,6 +401,60 @@ def test_initial_state_gradient_matches_central_differences(tiny_ndop):
 
 
 # --------------------------------------------------------------------------
+# The misfit itself: its volume weights and normalisation.  The gradient pins
+# above check dJ/du and dJ/dy0 against differences of the oracle's own J, so
+# a wrong cell volume would go unnoticed there (J and its source share it);
+# here J is written out from the month-end states and the grid's geometry.
+# --------------------------------------------------------------------------
+
+def _volumes_from_desc(inp):
+    """V_i = area_c h_k, straight from the descriptor arrays."""
+    a = inp.desc_arrays()
+    V = np.empty(a["n"])
+    for c in range(a["ncol"]):
+        r0, r1 = int(a["col_start"][c]), int(a["col_start"][c + 1])
+        V[r0:r1] = a["area"][c] * a["dz"][: r1 - r0]
+    return V
+
+
+def _misfit_by_hand(states, obs, V, nmat):
+    """J_b = sum_m sum_i sum_tr V_i (y - o)^2 / (2 nmat V_tot) for each member b."""
+    d2 = (states - obs) ** 2                                  # [nmat, n, W]
+    return np.einsum("i,miw->w", V, d2) / (2.0 * nmat * V.sum())
+
+
+@pytest.mark.parametrize("which", ["n", "ndop", "small", "batch"])
+def test_misfit_value_restated(which, tiny_n, tiny_ndop, small_ndop):
+    inp = {"n": tiny_n, "ndop": tiny_ndop, "small": small_ndop, "batch": tiny_ndop}[which]
+    o = oracle.Oracle(inp)
+    nb = 2 if which == "batch" else 1
+    u = synth.nominal(inp.model) if nb == 1 else synth.latin_hypercube(inp.model, nb, seed=9)
+    y0 = inp.initial_state(nb)
+    obs1 = _obs(inp)
+    obs = np.concatenate([obs1, obs1 * 1.03], axis=2) if nb == 2 else obs1
+    V = _volumes_from_desc(inp)
+    assert np.array_equal(V, inp.grid.volumes())
+    states = o.snapshots(u, y0)                               # after steps 240 (m + 1)
+    per_col = _misfit_by_hand(states, obs, V, inp.nmat)
+    J = per_col.reshape(nb, inp.ntracer).sum(axis=1)
+    assert np.allclose(o.year_misfit(u, y0, obs), J, rtol=1e-14, atol=0)
+    assert np.allclose(o.year_adjoint(u, y0, obs)[0], J, rtol=1e-14, atol=0)
+    # the pin separates the plausible mistakes: uniform weights, the layer
+    # heights of another column depth (reversed), no factor 1/2, V_tot of one layer
+    top = np.zeros_like(V)
+    top[inp.grid.col_start[:-1]] = V[inp.grid.col_start[:-1]]
+    dz_rev = inp.desc_arrays()["dz"][::-1]
+    V_rev = np.concatenate([inp.desc_arrays()["area"][c] * dz_rev[: inp.grid.col_start[c + 1] - inp.grid.col_start[c]]
+                            for c in range(inp.grid.ncol)])
+    for wrong in (_misfit_by_hand(states, obs, np.ones_like(V), inp.nmat),
+                  _misfit_by_hand(states, obs, V_rev, inp.nmat),
+                  2.0 * per_col,
+                  per_col * V.sum() / top.sum()):
+        Jw = wrong.reshape(nb, inp.ntracer).sum(axis=1)
+        assert np.abs(Jw / J - 1.0).max() > 1e-3
+
+
+# --------------------------------------------------------------------------
 # Internal BGC steps (section 7: several biogeochemical steps per ocean step)
 # --------------------------------------------------------------------------
 

@@ -20,6 +20,27 @@
 
 namespace {
 
+constexpr int kMaxTileRows = 256;          // rows per tile (LDS maps are sized for this)
+constexpr int kLdsBudget = 48 * 1024;      // dynamic LDS per workgroup
+constexpr size_t kAlign = 256;
+
+#define TMM_TRY(expr)                                   \
+    do {                                                \
+        if ((expr) != hipSuccess) return TMM_EDEVICE;   \
+    } while (0)
+
+#define TMM_LAUNCHED()                                  \
+    do {                                                \
+        if (hipGetLastError() != hipSuccess) return TMM_EDEVICE; \
+    } while (0)
+
+int ntracer_of(int model) {
+    return model == TMM_MODEL_N ? 1 : model == TMM_MODEL_NDOP ? 2 : model == TMM_MODEL_NDOPPHY ? 3 : -1;
+}
+int nparam_of(int model) {
+    return model == TMM_MODEL_N ? 5 : model == TMM_MODEL_NDOP ? 7 : model == TMM_MODEL_NDOPPHY ? 11 : -1;
+}
+
 // One partition of the water columns into tiles of at most max_rows rows.
 struct Tiling {
     int max_rows = 0;

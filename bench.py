@@ -186,6 +186,8 @@ def ensemble_leg(dev, stream, steps=30):
     U = synth.latin_hypercube(synth.MODEL_NDOP, nm, seed=17)
     L = synth.spinup_lengths(nm, seed=18)
     t = tmm.TMM(inp.desc_arrays(), nbatch_max=nm, device=dev, stream=stream)
+    from paper_1410_0204_amd import autotune
+    tuned = autotune.apply_tuned(t, nm)
     t.set_params(U)
     y0 = t.state(inp.initial_state(nm))
     s, e = _events()
@@ -205,6 +207,9 @@ def ensemble_leg(dev, stream, steps=30):
     torch.cuda.synchronize()
     ms_b = s.elapsed_time(e)
     member_years = int(L.sum())
+    # the plain method: one member at a time, in its own best configuration
+    autotune.apply(t, autotune.DEFAULTS)
+    tuned1 = autotune.apply_tuned(t, 1)
     t.set_params(U[0])
     y1 = t.state(inp.initial_state(1))
     t.year(y1, nyears=1, residuals=False)
@@ -227,6 +232,8 @@ def ensemble_leg(dev, stream, steps=30):
            "one_member_ms_per_year": ms_1, "sequential_member_years_per_s": 1000.0 / ms_1,
            "speedup": member_years * ms_1 / ms_b,
            "speedup_from_bytes": member_years * B1 / batched_bytes,
+           "tuned": tuned["named"] if tuned else "library defaults",
+           "tuned_one_member": tuned1["named"] if tuned1 else "library defaults",
            "inputs_generation_s": gen_s}
     log(f"[bench] ensemble: full-width step {us:.1f} us ({res['full_width_GBps']:.0f} GB/s, "
         f"{100 * res['full_width_frac']:.1f} % of peak); {member_years} member-years in {ms_b:.0f} ms "
@@ -275,6 +282,9 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
     t = tmm.TMM(inp.desc_arrays(), nbatch_max=1, adjoint_nbatch_max=1, ckpt_every=240, device=dev, stream=stream)
+    from paper_1410_0204_amd import autotune
+    tuned = autotune.apply_tuned(t, 1)
+    log(f"[bench] launch configuration: {tuned['named'] if tuned else 'library defaults'}")
     u = synth.nominal(inp.model)
     t.set_params(u)
     y0 = t.state(inp.initial_state())
@@ -408,7 +418,7 @@ def main():
         "config": {"workload": "global_128x64x15 N-DOP forward model years", "n": n, "columns": inp.grid.ncol,
                    "layers": 15, "tracers": W, "nstep": inp.nstep, "nnz_explicit": inp.tm.ae_nnz,
                    "nnz_implicit": inp.tm.ai_nnz, "step": "one model year",
-                   "path": kernel},
+                   "path": kernel, "tuned": tuned["named"] if tuned else "library defaults"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "hbm_frac_measured": (traffic / (us_per_launch * 1e-6) / 1e9 / HBM_PEAK_GBPS

@@ -11,6 +11,9 @@ kernel sources it was taken with.
 Usage (after the four rocprofv3 runs, each with ``-d DIR --output-format csv``):
   python -m paper_1410_0204_amd.counters KERNEL WORKLOAD FETCH_DIR WRITE_DIR \\
       COPY_FETCH_DIR COPY_WRITE_DIR OUT_JSON [--per-launch-units N]
+and, for the idle time between the launches of a graph-replayed kernel in a
+kernel trace:
+  python -m paper_1410_0204_amd.counters gaps TRACE_DIR KERNEL
 """
 
 import argparse
@@ -58,7 +61,40 @@ def largest_dispatch(directory, counter):
     return vals[key], names[key]
 
 
+def launch_gaps(directory, kernel):
+    """Idle time between consecutive dispatches of ``kernel`` in a rocprofv3
+    kernel trace (``--kernel-trace --output-format csv``): the dispatches are
+    grouped into runs separated by gaps of more than 1 ms (host work between
+    model years); within the runs, the sum of the gaps against the sum of the
+    kernel durations."""
+    files = glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no kernel_trace.csv under {directory}")
+    spans = []
+    for path in files:
+        with open(path, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if kernel in row.get("Kernel_Name", ""):
+                    spans.append((int(row["Start_Timestamp"]), int(row["End_Timestamp"])))
+    spans.sort()
+    busy = gap = 0
+    runs = 1
+    for (s0, e0), (s1, _) in zip(spans, spans[1:]):
+        d = s1 - e0
+        if d > 1_000_000:
+            runs += 1
+        else:
+            gap += max(d, 0)
+    busy = sum(e - s for s, e in spans)
+    return {"kernel": kernel, "dispatches": len(spans), "runs": runs, "busy_ns": busy, "gap_ns": gap,
+            "gap_fraction": gap / (busy + gap) if busy + gap else 0.0,
+            "mean_gap_us": gap / max(len(spans) - runs, 1) / 1000.0}
+
+
 def main(argv):
+    if argv and argv[0] == "gaps":
+        print(json.dumps(launch_gaps(argv[1], argv[2])))
+        return
     ap = argparse.ArgumentParser()
     for a in ("kernel", "workload", "fetch_dir", "write_dir", "copy_fetch_dir", "copy_write_dir", "out"):
         ap.add_argument(a)

@@ -52,7 +52,8 @@ enum {
     TMM_ESTATE = -4,        /* call not valid in the handle's state (e.g. no parameters set) */
     TMM_ENONFINITE = -5,    /* non-finite value found in a result (or in the state at the end of a
                                model year of tmm_year) */
-    TMM_EUNSUPPORTED = -6   /* valid request outside what this build supports */
+    TMM_EUNSUPPORTED = -6,  /* valid request outside what this build supports */
+    TMM_ETOOBIG = -7        /* request exceeds the fixed scratch of tmm_year_noalloc */
 };
 
 /* Biogeochemical models (section 2.2).  Parameter order is the order of the
@@ -146,6 +147,25 @@ int tmm_step(tmm_handle h, int j, const double *y_in, double *y_out);
  * all its years, writes y1 and resid_host, and returns TMM_ENONFINITE. */
 int tmm_year(tmm_handle h, int nyears, const int *years_per_member,
              const double *y0, double *y1, double *resid_host);
+
+/* tmm_year for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * model years with the same kernels, but every buffer besides y0 and y1 --
+ * the ping-pong state, a copy of the year's start state, the residual
+ * partial sums, the non-finite flag -- lives in a fixed device array of the
+ * library (32 MiB, one per device, held until the process ends) instead of
+ * the workspace's state buffers, and the call makes no allocation of any
+ * kind.  It always runs one launch per time step (the single-launch year
+ * kernel needs the workspace's state ring) and has no per-member lengths.
+ * Requests that do not fit, 2 n W + (tiles + 1) nbatch doubles > 32 MiB
+ * (about 2 million state values: the global grid with up to 19 members),
+ * return TMM_ETOOBIG before anything runs.  y1 may equal y0; resid_host and
+ * the non-finite check as for tmm_year.  With resid_host NULL and
+ * TMM_OPT_CHECK_FINITE 0 the call only enqueues kernels and does not
+ * synchronise.  The fixed array is shared by every call on a device: calls
+ * that overlap on one device (different streams or threads) race, and must
+ * be serialised by the caller. */
+int tmm_year_noalloc(tmm_handle h, int nyears, const double *y0, double *y1, double *resid_host);
 
 /* Directional derivative of the year map (section 6.1): jv = phi'(y) v by
  * mode TMM_JVP_FD or TMM_JVP_TANGENT, where phi_y (nullable) receives phi(y);

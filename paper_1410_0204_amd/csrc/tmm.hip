@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -18,7 +19,35 @@
 #include "tmm_persistent.hpp"
 #include "tmm_probe.hpp"
 
+// Scratch of tmm_year_noalloc: a fixed device array instead of workspace or
+// allocations (a ping-pong state, a copy of the year's start state, residual
+// partial sums and the non-finite flag).  Each device that loads the library
+// holds its own copy until the process ends.  Host code never uses the name
+// itself (on the host it is only a stand-in for the symbol): it uses the
+// device address from hipGetSymbolAddress, taken once per device at
+// tmm_create with that device current.
+constexpr size_t kNoAllocBytes = 32ull << 20;
+static __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
+
 namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+int scratch_address(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) return TMM_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TMM_EDEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TMM_OK;
+}
 
 constexpr int kMaxTileRows = 256;          // rows per tile (LDS maps are sized for this)
 constexpr int kLdsBudget = 48 * 1024;      // dynamic LDS per workgroup
@@ -320,6 +349,7 @@ struct tmm_ctx {
     int num_cu = 0;
     bool pers_used = false;        // a persistent launch happened since the last abort check
     bool check_finite = true;      // option TMM_OPT_CHECK_FINITE
+    double* noalloc = nullptr;     // device address of the static scratch on the handle's device
     int tile_rows_cap = 0;         // option TMM_OPT_TILE_ROWS (0: by width)
     std::vector<int> ae_rowptr, ae_colidx;   // explicit-matrix pattern (domain dependencies)
 
@@ -1072,6 +1102,7 @@ const char* tmm_strerror(int status) {
         case TMM_ESTATE: return "call not valid in the handle's state";
         case TMM_ENONFINITE: return "non-finite value in a result";
         case TMM_EUNSUPPORTED: return "unsupported request";
+        case TMM_ETOOBIG: return "request exceeds the fixed scratch of tmm_year_noalloc";
         default: return "unknown status";
     }
 }
@@ -1212,6 +1243,11 @@ int tmm_create(const tmm_desc* d, void* dev_workspace, size_t bytes, void* hip_s
     h->ae_colidx.assign(d->ae_colidx, d->ae_colidx + d->ae_nnz);
     if (build_persistent(h, 0)) return fail(TMM_EDEVICE);
     if (build_member_order(h)) return fail(TMM_EDEVICE);
+    {
+        void* sp = nullptr;
+        if (scratch_address(&sp)) return fail(TMM_EDEVICE);
+        h->noalloc = static_cast<double*>(sp);
+    }
     h->h_member.resize(P.nbatch_max);
     h->h_scol.resize(P.nbatch_max);
     h->h_dcol.resize(P.nbatch_max);
@@ -1507,6 +1543,75 @@ int tmm_query(tmm_handle h, int what, long long* value) {
             return TMM_OK;
         default: return TMM_EINVAL;
     }
+}
+
+int tmm_year_noalloc(tmm_handle h, int nyears, const double* y0, double* y1, double* resid_host) {
+    if (!h || !y0 || !y1 || nyears < 0) return TMM_EINVAL;
+    const int nb = h->nbatch;
+    if (nb < 1) return TMM_ESTATE;
+    if (!h->noalloc) return TMM_EDEVICE;
+    const Plan& P = h->P;
+    const int W = nb * P.ntr;
+    const size_t L = (size_t)P.n * W;
+    const Tiling& tf = h->tilings.front();
+    // scratch layout (doubles): ping-pong state, start-state copy, residual
+    // partials per tile, residuals, flag
+    const size_t o_part = align_up(2 * L * 8) / 8;
+    const size_t o_vec = o_part + align_up((size_t)tf.ntile * nb * 8) / 8;
+    const size_t o_flag = o_vec + align_up((size_t)nb * 8) / 8;
+    if ((o_flag + 32) * 8 > kNoAllocBytes) return TMM_ETOOBIG;
+    double* S = h->noalloc;
+    double* T = h->noalloc + L;
+    double* part = h->noalloc + o_part;
+    double* vec = h->noalloc + o_vec;
+    int* flag = reinterpret_cast<int*>(h->noalloc + o_flag);
+    if (h->check_finite) {
+        hipLaunchKernelGGL(tmm::k_fill_int, dim3(1), dim3(64), 0, h->stream, flag, 16, 0);
+        TMM_LAUNCHED();
+    }
+    for (int yr = 0; yr < nyears; ++yr) {
+        // the year's start state: y0, then y1; kept in T when it is about to be overwritten
+        // and the residual needs it
+        const double* in = yr == 0 ? y0 : y1;
+        const double* start = in;
+        if (resid_host && (yr > 0 || y1 == y0)) {
+            int rc = copy(h, T, in, L);
+            if (rc) return rc;
+            start = T;
+        }
+        // steps alternate between S and y1 and end in y1 (nstep is even)
+        const double* cur = in;
+        for (int j = 0; j < P.nstep; ++j) {
+            double* nxt = (j % 2 == 0) ? S : y1;
+            int rc = launch_step(h, j, nb, cur, nxt, nullptr, nullptr);
+            if (rc) return rc;
+            cur = nxt;
+        }
+        if (h->check_finite) {
+            hipLaunchKernelGGL(tmm::k_check_finite, dim3(launch_blocks(L)), dim3(256), 0, h->stream, y1, L, flag);
+            TMM_LAUNCHED();
+        }
+        if (resid_host) {
+            tmm::Grid g = h->grid(tf);
+            hipLaunchKernelGGL((tmm::k_tile_sqdiff<kMaxTileRows, kMaxTileRows>), dim3(tf.ntile), dim3(256), 0,
+                               h->stream, g, W, P.ntr, nb, y1, start, 0, part);
+            TMM_LAUNCHED();
+            hipLaunchKernelGGL(tmm::k_sum_tiles, dim3(1), dim3(256), 0, h->stream, tf.ntile, nb, nb, part, 1.0, 0, 1,
+                               vec);
+            TMM_LAUNCHED();
+            TMM_TRY(hipMemcpyAsync(resid_host + (size_t)yr * nb, vec, (size_t)nb * 8, hipMemcpyDeviceToHost,
+                                   h->stream));
+        }
+    }
+    if (nyears == 0 && y1 != y0) {
+        int rc = copy(h, y1, y0, L);
+        if (rc) return rc;
+    }
+    if (!resid_host && !h->check_finite) return TMM_OK;       // kernels only, no synchronisation
+    int bad = 0;
+    if (h->check_finite) TMM_TRY(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, h->stream));
+    TMM_TRY(hipStreamSynchronize(h->stream));
+    return bad ? TMM_ENONFINITE : TMM_OK;
 }
 
 int tmm_probe_exchange(tmm_handle h, int rounds, double* out) {

@@ -22,6 +22,7 @@ TMM_EDEVICE = -3
 TMM_ESTATE = -4
 TMM_ENONFINITE = -5
 TMM_EUNSUPPORTED = -6
+TMM_ETOOBIG = -7
 TMM_MODEL_N = 1
 TMM_MODEL_NDOP = 2
 TMM_MODEL_NDOPPHY = 3
@@ -48,6 +49,7 @@ TMM_Q_PERSISTENT_ADJOINT = 5
 EXPORTED = (
     "tmm_workspace_bytes", "tmm_create", "tmm_destroy", "tmm_set_params", "tmm_step", "tmm_year",
     "tmm_year_jvp", "tmm_year_adjoint", "tmm_set_option", "tmm_query", "tmm_strerror", "tmm_probe_exchange",
+    "tmm_year_noalloc",
 )
 
 _dp = C.POINTER(C.c_double)
@@ -98,6 +100,7 @@ def load():
             "tmm_query": (C.c_int, [vp, C.c_int, C.POINTER(C.c_longlong)]),
             "tmm_strerror": (C.c_char_p, [C.c_int]),
             "tmm_probe_exchange": (C.c_int, [vp, C.c_int, _dp]),
+            "tmm_year_noalloc": (C.c_int, [vp, C.c_int, vp, vp, _dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -158,6 +161,10 @@ def tmm_year(h, nyears, years_per_member, y0, y1, resid_host):
         ypm = np.ascontiguousarray(years_per_member, dtype=np.int32)
     _check(load().tmm_year(h, int(nyears), ypm.ctypes.data_as(_ip) if ypm is not None else None,
                            _ptr(y0), _ptr(y1), _host_d(resid_host)), "tmm_year")
+
+
+def tmm_year_noalloc(h, nyears, y0, y1, resid_host):
+    _check(load().tmm_year_noalloc(h, int(nyears), _ptr(y0), _ptr(y1), _host_d(resid_host)), "tmm_year_noalloc")
 
 
 def tmm_year_jvp(h, mode, y, v, phi_y, jv):
@@ -290,6 +297,12 @@ class TMM:
         out = self.state() if out is None else out
         resid = np.zeros((nyears, self.nbatch)) if residuals else None
         tmm_year(self.handle, nyears, years_per_member, self._state_arg(y0), self._state_arg(out), resid)
+        return out, resid
+
+    def year_noalloc(self, y0, out, nyears=1, residuals=True):
+        """Model years through tmm_year_noalloc: out (allocated by the caller) receives the state."""
+        resid = np.zeros((nyears, self.nbatch)) if residuals else None
+        tmm_year_noalloc(self.handle, nyears, self._state_arg(y0), self._state_arg(out), resid)
         return out, resid
 
     def year_jvp(self, y, v, mode=TMM_JVP_TANGENT, want_phi=True, phi=None):

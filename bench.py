@@ -257,6 +257,10 @@ def main():
     ap.add_argument("--log", default=None, help="JSONL progress log (newton mode)")
     ap.add_argument("--grid-steps", type=int, default=0,
                     help="grids / ensemble modes: time this many single steps instead of model years")
+    ap.add_argument("--member-band", type=int, default=None,
+                    help="ensemble mode: latitude rows per band of the member kernel's column order (-1: natural)")
+    ap.add_argument("--member-waves", type=int, default=None,
+                    help="ensemble mode: wavefronts per workgroup of the member kernel")
     ap.add_argument("--forward-only", action="store_true",
                     help="skip the per-step comparison and the adjoint (for hardware counter runs)")
     args = ap.parse_args()
@@ -620,6 +624,10 @@ def bench_ensemble(args):
     U = synth.latin_hypercube(synth.MODEL_NDOP, nm, seed=17)
     L = synth.spinup_lengths(nm, seed=18)
     t = tmm.TMM(inp.desc_arrays(), nbatch_max=nm)
+    if args.member_band is not None:
+        t.set_option(tmm.TMM_OPT_MEMBER_BAND_ROWS, args.member_band)
+    if args.member_waves is not None:
+        t.set_option(tmm.TMM_OPT_MEMBER_WAVES, args.member_waves)
     s, e = _events()
     t.set_params(U)
     y0 = t.state(inp.initial_state(nm))

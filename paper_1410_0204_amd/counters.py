@@ -55,8 +55,8 @@ def mean_per_dispatch(directory, counter, kernel):
     return sum(vals.values()) / len(vals), len(vals)
 
 
-def largest_dispatch(directory, counter):
-    vals, names = dispatch_values(directory, counter)
+def largest_dispatch(directory, counter, kernel=None):
+    vals, names = dispatch_values(directory, counter, kernel)
     key = max(vals, key=vals.get)
     return vals[key], names[key]
 
@@ -99,14 +99,15 @@ def main(argv):
     for a in ("kernel", "workload", "fetch_dir", "write_dir", "copy_fetch_dir", "copy_write_dir", "out"):
         ap.add_argument(a)
     ap.add_argument("--copy-bytes", type=int, default=512 * 1024 * 1024)
+    ap.add_argument("--copy-kernel", default="copyBuffer", help="name of the copy kernel in the calibration runs")
     ap.add_argument("--commands", nargs="*", default=[])
     ap.add_argument("--per-launch-units", type=int, default=1,
                     help="units (time steps) of one launch, for the per-unit figure")
     args = ap.parse_args(argv)
     fetch, nf = mean_per_dispatch(args.fetch_dir, "FETCH_SIZE", args.kernel)
     write, nw = mean_per_dispatch(args.write_dir, "WRITE_SIZE", args.kernel)
-    cf, cf_name = largest_dispatch(args.copy_fetch_dir, "FETCH_SIZE")
-    cw, cw_name = largest_dispatch(args.copy_write_dir, "WRITE_SIZE")
+    cf, cf_name = largest_dispatch(args.copy_fetch_dir, "FETCH_SIZE", args.copy_kernel)
+    cw, cw_name = largest_dispatch(args.copy_write_dir, "WRITE_SIZE", args.copy_kernel)
     fscale = args.copy_bytes / (cf * 1024.0)
     wscale = args.copy_bytes / (cw * 1024.0)
     total = fetch * 1024.0 * fscale + write * 1024.0 * wscale

@@ -64,8 +64,7 @@ enum {
                                u = alpha, K_H2O, K_1, K_I, lambda'_2, sigma_2, b */
     TMM_MODEL_NDOPPHY = 3   /* PO4-DOP-PHY (section 2.2.2), 3 tracers (PO4, DOP, PHY);
                                u = mu_1, K_H2O, K_1, K_I, lambda'_2, sigma_2, lambda_3, kappa_3,
-                               lambda'_3, sigma_3, b.  Internal BGC steps (nbgc > 1) are not
-                               supported with this model (TMM_EUNSUPPORTED) */
+                               lambda'_3, sigma_3, b */
 };
 
 /* Directional derivative of the year map (section 6.1). */

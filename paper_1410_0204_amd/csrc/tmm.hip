@@ -156,7 +156,7 @@ int validate(const tmm_desc* d, Plan& P) {
     if (d->nmat < 1 || d->nstep < 1 || d->nstep % d->nmat || (d->nstep / d->nmat) % 2) return TMM_EINVAL;
     if (d->neuphotic < 1 || d->neuphotic > d->nlayer) return TMM_EINVAL;
     if (d->nbgc < 0 || d->nbgc > tmm::kSubMax) return TMM_EINVAL;
-    if (d->nbgc > 1 && (d->neuphotic > tmm::kSubNeuMax || d->model == TMM_MODEL_NDOPPHY)) return TMM_EUNSUPPORTED;
+    if (d->nbgc > 1 && d->neuphotic > tmm::kSubNeuMax) return TMM_EUNSUPPORTED;
     if (d->nbatch_max < 1 || d->adjoint_nbatch_max < 0 || d->adjoint_nbatch_max > d->nbatch_max) return TMM_EINVAL;
     if (d->adjoint_nbatch_max > 0 && (d->ckpt_every < 1 || d->nstep % d->ckpt_every)) return TMM_EINVAL;
     if (d->adjoint_nbatch_max * nparam_of(d->model) > 128) return TMM_EINVAL;
@@ -549,10 +549,16 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
     tmm::Model md = h->model();
     tmm::Mats mt = h->mats();
     dim3 grid(t.ntile), blk(block);
+    // PO4-DOP-PHY has W >= 3, so its internal-step instance exists for CW = 2 only
+    const bool sub_phy = sub && h->P.ntr == 3;
+    if (sub_phy && CW != 2) return TMM_EUNSUPPORTED;
 #define TMM_STEP(C, T)                                                                                       \
     do {                                                                                                     \
-        if (sub)                                                                                             \
-            hipLaunchKernelGGL((tmm::k_step<C, T, kMaxTileRows, kMaxTileRows, true>), grid, blk, lds,       \
+        if (sub_phy)                                                                                         \
+            hipLaunchKernelGGL((tmm::k_step<C, T, kMaxTileRows, kMaxTileRows, (C == 2 ? 3 : 1)>), grid, blk, \
+                               lds, h->launch_stream(), g, md, mt, W, tpr, j, dtd, y, yo, v, vo);            \
+        else if (sub)                                                                                        \
+            hipLaunchKernelGGL((tmm::k_step<C, T, kMaxTileRows, kMaxTileRows, 1>), grid, blk, lds,          \
                                h->launch_stream(), g, md, mt, W, tpr, j, dtd, y, yo, v, vo);                 \
         else                                                                                                 \
             hipLaunchKernelGGL((tmm::k_step<C, T, kMaxTileRows, kMaxTileRows>), grid, blk, lds,             \
@@ -581,15 +587,10 @@ const void* persistent_kernel_of(bool tangent, int sn) {
 }
 
 const void* persistent_kernel(int ntr, bool tangent, int kmax, int tpb, int sn) {
-    if (ntr == 3) {    // PO4-DOP-PHY: one evaluation per step
-        if (tpb == 512)
-            return tangent ? (const void*)&tmm::k_year_persistent<3, true, 16, 512>
-                           : (const void*)&tmm::k_year_persistent<3, false, 16, 512>;
-        if (kmax == 16)
-            return tangent ? (const void*)&tmm::k_year_persistent<3, true, 16, 256>
-                           : (const void*)&tmm::k_year_persistent<3, false, 16, 256>;
-        return tangent ? (const void*)&tmm::k_year_persistent<3, true, 32, 256>
-                       : (const void*)&tmm::k_year_persistent<3, false, 32, 256>;
+    if (ntr == 3) {    // PO4-DOP-PHY
+        if (tpb == 512) return persistent_kernel_of<3, 16, 512>(tangent, sn);
+        if (kmax == 16) return persistent_kernel_of<3, 16, 256>(tangent, sn);
+        return persistent_kernel_of<3, 32, 256>(tangent, sn);
     }
     if (tpb == 512)
         return ntr == 1 ? persistent_kernel_of<1, 16, 512>(tangent, sn) : persistent_kernel_of<2, 16, 512>(tangent, sn);
@@ -607,9 +608,8 @@ const void* adjoint_kernel_of(int sn) {
 
 const void* adjoint_kernel(int ntr, int kmax, int tpb, int sn) {
     if (ntr == 3)
-        return tpb == 512 ? (const void*)&tmm::k_adjoint_persistent<3, 16, 512>
-                          : kmax == 16 ? (const void*)&tmm::k_adjoint_persistent<3, 16, 256>
-                                       : (const void*)&tmm::k_adjoint_persistent<3, 32, 256>;
+        return tpb == 512 ? adjoint_kernel_of<3, 16, 512>(sn)
+                          : kmax == 16 ? adjoint_kernel_of<3, 16, 256>(sn) : adjoint_kernel_of<3, 32, 256>(sn);
     if (tpb == 512) return ntr == 1 ? adjoint_kernel_of<1, 16, 512>(sn) : adjoint_kernel_of<2, 16, 512>(sn);
     if (kmax == 16) return ntr == 1 ? adjoint_kernel_of<1, 16, 256>(sn) : adjoint_kernel_of<2, 16, 256>(sn);
     return ntr == 1 ? adjoint_kernel_of<1, 32, 256>(sn) : adjoint_kernel_of<2, 32, 256>(sn);
@@ -1725,7 +1725,10 @@ int tmm_year_adjoint(tmm_handle h, const double* y0, const double* obs, int ckpt
                        double* out) -> int {
         const double sc = 1.0 / (P.nmat * h->vtot);
         double* ub = use_ae ? ubt : nullptr;
-        if (ntr == 3)
+        if (ntr == 3 && P.nsub > 1)
+            hipLaunchKernelGGL((tmm::k_adjoint<3, kMaxTileRows, kMaxTileRows, true>), dim3(tl.ntile), dim3(256), lds,
+                               h->stream, g, md, mt, W, nb, j, dtd, use_ae, use_ai, mu_in, yj, ob, sc, out, ub);
+        else if (ntr == 3)
             hipLaunchKernelGGL((tmm::k_adjoint<3, kMaxTileRows, kMaxTileRows>), dim3(tl.ntile), dim3(256), lds,
                                h->stream, g, md, mt, W, nb, j, dtd, use_ae, use_ai, mu_in, yj, ob, sc, out, ub);
         else if (ntr == 2 && P.nsub > 1)

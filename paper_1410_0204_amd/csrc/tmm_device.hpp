@@ -523,7 +523,7 @@ __device__ __forceinline__ void bgc_inc_adjoint(const Grid& g, const Model& md, 
     double pdeep = 0.0;
     for (int kk = ne; kk < c.nc; ++kk) pdeep += (1.0 - p.sig) * md.rho[tab + kk] * mu[(size_t)(c.rs + kk) * W + slot * NTR];
     double sphi = 0.0;
-    EuphoticAdj acc{0.0, 0.0, 0.0, 0.0, 0.0};
+    EuphoticAdj acc{};
     for (int s = md.nsub - 1; s >= 0; --s) {
         double inc[NEU][NTR], ys[NEU][NTR];
 #pragma unroll
@@ -537,7 +537,7 @@ __device__ __forceinline__ void bgc_inc_adjoint(const Grid& g, const Model& md, 
             for (int t = 0; t < NTR; ++t) ys[e][t] = ye[e][t] + inc[e][t];
         sphi += euphotic_reverse<NTR, NEU>(p, E, c.k, rho_k, pdeep, ys, h, ib, yb, acc);
     }
-    if (c.k >= ne) deep_reverse<NTR, NP>(p, deep_factors(p, h, md.nsub), md.nsub, h, rho_k, drho_k, sphi, yk, mk, yb, u);
+    if (c.k >= ne) deep_reverse<NTR, NP>(p, deep_factors<NTR>(p, h, md.nsub), md.nsub, h, rho_k, drho_k, sphi, yk, mk, yb, u);
     else euphotic_adj_finish<NTR, NEU, NP>(p, E, c.k, zc, drho_k, acc, u);
 #pragma unroll
     for (int t = 0; t < NTR; ++t) ybar[t] += yb[t];
@@ -548,9 +548,12 @@ __device__ __forceinline__ void bgc_inc_adjoint(const Grid& g, const Model& md, 
 // ---------------------------------------------------------------------------
 // Forward step (and its tangent).  One workgroup per tile; thread task =
 // (row, group of CW state columns).  Phase A: z = Ae(t_j) y + dt_d q(y) into
-// LDS.  Phase B: y_out = Ai(t_j) z from LDS.
+// LDS.  Phase B: y_out = Ai(t_j) z from LDS.  SUB: 0 = one BGC evaluation
+// per step, 1 = internal BGC steps for one or two tracers, 3 = internal BGC
+// steps for PO4-DOP-PHY (separate instances, so that each keeps only the
+// registers its own model needs).
 // ---------------------------------------------------------------------------
-template <int CW, bool TANGENT, int MAXR, int MAXC, bool SUB = false>
+template <int CW, bool TANGENT, int MAXR, int MAXC, int SUB = 0>
 __global__ __launch_bounds__(256) void k_step(Grid g, Model md, Mats mt, int W, int tpr, int j, double dtd,
                        const double* __restrict__ y, double* __restrict__ yo,
                        const double* __restrict__ v, double* __restrict__ vo) {
@@ -595,7 +598,7 @@ __global__ __launch_bounds__(256) void k_step(Grid g, Model md, Mats mt, int W, 
             }
         }
         // sources: one BGC evaluation per member, both tracers
-        if (md.ntr == 3) {
+        if (SUB == 3 || (SUB == 0 && md.ntr == 3)) {
             // PO4-DOP-PHY: the sources of each member once, then the thread's columns
             double qs[3] = {0.0, 0.0, 0.0}, qds[3] = {0.0, 0.0, 0.0};
             int cur = -1;
@@ -605,13 +608,18 @@ __global__ __launch_bounds__(256) void k_step(Grid g, Model md, Mats mt, int W, 
                 if (wc >= W) break;
                 const int slot = wc / 3;
                 if (slot != cur) {
-                    bgc_q_phy(g, md, y, W, c, slot, qs);
-                    if (TANGENT) bgc_q_phy_tangent(g, md, y, v, W, c, slot, qds);
+                    if constexpr (SUB == 3) {
+                        bgc_inc<3, TANGENT>(g, md, y, v, W, c, slot, qs, qds);
+                    } else {
+                        bgc_q_phy(g, md, y, W, c, slot, qs);
+                        if (TANGENT) bgc_q_phy_tangent(g, md, y, v, W, c, slot, qds);
+                    }
                     cur = slot;
                 }
                 const int tr = wc % 3;
-                acc[cc] += dtd * qs[tr];
-                if (TANGENT) accd[cc] += dtd * qds[tr];
+                const double sc = SUB ? 1.0 : dtd;   // internal steps return the increment itself
+                acc[cc] += sc * qs[tr];
+                if (TANGENT) accd[cc] += sc * qds[tr];
             }
         } else {
 #pragma unroll
@@ -623,7 +631,7 @@ __global__ __launch_bounds__(256) void k_step(Grid g, Model md, Mats mt, int W, 
             const int slot = wc / md.ntr;
             double q1, q2, qd1 = 0.0, qd2 = 0.0;
             double sc = dtd;      // internal steps return the increment itself
-            if (SUB) {
+            if constexpr (SUB == 1) {
                 double o[2] = {0.0, 0.0}, od[2] = {0.0, 0.0};
                 if (md.ntr == 2) bgc_inc<2, TANGENT>(g, md, y, v, W, c, slot, o, od);
                 else bgc_inc<1, TANGENT>(g, md, y, v, W, c, slot, o, od);
@@ -827,7 +835,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
         }
         const Euphotic<NEU> E = make_euphotic<NEU>(p, Q, ne, le, hz, re);
         for (int s = 0; s < md.nsub; ++s) sphi += euphotic_step<NTR, NEU>(p, E, ye, md.hsub, einc);
-        DF = deep_factors(p, md.hsub, md.nsub);
+        DF = deep_factors<NTR>(p, md.hsub, md.nsub);
     }
 
     // z = Ae(t_j) y + dt_d q for every row of the column, in registers

@@ -250,7 +250,7 @@ __device__ __forceinline__ void sub_adjoint_lds(const Grid& g, const Model& md, 
                 ib[e][t] = e < neq ? s_mu[le * NTR + t] : 0.0;
                 yb[e][t] = 0.0;
             }
-            acc[e] = EuphoticAdj{0.0, 0.0, 0.0, 0.0, 0.0};
+            acc[e] = EuphoticAdj{};
         }
         {
             double inc[NEU][NTR];
@@ -288,11 +288,7 @@ __device__ __forceinline__ void sub_adjoint_lds(const Grid& g, const Model& md, 
                 const int le = r0q + e;
 #pragma unroll
                 for (int t = 0; t < NTR; ++t) s_yb[le * NTR + t] = yb[e][t];
-                s_acc[le * 5 + 0] = acc[e].A;
-                s_acc[le * 5 + 1] = acc[e].B;
-                s_acc[le * 5 + 2] = acc[e].lam;
-                s_acc[le * 5 + 3] = acc[e].sig;
-                s_acc[le * 5 + 4] = acc[e].phib;
+                acc_store<NTR>(acc[e], s_acc + le * acc_fields<NTR>());
             }
         s_sphi[tid] = sphi;
     }
@@ -302,12 +298,11 @@ __device__ __forceinline__ void sub_adjoint_lds(const Grid& g, const Model& md, 
     if (k < ne) {
 #pragma unroll
         for (int t = 0; t < NTR; ++t) ybar[t] = s_yb[tid * NTR + t];
-        const EuphoticAdj acc{s_acc[tid * 5 + 0], s_acc[tid * 5 + 1], s_acc[tid * 5 + 2], s_acc[tid * 5 + 3],
-                              s_acc[tid * 5 + 4]};
+        const EuphoticAdj acc = acc_load<NTR>(s_acc + tid * acc_fields<NTR>());
         const Euphotic<NEU> E = make_euphotic<NEU>(p, Q_own, ne, oc.light, oc.hz, oc.rho);
         euphotic_adj_finish<NTR, NEU, NP>(p, E, k, zc, drho_k, acc, ub);
     } else {
-        deep_reverse<NTR, NP>(p, deep_factors(p, h, nsub), nsub, h, rho_k, drho_k, s_sphi[lc], yj, mr, ybar, ub);
+        deep_reverse<NTR, NP>(p, deep_factors<NTR>(p, h, nsub), nsub, h, rho_k, drho_k, s_sphi[lc], yj, mr, ybar, ub);
     }
 }
 
@@ -784,7 +779,7 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
     double* const s_mu = s_dyn;
     double* const s_traj = s_dyn + (size_t)(TPB + ps.ahalo_max) * NTR;
     __shared__ double s_yb[TS * NTR];      // internal-step results per euphotic row (SUB only)
-    __shared__ double s_acc[TS * 5];
+    __shared__ double s_acc[TS * acc_fields<NTR>()];
     __shared__ double s_sphi[TS];
 
     const int tid = threadIdx.x;

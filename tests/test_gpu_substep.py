@@ -3,10 +3,11 @@
 Every kernel path of libtmm runs with nbgc = 8 against the oracle with the
 same nbgc: the tile step kernel, the single-launch year kernel, the
 member-parallel ensemble kernel, both tangents, and the persistent and tile
-adjoints.  Tolerances as for one evaluation per step (states point by point,
-signed fields per tracer column, gradients per component, as in
-``tolerances.py``): one step 1e-14, one model year 1e-12, tangent 1e-11,
-adjoint 1e-10.
+adjoints, for the N and PO4-DOP models and for PO4-DOP-PHY (section 2.2.2),
+whose batches run through the tile kernels.  Tolerances as for one
+evaluation per step (states point by point, signed fields per tracer column,
+gradients per component, as in ``tolerances.py``): one step 1e-13, one model
+year 1e-12, tangent 1e-11, adjoint 1e-10.
 """
 
 import dataclasses
@@ -21,6 +22,7 @@ from tolerances import ADJOINT, MISFIT, STEP, TANGENT, YEAR, columnwise, compone
 pytestmark = pytest.mark.gpu
 
 NBGC = 8
+PHY = synth.MODEL_NDOPPHY
 
 
 def _tmm():
@@ -32,7 +34,9 @@ def _tmm():
 def inputs():
     return {"tiny_n": dataclasses.replace(synth.tiny(), nbgc=NBGC),
             "tiny_ndop": dataclasses.replace(synth.tiny(model=synth.MODEL_NDOP), nbgc=NBGC),
-            "small": dataclasses.replace(synth.small_ndop(), nbgc=NBGC)}
+            "small": dataclasses.replace(synth.small_ndop(), nbgc=NBGC),
+            "tiny_phy": dataclasses.replace(synth.tiny(model=PHY), nbgc=NBGC),
+            "small_phy": dataclasses.replace(synth.small_ndop(model=PHY), nbgc=NBGC)}
 
 
 def _make(inp, nbatch_max=1, adjoint=0, ckpt=240):
@@ -40,7 +44,7 @@ def _make(inp, nbatch_max=1, adjoint=0, ckpt=240):
     return _tmm().TMM(inp.desc_arrays(), nbatch_max=nbatch_max, adjoint_nbatch_max=adjoint, ckpt_every=ckpt)
 
 
-@pytest.mark.parametrize("name", ["tiny_n", "tiny_ndop", "small"])
+@pytest.mark.parametrize("name", ["tiny_n", "tiny_ndop", "small", "tiny_phy", "small_phy"])
 def test_substep_step_parity(inputs, name):
     inp = inputs[name]
     t = _make(inp)
@@ -60,7 +64,7 @@ def test_substep_step_parity(inputs, name):
 
 
 @pytest.mark.parametrize("persistent", [1, 0])
-@pytest.mark.parametrize("name", ["tiny_n", "tiny_ndop", "small"])
+@pytest.mark.parametrize("name", ["tiny_n", "tiny_ndop", "small", "tiny_phy", "small_phy"])
 def test_substep_year_parity(inputs, name, persistent):
     tmm = _tmm()
     inp = inputs[name]
@@ -100,25 +104,28 @@ def test_substep_member_kernel(inputs, nb, nsteps):
 
 
 @pytest.mark.parametrize("persistent", [1, 0])
-def test_substep_tangent(inputs, persistent):
+@pytest.mark.parametrize("name", ["small", "small_phy"])
+def test_substep_tangent(inputs, name, persistent):
     tmm = _tmm()
-    inp = inputs["small"]
+    inp = inputs[name]
+    ntr = inp.ntracer
     t = _make(inp)
     t.set_option(tmm.TMM_OPT_PERSISTENT, persistent)
     o = oracle.Oracle(inp)
     u = synth.nominal(inp.model)
     t.set_params(u)
     rng = np.random.default_rng(13)
-    y = inp.initial_state() * rng.uniform(0.8, 1.2, size=(inp.n, 2))
+    y = inp.initial_state() * rng.uniform(0.8, 1.2, size=(inp.n, ntr))
     v = rng.standard_normal(y.shape) * y
     phi, jv = t.year_jvp(t.state(y), t.state(v), mode=tmm.TMM_JVP_TANGENT)
     ephi, ejv = o.year_tangent(u, y, v)
-    assert pointwise(phi.cpu().numpy(), ephi, 2) <= YEAR
-    assert columnwise(jv.cpu().numpy(), ejv, 2, f"nbgc tangent, path {persistent}") <= TANGENT
+    assert pointwise(phi.cpu().numpy(), ephi, ntr) <= YEAR
+    assert columnwise(jv.cpu().numpy(), ejv, ntr, f"nbgc {name} tangent, path {persistent}") <= TANGENT
 
 
 @pytest.mark.parametrize("persistent", [1, 0])
-@pytest.mark.parametrize("name,ckpt", [("tiny_n", 240), ("tiny_ndop", 240), ("small", 480)])
+@pytest.mark.parametrize("name,ckpt", [("tiny_n", 240), ("tiny_ndop", 240), ("small", 480), ("tiny_phy", 240),
+                                       ("small_phy", 480)])
 def test_substep_adjoint(inputs, name, ckpt, persistent):
     import torch
     tmm = _tmm()
@@ -157,6 +164,46 @@ def test_substep_ensemble_adjoint(inputs):
     assert componentwise(J, eJ, "nbgc two members J") <= MISFIT
     assert componentwise(G, eG, "nbgc two members dJ/du") <= ADJOINT
     assert columnwise(dy0.cpu().numpy(), eY, 2, "nbgc two members dJ/dy0") <= ADJOINT
+
+
+def test_substep_phy_members(inputs):
+    """Three PO4-DOP-PHY members through the tile kernels: one model year, and
+    the tile adjoint with the gradient of every member."""
+    import torch
+    inp = inputs["tiny_phy"]
+    nb = 3
+    U = synth.latin_hypercube(PHY, nb, seed=8)
+    o = oracle.Oracle(inp)
+    rng = np.random.default_rng(9)
+    y0 = inp.initial_state(nb) * rng.uniform(0.7, 1.3, size=(inp.n, 3 * nb))
+    t = _make(inp, nbatch_max=nb, adjoint=nb)
+    t.set_params(U)
+    got, _ = t.year(t.state(y0))
+    exp, _ = o.year(U, y0)
+    assert pointwise(got.cpu().numpy(), exp, 3, "nbgc PHY three members, one year") <= YEAR
+    snaps = o.snapshots(synth.hidden_params(PHY, seed=21), inp.initial_state())
+    obs1 = snaps * (1 + 0.05 * synth.obs_noise(snaps.shape, seed=22))
+    obs = np.concatenate([obs1, obs1 * 1.01, obs1 * 0.99], axis=2)
+    eJ, eG, eY = o.year_adjoint(U, y0, obs)
+    J, G, dy0 = t.year_adjoint(t.state(y0), torch.as_tensor(obs).cuda())
+    assert componentwise(J, eJ, "nbgc PHY three members J") <= MISFIT
+    assert componentwise(G, eG, "nbgc PHY three members dJ/du") <= ADJOINT
+    assert columnwise(dy0.cpu().numpy(), eY, 3, "nbgc PHY three members dJ/dy0") <= ADJOINT
+
+
+def test_substep_phy_global_year():
+    """Full size: one PO4-DOP-PHY model year of the global grid with 8 internal steps (single-launch kernel)."""
+    tmm = _tmm()
+    inp = dataclasses.replace(synth.global_2p8(model=PHY), nbgc=NBGC)
+    t = _make(inp)
+    assert t.query(tmm.TMM_Q_PERSISTENT) == 1
+    u = synth.nominal(PHY)
+    t.set_params(u)
+    y0 = inp.initial_state()
+    got, _ = t.year(t.state(y0))
+    print("[gpu] oracle year, global grid, PO4-DOP-PHY, 8 internal steps (~60 s)", flush=True)
+    exp, _ = oracle.Oracle(inp).year(u, y0)
+    assert pointwise(got.cpu().numpy(), exp, 3, "nbgc PHY global year") <= YEAR
 
 
 def test_substep_global_year():

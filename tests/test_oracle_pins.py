@@ -480,13 +480,15 @@ def test_single_substep_is_the_plain_source(tiny_ndop):
     assert np.array_equal(a, b)
 
 
-def test_substeps_are_explicit_euler_of_the_column_ode(tiny_ndop):
+@pytest.mark.parametrize("grid", ["tiny_ndop", "tiny_phy"])
+def test_substeps_are_explicit_euler_of_the_column_ode(grid, request):
     """The source with n internal steps is n explicit Euler steps of dt/n on dy/dt = q(y).
 
     Brute force from the (separately pinned) column term, and first-order
-    convergence towards a fine-step solution of the same ODE."""
-    inp = tiny_ndop
-    u = synth.nominal(synth.MODEL_NDOP)
+    convergence towards a fine-step solution of the same ODE; for PO4-DOP and
+    PO4-DOP-PHY."""
+    inp = request.getfixturevalue(grid)
+    u = synth.nominal(inp.model)
     dt = 360.0 / inp.nstep
     for c in (0, 40):
         s, e, lat = _column(inp, c)
@@ -502,10 +504,13 @@ def test_substeps_are_explicit_euler_of_the_column_ode(tiny_ndop):
         for step in (dt, 30.0):
             end = y0 + oracle.bgc_source(inp.model, insol, h, y0, u, inp.neuphotic, step, 8)
             assert np.abs(end - euler(8, step / 8)).max() <= 1e-14 * np.abs(y0).max()
-        # first order: over a 5-day step the error against 8192 Euler steps halves as n doubles
-        fine = euler(8192, 5.0 / 8192) - y0
-        errs = [np.abs(oracle.bgc_source(inp.model, insol, h, y0, u, inp.neuphotic, 5.0, n) - fine).max()
-                for n in (4, 8, 16, 32)]
+        # first order: over a 5-day step the error against 8192 Euler steps halves as n doubles;
+        # PO4-DOP-PHY's growth scales with PHY itself, so its first-order regime starts at
+        # shorter sub-steps: a 1-day step there
+        span, ns = (5.0, (4, 8, 16, 32)) if inp.model == synth.MODEL_NDOP else (1.0, (4, 8, 16))
+        fine = euler(8192, span / 8192) - y0
+        errs = [np.abs(oracle.bgc_source(inp.model, insol, h, y0, u, inp.neuphotic, span, n) - fine).max()
+                for n in ns]
         assert errs[0] > 1e-6 * np.abs(fine).max()
         for a, b in zip(errs, errs[1:]):
             assert 1.8 < a / b < 2.2, errs
@@ -533,24 +538,28 @@ def test_substep_decay_closed_form(tiny_ndop):
         assert np.abs(y1.sum(1) / y0.sum(1) - 1).max() < 2e-13
 
 
-def test_substeps_conserve_mass(small_ndop):
-    u = synth.nominal(synth.MODEL_NDOP)
-    y0 = small_ndop.initial_state()
-    y1, _ = oracle.Oracle(small_ndop, nbgc=8).year(u, y0)
-    y1p, _ = oracle.Oracle(small_ndop, nbgc=1).year(u, y0)
-    V = small_ndop.grid.volumes()
+@pytest.mark.parametrize("model", [synth.MODEL_NDOP, synth.MODEL_NDOPPHY])
+def test_substeps_conserve_mass(small_ndop, model):
+    inp = small_ndop if model == synth.MODEL_NDOP else synth.small_ndop(model=model)
+    u = synth.nominal(model)
+    y0 = inp.initial_state()
+    y1, _ = oracle.Oracle(inp, nbgc=8).year(u, y0)
+    y1p, _ = oracle.Oracle(inp, nbgc=1).year(u, y0)
+    V = inp.grid.volumes()
     m0 = V @ y0.sum(1)
     assert abs(V @ y1.sum(1) - m0) <= 1e-13 * m0
     assert 0 < np.abs(y1 - y1p).max() < 0.05 * np.abs(y1p).max()   # close to, not equal to, one step
 
 
-def test_substep_derivatives(tiny_ndop):
-    """Tangent vs central differences, tangent vs reverse (dot test), dJ/du vs differences, with nbgc = 8."""
-    inp = tiny_ndop
+@pytest.mark.parametrize("grid", ["tiny_ndop", "tiny_phy"])
+def test_substep_derivatives(grid, request):
+    """Tangent vs central differences, tangent vs reverse (dot test), dJ/du vs differences, with nbgc = 8
+    (PO4-DOP and PO4-DOP-PHY)."""
+    inp = request.getfixturevalue(grid)
     o = oracle.Oracle(inp, nbgc=8)
-    u = synth.nominal(synth.MODEL_NDOP)
+    u = synth.nominal(inp.model)
     rng = np.random.default_rng(14)
-    y = inp.initial_state() * rng.uniform(0.8, 1.2, size=(inp.n, 2))
+    y = inp.initial_state() * rng.uniform(0.8, 1.2, size=(inp.n, inp.ntracer))
     v = rng.standard_normal(y.shape) * y
     w = rng.standard_normal(y.shape)
     _, jv = o.year_tangent(u, y, v)

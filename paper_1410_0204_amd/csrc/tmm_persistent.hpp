@@ -553,14 +553,22 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
         }
 
         // the halo of state jj (ring slot jj; slot 0 holds y_in) into LDS: every
-        // pass issues the loads of all the lane's halo rows together and
-        // defines them all again, until none is the sentinel
+        // pass issues the loads of all the lane's halo rows together, and only
+        // then checks them (a check inside a row's branch would make the loads
+        // of the next row wait for those of this one: one round trip per row),
+        // until none is the sentinel
         {
             const size_t sb = (size_t)(jj % kRing) * state_len;
             double hv[kHaloPerThread][NTR], hd[kHaloPerThread][NTR];
+#pragma unroll
+            for (int i = 0; i < kHaloPerThread; ++i)
+#pragma unroll
+                for (int t = 0; t < NTR; ++t) {
+                    hv[i][t] = 0.0;
+                    hd[i][t] = 0.0;
+                }
             long long it = 0;
             for (;;) {
-                bool miss = false;
 #pragma unroll
                 for (int i = 0; i < kHaloPerThread; ++i) {
                     if (hrow[i] < 0) continue;
@@ -568,13 +576,18 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
                     for (int t = 0; t < NTR; ++t) {
                         const size_t o = ring_at(sb, g.n, hrow[i], t);
                         hv[i][t] = __hip_atomic_load(&ps.ring[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        miss |= is_sentinel(hv[i][t]);
-                        if (TANGENT) {
+                        if (TANGENT)
                             hd[i][t] = __hip_atomic_load(&ps.vring[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            miss |= is_sentinel(hd[i][t]);
-                        }
                     }
                 }
+                bool miss = false;
+#pragma unroll
+                for (int i = 0; i < kHaloPerThread; ++i)
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) {
+                        miss |= is_sentinel(hv[i][t]);
+                        if (TANGENT) miss |= is_sentinel(hd[i][t]);
+                    }
                 if (!miss) break;
                 ++it;
                 if (it > ps.spin_limit ||
@@ -1029,23 +1042,30 @@ __global__ __launch_bounds__(TPB, 1) void k_adjoint_persistent(
             }
         }
 
-        // the halo of mu_j (ring slot jj) into LDS, all of the lane's rows per pass
+        // the halo of mu_j (ring slot jj) into LDS, all of the lane's rows per
+        // pass, loaded together and then checked (as in the forward kernel)
         {
             const size_t sb = (size_t)(jj % kRing) * state_len;
             double hv[kHaloPerThread][NTR];
+#pragma unroll
+            for (int i = 0; i < kHaloPerThread; ++i)
+#pragma unroll
+                for (int t = 0; t < NTR; ++t) hv[i][t] = 0.0;
             long long it = 0;
             for (;;) {
-                bool miss = false;
 #pragma unroll
                 for (int i = 0; i < kHaloPerThread; ++i) {
                     if (hrow[i] < 0) continue;
 #pragma unroll
-                    for (int t = 0; t < NTR; ++t) {
+                    for (int t = 0; t < NTR; ++t)
                         hv[i][t] = __hip_atomic_load(&ps.ring[ring_at(sb, g.n, hrow[i], t)], __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
-                        miss |= is_sentinel(hv[i][t]);
-                    }
                 }
+                bool miss = false;
+#pragma unroll
+                for (int i = 0; i < kHaloPerThread; ++i)
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) miss |= is_sentinel(hv[i][t]);
                 if (!miss) break;
                 ++it;
                 if (it > ps.spin_limit ||

@@ -114,8 +114,10 @@ struct Plan {
     int ntile_max = 0;
     // workspace offsets (bytes)
     size_t o_ae, o_aecol, o_aet, o_aetcol, o_aicm, o_airm, o_colstart, o_blk, o_lat, o_area, o_dz;
+    size_t o_aeself;           // per row: the ELL slot of Ae that reads the row itself
     std::vector<size_t> o_tiles;
     size_t o_u, o_light, o_rho, o_drho, o_member, o_scol, o_dcol;
+    size_t o_uT, o_lightT, o_rhoT;   // member-fastest copies (member-parallel kernel)
     size_t o_ybuf[3], o_vbuf[2], o_part, o_vec, o_ubt, o_jpart, o_ckpt, o_seg, o_final, o_mu[2];
     size_t o_pubar, o_pjpart;       // per-domain adjoint partial sums (persistent path)
     size_t vec_stride;
@@ -199,11 +201,18 @@ int validate(const tmm_desc* d, Plan& P) {
     P.ntr = ntracer_of(d->model); P.nparam = nparam_of(d->model);
     P.npad = (d->n + 63) / 64 * 64;
     P.col_start.assign(d->col_start, d->col_start + d->ncol + 1);
+    // ELL width of Ae: every row gets a slot that reads the row itself (its
+    // diagonal entry, else a zero padding entry), so a row without a diagonal
+    // counts one more
     int ew = 0;
     std::vector<int> tcount(d->n, 0);
     for (int i = 0; i < d->n; ++i) {
-        ew = std::max(ew, d->ae_rowptr[i + 1] - d->ae_rowptr[i]);
-        for (int e = d->ae_rowptr[i]; e < d->ae_rowptr[i + 1]; ++e) tcount[d->ae_colidx[e]]++;
+        bool diag = false;
+        for (int e = d->ae_rowptr[i]; e < d->ae_rowptr[i + 1]; ++e) {
+            tcount[d->ae_colidx[e]]++;
+            diag = diag || d->ae_colidx[e] == i;
+        }
+        ew = std::max(ew, d->ae_rowptr[i + 1] - d->ae_rowptr[i] + (diag ? 0 : 1));
     }
     P.ew = ew;
     P.etw = *std::max_element(tcount.begin(), tcount.end());
@@ -225,6 +234,7 @@ int validate(const tmm_desc* d, Plan& P) {
     const size_t nm = d->nmat, npad = P.npad;
     P.o_ae = take(nm * P.ew * npad * 8);
     P.o_aecol = take((size_t)P.ew * npad * 4);
+    P.o_aeself = take((size_t)npad * 4);
     P.o_aet = take(nm * P.etw * npad * 8);
     P.o_aetcol = take((size_t)P.etw * npad * 4);
     P.o_aicm = take(nm * P.nblk * 8);
@@ -242,6 +252,9 @@ int validate(const tmm_desc* d, Plan& P) {
     P.o_rho = take(nbm * (d->nlayer + 1) * d->nlayer * 8);
     P.o_drho = take(nbm * (d->nlayer + 1) * d->nlayer * 8);
     P.o_member = take(nbm * 4);
+    P.o_uT = take(nbm * P.nparam * 8);
+    P.o_lightT = take(nbm * d->nlayer * 8);
+    P.o_rhoT = take(nbm * (d->nlayer + 1) * d->nlayer * 8);
     P.o_scol = take(nbm * 4);
     P.o_dcol = take(nbm * 4);
     const size_t state = (size_t)d->n * nbm * P.ntr * 8;
@@ -377,6 +390,10 @@ struct tmm_ctx {
         m.rho = at<double>(P.o_rho);
         m.drho = at<double>(P.o_drho);
         m.member = at<int>(P.o_member);
+        m.uT = at<double>(P.o_uT);
+        m.lightT = at<double>(P.o_lightT);
+        m.rhoT = at<double>(P.o_rhoT);
+        m.nbm = P.nbatch_max;
         m.nsub = P.nsub;
         m.hsub = tmm::kDaysPerYear / P.nstep / P.nsub;
         return m;
@@ -389,6 +406,7 @@ struct tmm_ctx {
         m.ai_month = P.nblk;
         m.ae = at<double>(P.o_ae);
         m.ae_col = at<int>(P.o_aecol);
+        m.ae_self = at<int>(P.o_aeself);
         m.aet = at<double>(P.o_aet);
         m.aet_col = at<int>(P.o_aetcol);
         m.ai_cm = at<double>(P.o_aicm);
@@ -1131,23 +1149,32 @@ int tmm_create(const tmm_desc* d, void* dev_workspace, size_t bytes, void* hip_s
     auto fail = [&](int code) { (void)hipStreamSynchronize(h->stream); delete h; return code; };
 
     // Ae in slot-major ELL; padding entries point at the row itself with value 0.
+    // self[i]: the slot of row i that reads row i (its diagonal entry, else the
+    // first padding entry; the width leaves one for every row without a diagonal).
     {
         std::vector<int> col((size_t)P.ew * P.npad);
         std::vector<int> pos(d->ae_nnz);
+        std::vector<int> self(P.npad, 0);
         for (int i = 0; i < P.npad; ++i) {
             const int len = i < P.n ? d->ae_rowptr[i + 1] - d->ae_rowptr[i] : 0;
+            int own = -1;
             for (int s = 0; s < P.ew; ++s) {
                 const size_t at = (size_t)s * P.npad + i;
                 if (s < len) {
                     const int e = d->ae_rowptr[i] + s;
                     col[at] = d->ae_colidx[e];
                     pos[e] = (int)at;
+                    if (own < 0 && col[at] == i) own = s;
                 } else {
                     col[at] = i < P.n ? i : 0;
+                    if (own < 0 && i < P.n) own = s;
                 }
             }
+            if (i < P.n && own < 0) return fail(TMM_EINVAL);
+            self[i] = own < 0 ? 0 : own;
         }
         if (upload(h, h->at<int>(P.o_aecol), col.data(), col.size() * 4)) return fail(TMM_EDEVICE);
+        if (upload(h, h->at<int>(P.o_aeself), self.data(), self.size() * 4)) return fail(TMM_EDEVICE);
         std::vector<double> val((size_t)P.ew * P.npad);
         for (int m = 0; m < P.nmat; ++m) {
             std::fill(val.begin(), val.end(), 0.0);
@@ -1291,12 +1318,18 @@ int tmm_set_params(tmm_handle h, int nbatch, const double* u) {
     }
     std::vector<double> uu(u, u + (size_t)nbatch * np);
     if (upload(h, h->at<double>(h->P.o_u), uu.data(), uu.size() * 8)) return TMM_EDEVICE;
+    const size_t nbm = (size_t)h->P.nbatch_max;
+    std::vector<double> ut(nbm * np, 0.0);
+    for (int b = 0; b < nbatch; ++b)
+        for (int i = 0; i < np; ++i) ut[(size_t)i * nbm + b] = u[(size_t)b * np + i];
+    if (upload(h, h->at<double>(h->P.o_uT), ut.data(), ut.size() * 8)) return TMM_EDEVICE;
     for (int b = 0; b < nbatch; ++b) h->h_member[b] = b;
     if (upload(h, h->at<int>(h->P.o_member), h->h_member.data(), (size_t)nbatch * 4)) return TMM_EDEVICE;
     const int total = nbatch * (h->P.nlayer + 1) * h->P.nlayer;
     hipLaunchKernelGGL(tmm::k_param_tables, dim3((total + 255) / 256), dim3(256), 0, h->stream, nbatch, h->P.model,
                        np, h->P.nlayer, h->P.neu, h->at<double>(h->P.o_u), h->at<double>(h->P.o_dz),
-                       h->at<double>(h->P.o_light), h->at<double>(h->P.o_rho), h->at<double>(h->P.o_drho));
+                       h->at<double>(h->P.o_light), h->at<double>(h->P.o_rho), h->at<double>(h->P.o_drho),
+                       h->P.nbatch_max, h->at<double>(h->P.o_lightT), h->at<double>(h->P.o_rhoT));
     TMM_LAUNCHED();
     TMM_TRY(hipStreamSynchronize(h->stream));
     h->nbatch = nbatch;

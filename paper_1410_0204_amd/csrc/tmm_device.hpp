@@ -47,32 +47,40 @@ struct BgcParams {
 
 namespace tmm {
 
-__device__ __forceinline__ BgcParams load_params(const double* __restrict__ u, int model, int nparam, int m) {
-    const double* p = u + (size_t)m * nparam;
+// Parameter i of member m at u[m * sm + i * sp]: the member-major table
+// (sm = nparam, sp = 1) or its member-fastest copy (sm = 1, sp = members).
+__device__ __forceinline__ BgcParams load_params_at(const double* __restrict__ u, int model, size_t sm, size_t sp,
+                                                    int m) {
+    const double* q = u + (size_t)m * sm;
+    auto p = [&](int i) { return q[(size_t)i * sp]; };
     BgcParams r;
-    r.alpha = p[0];
-    r.kw = p[1];
-    r.k1 = p[2];
-    r.ki = p[3];
+    r.alpha = p(0);
+    r.kw = p(1);
+    r.k1 = p(2);
+    r.ki = p(3);
     r.lam3 = r.kap3 = r.lam3p = r.sig3 = 0.0;
     if (model == MODEL_NDOPPHY) {
-        r.lam = p[4];
-        r.sig = p[5];
-        r.lam3 = p[6];
-        r.kap3 = p[7];
-        r.lam3p = p[8];
-        r.sig3 = p[9];
-        r.b = p[10];
+        r.lam = p(4);
+        r.sig = p(5);
+        r.lam3 = p(6);
+        r.kap3 = p(7);
+        r.lam3p = p(8);
+        r.sig3 = p(9);
+        r.b = p(10);
     } else if (model == MODEL_NDOP) {
-        r.lam = p[4];
-        r.sig = p[5];
-        r.b = p[6];
+        r.lam = p(4);
+        r.sig = p(5);
+        r.b = p(6);
     } else {
         r.lam = 0.0;
         r.sig = 0.0;
-        r.b = p[4];
+        r.b = p(4);
     }
     return r;
+}
+
+__device__ __forceinline__ BgcParams load_params(const double* __restrict__ u, int model, int nparam, int m) {
+    return load_params_at(u, model, (size_t)nparam, 1, m);
 }
 
 // Month pair and weight of step j: monthly matrices sit at mid-month and the
@@ -137,12 +145,15 @@ __device__ __forceinline__ Production production(const BgcParams& p, double N, d
 // Per-member tables: light attenuation exp(-z_k K_H2O) at layer centres and
 // the Martin-curve remineralisation fractions rho_k (per metre) with
 // d rho_k / d b, for every column depth n_c.
-// Layout: light[m][k], rho[(m*(nlayer+1) + n_c)*nlayer + k].
+// Layout: light[m][k], rho[(m*(nlayer+1) + n_c)*nlayer + k]; the
+// member-fastest copies lightT[k][m] and rhoT[n_c*nlayer + k][m] (member
+// stride nbm) serve the member-parallel kernel, whose lanes are members.
 // ---------------------------------------------------------------------------
 __global__ void k_param_tables(int nbatch, int model, int nparam, int nlayer, int neu,
                                const double* __restrict__ u, const double* __restrict__ dz,
                                double* __restrict__ light, double* __restrict__ rho,
-                               double* __restrict__ drho) {
+                               double* __restrict__ drho, int nbm, double* __restrict__ lightT,
+                               double* __restrict__ rhoT) {
     const int per_member = (nlayer + 1) * nlayer;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nbatch * per_member) return;
@@ -159,7 +170,9 @@ __global__ void k_param_tables(int nbatch, int model, int nparam, int nlayer, in
     };
     if (nc == 0) {
         const double z = bottom(k) - 0.5 * dz[k];
-        light[(size_t)m * nlayer + k] = exp(-z * p.kw);
+        const double l = exp(-z * p.kw);
+        light[(size_t)m * nlayer + k] = l;
+        lightT[(size_t)k * nbm + m] = l;
     }
     double r = 0.0, dr = 0.0;
     if (nc >= 1 && k < nc) {
@@ -182,6 +195,7 @@ __global__ void k_param_tables(int nbatch, int model, int nparam, int nlayer, in
     }
     rho[idx] = r;
     drho[idx] = dr;
+    rhoT[(size_t)rem * nbm + m] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -207,6 +221,12 @@ struct Model {
     const double* rho;       // [members][nlayer+1][nlayer]
     const double* drho;
     const int* member;       // [slots] parameter row of each state slot
+    // member-fastest copies for the member-parallel kernel (lane = member):
+    // uT[i][m], lightT[k][m], rhoT[n_c*nlayer + k][m], member stride nbm
+    const double* uT;
+    const double* lightT;
+    const double* rhoT;
+    int nbm;
     int nsub;                // internal BGC steps per ocean step (section 7)
     double hsub;             // their length dt_d / nsub, days
 };
@@ -219,6 +239,7 @@ struct Mats {
     size_t ai_month;         // values per month of the block array
     const double* ae;        // [nmat][ew][npad]
     const int* ae_col;       // [ew][npad]
+    const int* ae_self;      // [npad] the slot of each row that reads the row itself
     const double* aet;       // [nmat][etw][npad]
     const int* aet_col;
     const double* ai_cm;     // [nmat][blocks] column-major blocks
@@ -756,8 +777,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
     // overlaps it (a load cannot move across the barrier)
     const double Q = g.ins[(size_t)(j % g.nstep) * g.nlat + g.col_lat[c]];
     const int m = md.member[bb];
-    const BgcParams p = load_params(md.u, md.model, md.nparam, m);
-    const size_t tab = ((size_t)m * (g.nlayer + 1) + nc) * g.nlayer;
+    // member tables through their member-fastest copies: the lanes of one
+    // load read neighbouring words instead of one cache line each
+    const BgcParams p = load_params_at(md.uT, md.model, 1, (size_t)md.nbm, m);
+    const double* rhoc = md.rhoT + (size_t)nc * g.nlayer * md.nbm + m;   // rho_k of this depth at [k * nbm]
     const size_t me = (size_t)bb * NTR;
     const int ne = nc < g.neu ? nc : g.neu;
     double Ne[NEU], le[NEU], f[NEU];
@@ -765,7 +788,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
     for (int e = 0; e < NEU; ++e) {
         const int re = rs + (e < nc ? e : nc - 1);
         Ne[e] = y[(size_t)re * W + me];
-        le[e] = md.light[(size_t)m * g.nlayer + (e < g.nlayer ? e : 0)];
+        le[e] = md.lightT[(size_t)(e < g.nlayer ? e : 0) * md.nbm + m];
     }
 
     // stage the interpolated column matrices (this wavefront's slice only);
@@ -829,7 +852,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
             ye[e][0] = e < ne ? Ne[e] : 0.0;
             if (NTR > 1) ye[e][NTR - 1] = e < ne ? y[(size_t)rr * W + me + NTR - 1] : 0.0;
             hz[e] = g.dz[ee];
-            re[e] = md.rho[tab + ee];
+            re[e] = rhoc[(size_t)ee * md.nbm];
 #pragma unroll
             for (int t = 0; t < NTR; ++t) einc[e][t] = 0.0;
         }
@@ -857,8 +880,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
                 for (int t = 0; t < NTR; ++t) yv[sl][t] = src[t];
             }
         }
-        const double dop = NTR > 1 ? y[(size_t)(rs + kk) * W + me + NTR - 1] : 0.0;
-        const double rho = md.rho[tab + kk];
+        // the row's own DOP, from the stencil slot that reads the row itself
+        // (a wavefront-uniform index, so this is a select, not a load)
+        double dop = 0.0;
+        if constexpr (NTR > 1) {
+            const int own = mt.ae_self[rs + kk];
+#pragma unroll
+            for (int sl = 0; sl < EL; ++sl) dop = sl == own ? yv[sl][NTR - 1] : dop;
+        }
+        const double rho = rhoc[(size_t)kk * md.nbm];
         double acc[NTR];
 #pragma unroll
         for (int t = 0; t < NTR; ++t) acc[t] = 0.0;

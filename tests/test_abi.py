@@ -86,13 +86,46 @@ def test_internal_bgc_steps_in_descriptor(small_ndop):
 
 
 def test_po4_dop_phy_descriptor():
-    """Three tracers are accepted; internal BGC steps are not supported with them."""
+    """Three tracers are accepted, with and without internal BGC steps (up to 4 euphotic layers)."""
     import synth
     inp = synth.tiny(model=synth.MODEL_NDOPPHY)
     d, _ = _desc(inp)
     assert _status(d)[0] == 0
     d, _ = _desc(inp, nbgc=8)
+    assert _status(d)[0] == 0
+    small = synth.small_ndop(model=synth.MODEL_NDOPPHY)
+    d, _ = _desc(small, nbgc=8, neuphotic=5)
     assert _status(d)[0] == -6
+
+
+def test_rows_without_diagonal_widen_the_stencil_table(small_ndop):
+    """Every row keeps a stencil slot that reads the row itself (the member-parallel kernel takes the
+    row's own state from it): a row of the greatest length without its diagonal widens the ELL table
+    by one slot, so the workspace grows; the same change in a shorter row does not."""
+    tm = small_ndop.tm
+    lens = np.diff(tm.ae_rowptr)
+    d, keep = _desc(small_ndop)            # keep: the arrays the descriptor points into
+    base = _status(d)
+    assert base[0] == 0
+
+    def without_diagonal(i):
+        col = tm.ae_colidx.copy()
+        e0, e1 = tm.ae_rowptr[i], tm.ae_rowptr[i + 1]
+        row = set(col[e0:e1].tolist())
+        assert i in row
+        spare = next(c for c in range(small_ndop.n) if c not in row)
+        col[e0 + list(col[e0:e1]).index(i)] = spare
+        return col
+
+    full = int(np.argmax(lens))
+    short = int(np.argmin(lens))
+    assert lens[short] < lens[full]
+    d, keep = _desc(small_ndop, ae_colidx=without_diagonal(full))
+    rc, n = _status(d)
+    assert rc == 0 and n > base[1]
+    d, keep = _desc(small_ndop, ae_colidx=without_diagonal(short))
+    rc, n = _status(d)
+    assert rc == 0 and n == base[1]
 
 
 def test_strerror():

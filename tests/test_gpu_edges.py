@@ -182,3 +182,35 @@ def test_exchange_probe():
     for k in ("round_trip_same_xcd_us", "round_trip_cross_xcd_us", "barrier_us", "agent_load_us"):
         assert 0.0 < p[k] < 1000.0, k
     assert all(0 <= x < 16 for x in p["xcds"])
+
+
+def test_member_kernel_rows_without_diagonal():
+    """The member-parallel kernel takes a row's own DOP from the stencil slot that reads the row
+    itself: the diagonal entry, or, in a row without one, a zero padding entry (the ELL table is
+    widened when the longest row lacks its diagonal).  Rows of both kinds, 20 members, steps
+    against the oracle."""
+    import copy
+    tmm = _tmm()
+    inp = copy.deepcopy(synth.small_ndop())
+    tm = inp.tm
+    lens = np.diff(tm.ae_rowptr)
+    col = tm.ae_colidx.copy()
+    for i in (int(np.argmax(lens)), int(np.argmin(lens)), inp.n // 2):
+        e0, e1 = tm.ae_rowptr[i], tm.ae_rowptr[i + 1]
+        row = set(col[e0:e1].tolist())
+        spare = next(c for c in range(inp.n) if c not in row)
+        col[e0 + list(col[e0:e1]).index(i)] = spare       # the diagonal's value now acts on another row
+    tm.ae_colidx = col
+    nb = 20
+    U = synth.latin_hypercube(synth.MODEL_NDOP, nb, seed=44)
+    print(f"[gpu] member kernel, rows without diagonal, {nb} members", flush=True)
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=nb)
+    t.set_option(tmm.TMM_OPT_MEMBER_KERNEL_MIN, 1)
+    t.set_params(U)
+    o = oracle.Oracle(inp)
+    rng = np.random.default_rng(45)
+    y = inp.initial_state(nb) * rng.uniform(0.7, 1.3, size=(inp.n, 2 * nb))
+    for j in (0, 1439, 2879):
+        got = t.step(j, t.state(y)).cpu().numpy()
+        exp = o.step(U, j, y)
+        assert pointwise(got, exp, 2, f"rows without diagonal, step {j}") <= STEP, j

@@ -365,6 +365,7 @@ def main():
         ms_fwd1 = start.elapsed_time(stop)
         ta = tmm.TMM(inp.desc_arrays(), nbatch_max=1, adjoint_nbatch_max=1, ckpt_every=inp.nstep, device=dev,
                      stream=stream)
+        autotune.apply_tuned(ta, 1)       # the same launch configuration as the forward years
         ta.set_params(u)
         for h, ck in ((ta, inp.nstep), (t, 240)):
             h.year_adjoint(y0, obs, want_dy0=False)   # warm-up
@@ -460,6 +461,8 @@ def bench_variant(args, inp, dev, stream, ms_plain, label):
     import synth
     t = tmm.TMM(inp.desc_arrays(), nbatch_max=1, adjoint_nbatch_max=1, ckpt_every=inp.nstep, device=dev,
                 stream=stream)
+    from paper_1410_0204_amd import autotune
+    autotune.apply_tuned(t, 1)            # this shape's tuned entry, if the table has one
     t.set_params(synth.nominal(inp.model))
     y0 = t.state(inp.initial_state())
     ya = t.state()

@@ -121,6 +121,14 @@ def custom(nlon: int, nlat: int, nlayer: int, ncol: int, n: int, model: int = MO
 
 
 def by_name(name: str) -> Inputs:
+    """The named workloads, plus the global grid's PO4-DOP-PHY model ("global_phy") and its
+    8 internal BGC steps per ocean step ("global_nbgc8")."""
+    if name == "global_phy":
+        return global_2p8(model=MODEL_NDOPPHY)
+    if name == "global_nbgc8":
+        inp = global_2p8()
+        inp.nbgc = 8
+        return inp
     table = {"tiny": tiny, "global": global_2p8, "ensemble": ensemble_1p4, "small": small_ndop,
              "one_degree": one_degree}
     return table[name]()

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -133,6 +134,7 @@ struct Plan {
     size_t o_probe;                 // words, results and load chain of tmm_probe_exchange
     size_t o_ring, o_vring;         // state rings of the persistent forward kernel (0: none)
     size_t o_phaloptr, o_phalo;     // halo rows of each domain
+    size_t o_pqlat;                 // latitude rows of each domain (insolation table in LDS)
     size_t o_pahaloptr, o_pahalo;   // ... for the transposed stencil (reverse sweep)
     size_t dep_capacity, halo_capacity;
     size_t total;
@@ -310,6 +312,7 @@ int validate(const tmm_desc* d, Plan& P) {
     P.o_phalo = take(P.halo_capacity * 4);
     P.o_pahaloptr = take((size_t)(kMaxDomains + 1) * 4);
     P.o_pahalo = take(P.halo_capacity * 4);
+    P.o_pqlat = take((size_t)kMaxDomains * (1 + tmm::kInsLat) * 4);
     if (d->n <= kMaxPersistentRows) {
         P.o_ring = take((size_t)tmm::kRing * d->n * P.ntr * 8);
         P.o_vring = take((size_t)tmm::kRing * d->n * P.ntr * 8);
@@ -341,6 +344,8 @@ struct tmm_ctx {
     int pers_tpb = 256;            // threads (= maximum rows) per domain
     int pers_hmax = 0;             // largest domain halo (rows)
     int pers_ahmax = 0;            // ... of the transposed stencil
+    int pers_qmax = 0;             // most latitude rows a domain spans (its insolation table in LDS)
+    bool pers_ql = false;          // the forward kernels keep that table in LDS
     int wide_min_members = 16;     // batches of at least this many members use k_step_members
     int mem_waves = tmm::kMembersWaves;   // option TMM_OPT_MEMBER_WAVES
     int mem_band = kDefaultBandRows;      // option TMM_OPT_MEMBER_BAND_ROWS (0: natural column order)
@@ -595,7 +600,9 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
 // steps (sn = 0: one evaluation per step; else the euphotic register width);
 // 512-thread workgroups exist for 16-row blocks only.
 template <int NTR, int KMAX, int TPB>
-const void* persistent_kernel_of(bool tangent, int sn) {
+const void* persistent_kernel_of(bool tangent, int sn, bool ql) {
+    if (sn == 0 && ql) return tangent ? (const void*)&tmm::k_year_persistent<NTR, true, KMAX, TPB, 0, true>
+                                      : (const void*)&tmm::k_year_persistent<NTR, false, KMAX, TPB, 0, true>;
     if (sn == 2) return tangent ? (const void*)&tmm::k_year_persistent<NTR, true, KMAX, TPB, 2>
                                 : (const void*)&tmm::k_year_persistent<NTR, false, KMAX, TPB, 2>;
     if (sn == 4) return tangent ? (const void*)&tmm::k_year_persistent<NTR, true, KMAX, TPB, 4>
@@ -604,17 +611,19 @@ const void* persistent_kernel_of(bool tangent, int sn) {
                    : (const void*)&tmm::k_year_persistent<NTR, false, KMAX, TPB>;
 }
 
-const void* persistent_kernel(int ntr, bool tangent, int kmax, int tpb, int sn) {
+const void* persistent_kernel(int ntr, bool tangent, int kmax, int tpb, int sn, bool ql = false) {
     if (ntr == 3) {    // PO4-DOP-PHY
-        if (tpb == 512) return persistent_kernel_of<3, 16, 512>(tangent, sn);
-        if (kmax == 16) return persistent_kernel_of<3, 16, 256>(tangent, sn);
-        return persistent_kernel_of<3, 32, 256>(tangent, sn);
+        if (tpb == 512) return persistent_kernel_of<3, 16, 512>(tangent, sn, ql);
+        if (kmax == 16) return persistent_kernel_of<3, 16, 256>(tangent, sn, ql);
+        return persistent_kernel_of<3, 32, 256>(tangent, sn, ql);
     }
     if (tpb == 512)
-        return ntr == 1 ? persistent_kernel_of<1, 16, 512>(tangent, sn) : persistent_kernel_of<2, 16, 512>(tangent, sn);
+        return ntr == 1 ? persistent_kernel_of<1, 16, 512>(tangent, sn, ql)
+                        : persistent_kernel_of<2, 16, 512>(tangent, sn, ql);
     if (kmax == 16)
-        return ntr == 1 ? persistent_kernel_of<1, 16, 256>(tangent, sn) : persistent_kernel_of<2, 16, 256>(tangent, sn);
-    return ntr == 1 ? persistent_kernel_of<1, 32, 256>(tangent, sn) : persistent_kernel_of<2, 32, 256>(tangent, sn);
+        return ntr == 1 ? persistent_kernel_of<1, 16, 256>(tangent, sn, ql)
+                        : persistent_kernel_of<2, 16, 256>(tangent, sn, ql);
+    return ntr == 1 ? persistent_kernel_of<1, 32, 256>(tangent, sn, ql) : persistent_kernel_of<2, 32, 256>(tangent, sn, ql);
 }
 
 template <int NTR, int KMAX, int TPB>
@@ -660,6 +669,8 @@ tmm::Persist persist_args(tmm_ctx* h) {
     ps.ahalo_ptr = h->at<int>(P.o_pahaloptr);
     ps.ahalo_row = h->at<int>(P.o_pahalo);
     ps.ahalo_max = h->pers_ahmax;
+    ps.qlat = h->at<int>(P.o_pqlat);
+    ps.qlat_max = h->pers_qmax;
     return ps;
 }
 
@@ -692,9 +703,11 @@ int launch_persistent(tmm_ctx* h, tmm::StepRange sr, const double* y, double* ou
     tmm::Persist ps = persist_args(h);
     double dtd = tmm::kDaysPerYear / P.nstep;
     void* args[] = {&g, &md, &mt, &ps, &sr, &dtd, &y, &out, &v, &vout};
-    TMM_TRY(hipLaunchCooperativeKernel(persistent_kernel(P.ntr, v != nullptr, h->pers_kmax, h->pers_tpb, persistent_sn(P)),
+    TMM_TRY(hipLaunchCooperativeKernel(persistent_kernel(P.ntr, v != nullptr, h->pers_kmax, h->pers_tpb, persistent_sn(P),
+                                                         h->pers_ql),
                                        dim3(h->pers_G), dim3(h->pers_tpb), args,
-                                       tmm::year_kernel_dyn_lds(h->pers_tpb, h->pers_hmax, P.ntr, v != nullptr),
+                                       tmm::year_kernel_dyn_lds(h->pers_tpb, h->pers_hmax, P.ntr, v != nullptr,
+                                                                h->pers_qmax, P.nstep),
                                        h->stream));
     h->pers_used = true;
     return TMM_OK;
@@ -831,6 +844,22 @@ int run_year(tmm_ctx* h, int nb, const double* y, double* out, double* a, double
     return TMM_OK;
 }
 
+// The largest dynamic LDS any handle on a device has needed of a kernel: the
+// attribute is a limit of the kernel, shared by every handle, so it only grows
+// (a handle never lowers it below what another one launches with).
+int ensure_dyn_lds(const void* fk, size_t dyn) {
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, size_t> granted;
+    int dev = 0;
+    TMM_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& cur = granted[{dev, fk}];
+    if (dyn <= cur) return TMM_OK;
+    TMM_TRY(hipFuncSetAttribute(fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+    cur = dyn;
+    return TMM_OK;
+}
+
 // Domains for the persistent kernel: contiguous runs of water columns with
 // about n/G rows each (at most the workgroup size), the domains each one must
 // wait for (both directions of every explicit-matrix coupling), and an
@@ -860,11 +889,11 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     TMM_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     for (int t = 0; t < 2; ++t) {
         const void* fk = persistent_kernel(P.ntr, t, h->pers_kmax, tpb, sn);
-        const size_t dyn = tmm::year_kernel_dyn_lds(tpb, (int)halo_cap, P.ntr, t);
+        const size_t dyn = tmm::year_kernel_dyn_lds(tpb, (int)halo_cap, P.ntr, t, 0, 0);
         hipFuncAttributes attr;
         TMM_TRY(hipFuncGetAttributes(&attr, fk));
         if (attr.sharedSizeBytes + dyn > (size_t)lds_max) return TMM_OK;
-        TMM_TRY(hipFuncSetAttribute(fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+        TMM_TRY(ensure_dyn_lds(fk, dyn));
         int o = 0;
         TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, fk, tpb, dyn));
         occ = t == 0 ? o : std::min(occ, o);
@@ -876,7 +905,7 @@ int build_persistent(tmm_ctx* h, int target_rows) {
         hipFuncAttributes attr;
         TMM_TRY(hipFuncGetAttributes(&attr, fa));
         if (attr.sharedSizeBytes + dyn <= (size_t)lds_max) {
-            if (dyn > 0) TMM_TRY(hipFuncSetAttribute(fa, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+            if (dyn > 0) TMM_TRY(ensure_dyn_lds(fa, dyn));
             TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_adj, fa, tpb, dyn));
         }
     }
@@ -965,6 +994,39 @@ int build_persistent(tmm_ctx* h, int target_rows) {
         std::fill(ahalo_ptr.begin(), ahalo_ptr.end(), 0);
     }
     if (ahalo.empty()) ahalo.push_back(0);
+    // latitude rows of each domain's columns: without internal BGC steps the
+    // forward kernels keep the insolation of those rows for the whole year in
+    // LDS beside their halo, where it fits (else they load it every step)
+    std::vector<int> qlat((size_t)G * (1 + tmm::kInsLat), 0);
+    int qmax = 0;
+    bool ql = sn == 0;
+    for (int q = 0; q < G && ql; ++q) {
+        int* e = qlat.data() + (size_t)q * (1 + tmm::kInsLat);
+        for (int c = dom[q]; c < dom[q + 1] && ql; ++c) {
+            const int l = P.col_lat[c];
+            bool seen = false;
+            for (int i = 0; i < e[0]; ++i) seen = seen || e[1 + i] == l;
+            if (seen) continue;
+            if (e[0] == tmm::kInsLat) ql = false;
+            else e[1 + e[0]++] = l;
+        }
+        qmax = std::max(qmax, e[0]);
+    }
+    for (int t = 0; t < 2 && ql; ++t) {
+        const void* fk = persistent_kernel(P.ntr, t, h->pers_kmax, tpb, sn, true);
+        const size_t dyn = tmm::year_kernel_dyn_lds(tpb, hmax, P.ntr, t, qmax, P.nstep);
+        hipFuncAttributes attr;
+        TMM_TRY(hipFuncGetAttributes(&attr, fk));
+        if (attr.sharedSizeBytes + dyn > (size_t)lds_max) {
+            ql = false;
+            break;
+        }
+        TMM_TRY(ensure_dyn_lds(fk, dyn));
+        int o = 0;
+        TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, fk, tpb, dyn));
+        if ((long long)ncu * o < G) ql = false;
+    }
+    if (!ql) qmax = 0;
     std::vector<int> block_dom(G);
     {
         int next = 0;
@@ -978,7 +1040,8 @@ int build_persistent(tmm_ctx* h, int target_rows) {
         upload(h, h->at<int>(P.o_phaloptr), halo_ptr.data(), halo_ptr.size() * 4) ||
         upload(h, h->at<int>(P.o_phalo), halo.data(), halo.size() * 4) ||
         upload(h, h->at<int>(P.o_pahaloptr), ahalo_ptr.data(), ahalo_ptr.size() * 4) ||
-        upload(h, h->at<int>(P.o_pahalo), ahalo.data(), ahalo.size() * 4))
+        upload(h, h->at<int>(P.o_pahalo), ahalo.data(), ahalo.size() * 4) ||
+        upload(h, h->at<int>(P.o_pqlat), qlat.data(), qlat.size() * 4))
         return TMM_EDEVICE;
     hipLaunchKernelGGL(tmm::k_fill_int, dim3(1), dim3(64), 0, h->stream, h->at<int>(P.o_pabort), 16, 0);
     TMM_LAUNCHED();
@@ -987,6 +1050,8 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     h->pers_tpb = tpb;
     h->pers_hmax = hmax;
     h->pers_ahmax = ahmax;
+    h->pers_qmax = qmax;
+    h->pers_ql = ql;
     h->pers_ok = true;
     h->pers_adj_ok = ahalo_ok && (long long)ncu * occ_adj >= G;
     return TMM_OK;

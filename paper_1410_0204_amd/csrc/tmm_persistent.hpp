@@ -91,11 +91,19 @@ struct Persist {
     const int* ahalo_ptr;   // the same for the transposed stencil of the reverse sweep
     const int* ahalo_row;
     int ahalo_max;
+    const int* qlat;        // [G][1 + kInsLat]: number of distinct latitude rows of the domain's
+                            // columns, then those rows (indices into the insolation table)
+    int qlat_max;           // largest such number over the domains
 };
 
-// Dynamic LDS of the forward kernel: own rows then halo rows, for y (and v).
-__host__ __device__ inline size_t year_kernel_dyn_lds(int tpb, int halo_max, int ntr, bool tangent) {
-    return (size_t)(tpb + halo_max) * ntr * 8 * (tangent ? 2 : 1);
+// Distinct latitude rows a domain may span for its insolation table in LDS.
+constexpr int kInsLat = 8;
+
+// Dynamic LDS of the forward kernel: own rows then halo rows, for y (and v),
+// then the insolation of the domain's latitude rows for every step of the year.
+__host__ __device__ inline size_t year_kernel_dyn_lds(int tpb, int halo_max, int ntr, bool tangent, int qlat_max,
+                                                      int nstep) {
+    return (size_t)(tpb + halo_max) * ntr * 8 * (tangent ? 2 : 1) + (size_t)qlat_max * nstep * 8;
 }
 
 // Steps j0 .. j1-1 of the year for one launch, with optional state storage
@@ -309,8 +317,9 @@ __device__ __forceinline__ void sub_adjoint_lds(const Grid& g, const Model& md, 
 // NTR tracers of one member; TANGENT also steps v = phi'(y) direction; TPB
 // threads per workgroup = maximum rows per domain; SN = 0 for one BGC
 // evaluation per step, else internal BGC steps with SN >= neu euphotic rows
-// held in registers.
-template <int NTR, bool TANGENT, int KMAX, int TPB, int SN = 0>
+// held in registers; QL: the insolation of the domain's latitude rows for the
+// whole year in LDS (else loaded from the global table every step).
+template <int NTR, bool TANGENT, int KMAX, int TPB, int SN = 0, bool QL = false>
 __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     Grid g, Model md, Mats mt, Persist ps, StepRange sr, double dtd, const double* __restrict__ y_in,
     double* __restrict__ y_out, const double* __restrict__ v_in, double* __restrict__ v_out) {
@@ -410,14 +419,33 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     }
     const int dep0 = ps.dep_ptr[d], ndep = ps.dep_ptr[d + 1] - dep0;
     int m0 = -1, m1 = -1;
+    // QL: the insolation of the domain's latitude rows at every step of the
+    // year, staged once: read from LDS, the sources of a step wait for no
+    // global memory operation (an insolation load carried from one step to the
+    // next made the compiler wait there for all outstanding memory operations,
+    // the previous step's write-through ring stores included)
+    const double* s_insq = nullptr;
+    if constexpr (QL) {
+        double* const s_ins = s_dyn + (size_t)(TPB + ps.halo_max) * NTR * (TANGENT ? 2 : 1);
+        const int* const dlat = ps.qlat + (size_t)d * (1 + kInsLat);
+        const int nq = dlat[0];
+        for (int i = tid; i < nq * g.nstep; i += blockDim.x) {
+            const int l = i / g.nstep, jx = i - l * g.nstep;
+            s_ins[i] = g.ins[(size_t)jx * g.nlat + dlat[1 + l]];
+        }
+        int ql = 0;
+        for (int l = 0; l < nq; ++l)
+            if (dlat[1 + l] == latrow) ql = l;
+        s_insq = s_ins + (size_t)ql * g.nstep;
+    }
     __syncthreads();
 
     const int nsteps = sr.j1 - sr.j0;
     const size_t state_len = (size_t)g.n * NTR;
     const int spm = g.nstep / g.nmat;
     const double vol = g.area[c] * g.dz[k];
-    // month pair, weight and insolation of the coming step, prepared at the end
-    // of the step before (off the neighbours' critical path); the month pair and
+    // month pair and weight of the coming step, prepared at the end of the
+    // step before (off the neighbours' critical path); the month pair and
     // the month-end counter advance by one step at a time, without divisions
     int k0, k1, pr_r, me_cnt;
     double w;
@@ -429,9 +457,10 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
         me_cnt = (sr.j0 + 1) % spm;
     }
     int jm = sr.j0 % g.nstep;
-    double Q = g.ins[(size_t)jm * g.nlat + latrow];
+    double Qg = QL ? 0.0 : g.ins[(size_t)jm * g.nlat + latrow];
     for (int jj = 0; jj < nsteps; ++jj) {
         const int j = sr.j0 + jj;
+        const double Q = QL ? s_insq[jm] : Qg;
         if (sr.store && own && jj % sr.store_every == 0) {
 #pragma unroll
             for (int t = 0; t < NTR; ++t)
@@ -518,13 +547,12 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             }
         }
 
-        // the coming step's insolation, loaded here (after this step's last use
-        // of Q, before the halo polls) rather than at the end of the step: the
-        // next step's sources begin with a wait for all outstanding global
-        // memory operations, and a load issued at the end of the step was still
-        // in flight there
+        // without the table, the coming step's insolation is loaded here
+        // (after this step's last use of it, before the halo polls) rather
+        // than at the end of the step, where it would still be in flight at the
+        // next step's sources
         const int jn = jm + 1 == g.nstep ? 0 : jm + 1;
-        const double Qn = g.ins[(size_t)jn * g.nlat + latrow];
+        const double Qn = QL ? 0.0 : g.ins[(size_t)jn * g.nlat + latrow];
 
         // hand-over every kRingK steps: publish the phase counter and wait for
         // the neighbours' counters
@@ -709,7 +737,7 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
         asm volatile("" : "+v"(w));
         me_cnt = me_cnt + 1 == spm ? 0 : me_cnt + 1;
         jm = jn;
-        Q = Qn;
+        Qg = Qn;
         __syncthreads();
         // month-end misfit partial sums (after publishing, off the neighbours' critical path)
         if (sr.obs && month_end) {

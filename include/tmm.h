@@ -222,8 +222,12 @@ enum {
     TMM_Q_DOMAINS = 2,      /* workgroups (column domains) of the persistent kernel */
     TMM_Q_WORKSPACE = 3,    /* workspace bytes in use */
     TMM_Q_COMPUTE_UNITS = 4, /* compute units of the device */
-    TMM_Q_PERSISTENT_ADJOINT = 5 /* 1 if single-member adjoints use the persistent reverse kernel (its
+    TMM_Q_PERSISTENT_ADJOINT = 5, /* 1 if single-member adjoints use the persistent reverse kernel (its
                                     store of internal BGC steps must fit the workgroup's LDS) */
+    TMM_Q_INSOLATION_LDS = 6 /* 1 if the persistent forward kernels hold the year's insolation of each
+                                domain's latitude rows in LDS (no internal BGC steps, at most 8 latitude
+                                rows per domain, and the table fits beside the halo); 0 if they load it
+                                every step */
 };
 
 /* Sets an execution option; results are the same either way up to rounding

@@ -1639,6 +1639,7 @@ int tmm_query(tmm_handle h, int what, long long* value) {
         case TMM_Q_PERSISTENT_ADJOINT:
             *value = (h->pers_ok && h->pers_adj_ok && h->P.etw <= tmm::kEllMax) ? 1 : 0;
             return TMM_OK;
+        case TMM_Q_INSOLATION_LDS: *value = (h->pers_ok && h->pers_ql) ? 1 : 0; return TMM_OK;
         default: return TMM_EINVAL;
     }
 }

@@ -45,6 +45,7 @@ TMM_Q_DOMAINS = 2
 TMM_Q_WORKSPACE = 3
 TMM_Q_COMPUTE_UNITS = 4
 TMM_Q_PERSISTENT_ADJOINT = 5
+TMM_Q_INSOLATION_LDS = 6
 
 EXPORTED = (
     "tmm_workspace_bytes", "tmm_create", "tmm_destroy", "tmm_set_params", "tmm_step", "tmm_year",

@@ -214,3 +214,31 @@ def test_member_kernel_rows_without_diagonal():
         got = t.step(j, t.state(y)).cpu().numpy()
         exp = o.step(U, j, y)
         assert pointwise(got, exp, 2, f"rows without diagonal, step {j}") <= STEP, j
+
+
+@pytest.mark.parametrize("grid", ["few_latitudes", "many_latitudes"])
+def test_persistent_insolation_table_and_its_fallback(grid):
+    """The persistent forward kernel holds the year's insolation of its domain's latitude rows in
+    LDS; a domain spanning more than 8 latitude rows (here: two columns per latitude row, one
+    domain) loads it every step instead.  Both against the oracle, forward year and tangent."""
+    tmm = _tmm()
+    if grid == "few_latitudes":
+        inp = synth.small_ndop()
+    else:
+        inp = synth.custom(nlon=2, nlat=40, nlayer=4, ncol=60, n=200, model=synth.MODEL_NDOP)
+    print(f"[gpu] insolation table, {grid}: n={inp.n}", flush=True)
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=1)
+    assert t.query(tmm.TMM_Q_PERSISTENT) == 1
+    assert t.query(tmm.TMM_Q_INSOLATION_LDS) == (1 if grid == "few_latitudes" else 0)
+    o = oracle.Oracle(inp)
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    rng = np.random.default_rng(46)
+    y = inp.initial_state() * rng.uniform(0.8, 1.2, size=(inp.n, 2))
+    got, _ = t.year(t.state(y))
+    exp, _ = o.year(u, y)
+    assert pointwise(got.cpu().numpy(), exp, 2, f"insolation {grid}, one year") <= YEAR
+    v = rng.standard_normal(y.shape) * y
+    phi, jv = t.year_jvp(t.state(y), t.state(v), mode=tmm.TMM_JVP_TANGENT)
+    ephi, ejv = o.year_tangent(u, y, v)
+    assert columnwise(jv.cpu().numpy(), ejv, 2, f"insolation {grid}, tangent") <= TANGENT

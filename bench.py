@@ -627,6 +627,9 @@ def bench_ensemble(args):
     U = synth.latin_hypercube(synth.MODEL_NDOP, nm, seed=17)
     L = synth.spinup_lengths(nm, seed=18)
     t = tmm.TMM(inp.desc_arrays(), nbatch_max=nm)
+    from paper_1410_0204_amd import autotune
+    tuned = autotune.apply_tuned(t, nm)     # the options below override it
+    log(f"[ensemble] launch configuration: {tuned['named'] if tuned else 'library defaults'}")
     if args.member_band is not None:
         t.set_option(tmm.TMM_OPT_MEMBER_BAND_ROWS, args.member_band)
     if args.member_waves is not None:
@@ -658,7 +661,10 @@ def bench_ensemble(args):
     torch.cuda.synchronize()
     ms_b = s.elapsed_time(e)
     member_years = int(L.sum())
-    # one-member runs: time one model year of member 0, extrapolate to all member-years
+    # one-member runs: time one model year of member 0 in its own tuned
+    # configuration, extrapolate to all member-years
+    autotune.apply(t, autotune.DEFAULTS)
+    autotune.apply_tuned(t, 1)
     t.set_params(U[0])
     y1 = t.state(inp.initial_state(1))
     t.year(y1, nyears=1, residuals=False)

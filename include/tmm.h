@@ -195,7 +195,8 @@ enum {
                                 0 = the default (256) */
     TMM_OPT_MEMBER_KERNEL_MIN = 3, /* forward steps of batches with at least this many members use the
                                      member-parallel kernel (one wavefront per water column, lane =
-                                     member); default 16; 0 = never */
+                                     member); default 6, about where it overtakes the tile kernel
+                                     on grids of 50k to 500k points; 0 = never */
     TMM_OPT_GRAPH = 4,           /* 1 (default): model years on the launch-per-step path are captured
                                     once per (members, buffers) into a hipGraph and replayed */
     TMM_OPT_SPIN_LIMIT = 5,      /* polls after which a wait of the persistent kernels gives up

@@ -42,7 +42,7 @@ TILE_ROWS = (32, 64, 128, 256)
 MEMBER_WAVES = (2, 4, 8)
 MEMBER_BANDS = (-1, 4, 8, 16, 32)
 
-DEFAULTS = {T.TMM_OPT_PERSISTENT: 1, T.TMM_OPT_DOMAIN_ROWS: 0, T.TMM_OPT_MEMBER_KERNEL_MIN: 16,
+DEFAULTS = {T.TMM_OPT_PERSISTENT: 1, T.TMM_OPT_DOMAIN_ROWS: 0, T.TMM_OPT_MEMBER_KERNEL_MIN: 6,
             T.TMM_OPT_GRAPH: 1, T.TMM_OPT_TILE_ROWS: 0, T.TMM_OPT_MEMBER_WAVES: 0, T.TMM_OPT_MEMBER_BAND_ROWS: 0}
 
 NAMES = {T.TMM_OPT_PERSISTENT: "persistent", T.TMM_OPT_DOMAIN_ROWS: "domain_rows",
@@ -73,7 +73,10 @@ def candidates(t, nbatch):
     if nbatch > 1 and t.ntracer <= 2:
         for waves in MEMBER_WAVES:
             for band in MEMBER_BANDS:
-                out.append({T.TMM_OPT_PERSISTENT: 0, T.TMM_OPT_MEMBER_KERNEL_MIN: 1,
+                # the member kernel at this width; narrower batches (members that
+                # finish early) keep the default crossover to the tile kernel
+                out.append({T.TMM_OPT_PERSISTENT: 0,
+                            T.TMM_OPT_MEMBER_KERNEL_MIN: min(DEFAULTS[T.TMM_OPT_MEMBER_KERNEL_MIN], nbatch),
                             T.TMM_OPT_MEMBER_WAVES: waves, T.TMM_OPT_MEMBER_BAND_ROWS: band})
     return out
 

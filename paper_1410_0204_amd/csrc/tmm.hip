@@ -346,7 +346,7 @@ struct tmm_ctx {
     int pers_ahmax = 0;            // ... of the transposed stencil
     int pers_qmax = 0;             // most latitude rows a domain spans (its insolation table in LDS)
     bool pers_ql = false;          // the forward kernels keep that table in LDS
-    int wide_min_members = 16;     // batches of at least this many members use k_step_members
+    int wide_min_members = 6;      // batches of at least this many members use k_step_members
     int mem_waves = tmm::kMembersWaves;   // option TMM_OPT_MEMBER_WAVES
     int mem_band = kDefaultBandRows;      // option TMM_OPT_MEMBER_BAND_ROWS (0: natural column order)
     int mem_blocks = 0;            // workgroups of one member-kernel launch (per member group)

@@ -115,7 +115,6 @@ struct Plan {
     int ntile_max = 0;
     // workspace offsets (bytes)
     size_t o_ae, o_aecol, o_aet, o_aetcol, o_aicm, o_airm, o_colstart, o_blk, o_lat, o_area, o_dz;
-    size_t o_aeself;           // per row: the ELL slot of Ae that reads the row itself
     std::vector<size_t> o_tiles;
     size_t o_u, o_light, o_rho, o_drho, o_member, o_scol, o_dcol;
     size_t o_uT, o_lightT, o_rhoT;   // member-fastest copies (member-parallel kernel)
@@ -203,9 +202,9 @@ int validate(const tmm_desc* d, Plan& P) {
     P.ntr = ntracer_of(d->model); P.nparam = nparam_of(d->model);
     P.npad = (d->n + 63) / 64 * 64;
     P.col_start.assign(d->col_start, d->col_start + d->ncol + 1);
-    // ELL width of Ae: every row gets a slot that reads the row itself (its
-    // diagonal entry, else a zero padding entry), so a row without a diagonal
-    // counts one more
+    // ELL width of Ae: slot 0 of every row reads the row itself (its diagonal
+    // entry, else a zero padding entry), so a row without a diagonal counts
+    // one more
     int ew = 0;
     std::vector<int> tcount(d->n, 0);
     for (int i = 0; i < d->n; ++i) {
@@ -236,7 +235,6 @@ int validate(const tmm_desc* d, Plan& P) {
     const size_t nm = d->nmat, npad = P.npad;
     P.o_ae = take(nm * P.ew * npad * 8);
     P.o_aecol = take((size_t)P.ew * npad * 4);
-    P.o_aeself = take((size_t)npad * 4);
     P.o_aet = take(nm * P.etw * npad * 8);
     P.o_aetcol = take((size_t)P.etw * npad * 4);
     P.o_aicm = take(nm * P.nblk * 8);
@@ -411,7 +409,6 @@ struct tmm_ctx {
         m.ai_month = P.nblk;
         m.ae = at<double>(P.o_ae);
         m.ae_col = at<int>(P.o_aecol);
-        m.ae_self = at<int>(P.o_aeself);
         m.aet = at<double>(P.o_aet);
         m.aet_col = at<int>(P.o_aetcol);
         m.ai_cm = at<double>(P.o_aicm);
@@ -509,7 +506,7 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
     const bool tangent = v != nullptr;
     const bool sub = h->P.nsub > 1;
     if (!tangent && nb >= h->wide_min_members && h->P.ntr <= 2 && h->P.nlayer <= 32 &&
-        h->P.ew <= tmm::kMembersEll) {
+        h->P.ew <= tmm::kMembersEll && (size_t)h->P.npad * W * 8 <= UINT32_MAX) {
         // member-parallel kernel: one wavefront per column and 64 members
         const int kmax = h->P.nlayer <= 16 ? 16 : h->P.nlayer <= 24 ? 24 : 32;
         const double dtd = tmm::kDaysPerYear / h->P.nstep;
@@ -1214,32 +1211,31 @@ int tmm_create(const tmm_desc* d, void* dev_workspace, size_t bytes, void* hip_s
     auto fail = [&](int code) { (void)hipStreamSynchronize(h->stream); delete h; return code; };
 
     // Ae in slot-major ELL; padding entries point at the row itself with value 0.
-    // self[i]: the slot of row i that reads row i (its diagonal entry, else the
-    // first padding entry; the width leaves one for every row without a diagonal).
+    // Slot 0 of row i reads row i: the row's entries in their given order, with
+    // the one that reads row i (its diagonal entry, else the first padding entry;
+    // the width leaves one for every row without a diagonal) swapped to the front.
     {
         std::vector<int> col((size_t)P.ew * P.npad);
         std::vector<int> pos(d->ae_nnz);
-        std::vector<int> self(P.npad, 0);
         for (int i = 0; i < P.npad; ++i) {
             const int len = i < P.n ? d->ae_rowptr[i + 1] - d->ae_rowptr[i] : 0;
-            int own = -1;
+            int own = i < P.n ? -1 : 0;
+            for (int s = 0; s < P.ew && own < 0; ++s)
+                if (s >= len || d->ae_colidx[d->ae_rowptr[i] + s] == i) own = s;
+            if (own < 0) return fail(TMM_EINVAL);
             for (int s = 0; s < P.ew; ++s) {
+                const int from = s == 0 ? own : s == own ? 0 : s;
                 const size_t at = (size_t)s * P.npad + i;
-                if (s < len) {
-                    const int e = d->ae_rowptr[i] + s;
+                if (from < len) {
+                    const int e = d->ae_rowptr[i] + from;
                     col[at] = d->ae_colidx[e];
                     pos[e] = (int)at;
-                    if (own < 0 && col[at] == i) own = s;
                 } else {
                     col[at] = i < P.n ? i : 0;
-                    if (own < 0 && i < P.n) own = s;
                 }
             }
-            if (i < P.n && own < 0) return fail(TMM_EINVAL);
-            self[i] = own < 0 ? 0 : own;
         }
         if (upload(h, h->at<int>(P.o_aecol), col.data(), col.size() * 4)) return fail(TMM_EDEVICE);
-        if (upload(h, h->at<int>(P.o_aeself), self.data(), self.size() * 4)) return fail(TMM_EDEVICE);
         std::vector<double> val((size_t)P.ew * P.npad);
         for (int m = 0; m < P.nmat; ++m) {
             std::fill(val.begin(), val.end(), 0.0);

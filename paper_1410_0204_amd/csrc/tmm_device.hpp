@@ -238,8 +238,7 @@ struct Mats {
     size_t aet_month;
     size_t ai_month;         // values per month of the block array
     const double* ae;        // [nmat][ew][npad]
-    const int* ae_col;       // [ew][npad]
-    const int* ae_self;      // [npad] the slot of each row that reads the row itself
+    const int* ae_col;       // [ew][npad]; slot 0 of every row reads the row itself
     const double* aet;       // [nmat][etw][npad]
     const int* aet_col;
     const double* ai_cm;     // [nmat][blocks] column-major blocks
@@ -728,7 +727,7 @@ __global__ __launch_bounds__(256) void k_step(Grid g, Model md, Mats mt, int W, 
 // Forward step for ensembles: one wavefront per water column and group of up
 // to 64 members, lane = member (both tracers).  Each wavefront first stages
 // the column's interpolated matrices in its own LDS slice with coalesced loads
-// (the Ai block, and the Ae rows: column indices and values), so that all
+// (the Ai block, and the Ae rows: row offsets and values), so that all
 // gathers of the state are independent and wave-uniform reads come from LDS.
 // A member's parameters, light factors and export Phi are evaluated once per
 // column; z of the column stays in registers (KMAX >= column depth).
@@ -755,7 +754,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
     // loop below runs to its compile-time bound without branches
     __shared__ double s_ai[WAVES][KMAX * KMAX];
     __shared__ double s_ae[WAVES][KMAX * EL];
-    __shared__ int s_col[WAVES][KMAX * EL];
+    __shared__ uint32_t s_off[WAVES][KMAX * EL];   // byte offset of the row each entry reads (< 2^32)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = blockIdx.x * WAVES + wave;
     const int craw = order ? order[slot] : (slot < ncol ? slot : -1);
@@ -820,7 +819,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
             const int col = mt.ae_col[e];
             const double v = om * ae0[e] + w * ae1[e];
             if (i < KMAX * EL) {
-                s_col[wave][i] = in ? col : rs;
+                s_off[wave][i] = (uint32_t)(in ? col : rs) * (uint32_t)(W * 8);
                 s_ae[wave][i] = in ? v : 0.0;
             }
         }
@@ -861,7 +860,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
         DF = deep_factors<NTR>(p, md.hsub, md.nsub);
     }
 
-    // z = Ae(t_j) y + dt_d q for every row of the column, in registers
+    // z = Ae(t_j) y + dt_d q for every row of the column, in registers.  Rows
+    // past the column's depth (k >= nc) repeat finite work on its rows and
+    // meet zero columns of the staged Ai block below.
+    // A gather is a 32-bit byte offset (the staged row offset plus the lane's
+    // member) on the state's base address.
+    const char* ybytes = reinterpret_cast<const char*>(y);
+    const uint32_t me8 = (uint32_t)me * 8u;
     double z[KMAX][NTR];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
@@ -869,7 +874,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
         double yv[EL][NTR];
 #pragma unroll
         for (int sl = 0; sl < EL; ++sl) {
-            const double* src = y + (size_t)s_col[wave][k * EL + sl] * W + me;
+            const double* src =
+                reinterpret_cast<const double*>(ybytes + (size_t)(s_off[wave][k * EL + sl] + me8));
             if constexpr (NTR == 2) {
                 // both tracers of a member in one 16-byte load (W is even, so the pair is aligned)
                 const double2 v = *reinterpret_cast<const double2*>(src);
@@ -880,14 +886,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
                 for (int t = 0; t < NTR; ++t) yv[sl][t] = src[t];
             }
         }
-        // the row's own DOP, from the stencil slot that reads the row itself
-        // (a wavefront-uniform index, so this is a select, not a load)
-        double dop = 0.0;
-        if constexpr (NTR > 1) {
-            const int own = mt.ae_self[rs + kk];
-#pragma unroll
-            for (int sl = 0; sl < EL; ++sl) dop = sl == own ? yv[sl][NTR - 1] : dop;
-        }
+        // the row's own DOP: slot 0 of every row reads the row itself
+        const double dop = NTR > 1 ? yv[0][NTR - 1] : 0.0;
         const double rho = rhoc[(size_t)kk * md.nbm];
         double acc[NTR];
 #pragma unroll
@@ -909,19 +909,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
                     for (int t = 0; t < NTR; ++t) src[t] = einc[e][t];
                 }
 #pragma unroll
-            for (int t = 0; t < NTR; ++t) z[k][t] = k < nc ? acc[t] + src[t] : 0.0;
+            for (int t = 0; t < NTR; ++t) z[k][t] = acc[t] + src[t];
         } else {
             double fk = 0.0;
 #pragma unroll
             for (int e = 0; e < NEU; ++e)
                 if (e == k) fk = f[e];
             const double q1 = -fk + p.lam * dop + (1.0 - p.sig) * Phi * rho;
-            const double z0 = acc[0] + dtd * q1;
-            z[k][0] = k < nc ? z0 : 0.0;
-            if (NTR > 1) {
-                const double z1 = acc[NTR - 1] + dtd * (p.sig * fk - p.lam * dop);
-                z[k][NTR - 1] = k < nc ? z1 : 0.0;
-            }
+            z[k][0] = acc[0] + dtd * q1;
+            if (NTR > 1) z[k][NTR - 1] = acc[NTR - 1] + dtd * (p.sig * fk - p.lam * dop);
         }
     }
 

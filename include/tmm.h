@@ -211,10 +211,16 @@ enum {
     TMM_OPT_MEMBER_BAND_ROWS = 8, /* latitude rows per band of the member-parallel kernel's column
                                     order (needs the descriptor's longitudes); 0 = the default (16),
                                     -1 = the natural column order */
-    TMM_OPT_TILE_ROWS = 9        /* largest tile (rows per workgroup) of the launch-per-step tile
+    TMM_OPT_TILE_ROWS = 9,       /* largest tile (rows per workgroup) of the launch-per-step tile
                                     kernels: 32, 64, 128 or 256 (a tiling no deeper than the
                                     deepest column is used as the smallest); 0 = by state width
                                     (128 up to 4 state columns, else 256) */
+    TMM_OPT_WAVE_LOCAL = 10      /* 1 (default): the persistent forward kernels place each water
+                                    column within one wavefront where the domains allow it (more,
+                                    smaller domains if needed), so that a time step needs one
+                                    workgroup barrier instead of three; 0: packed columns and
+                                    three barriers per step.  Rebuilds the domains; the results
+                                    are the same bit for bit */
 };
 
 /* Queries (tmm_query). */
@@ -225,10 +231,12 @@ enum {
     TMM_Q_COMPUTE_UNITS = 4, /* compute units of the device */
     TMM_Q_PERSISTENT_ADJOINT = 5, /* 1 if single-member adjoints use the persistent reverse kernel (its
                                     store of internal BGC steps must fit the workgroup's LDS) */
-    TMM_Q_INSOLATION_LDS = 6 /* 1 if the persistent forward kernels hold the year's insolation of each
+    TMM_Q_INSOLATION_LDS = 6, /* 1 if the persistent forward kernels hold the year's insolation of each
                                 domain's latitude rows in LDS (no internal BGC steps, at most 8 latitude
                                 rows per domain, and the table fits beside the halo); 0 if they load it
                                 every step */
+    TMM_Q_WAVE_LOCAL = 7     /* 1 if the persistent forward kernels run with wave-aligned water
+                                columns (option TMM_OPT_WAVE_LOCAL) */
 };
 
 /* Sets an execution option; results are the same either way up to rounding

@@ -134,6 +134,7 @@ struct Plan {
     size_t o_ring, o_vring;         // state rings of the persistent forward kernel (0: none)
     size_t o_phaloptr, o_phalo;     // halo rows of each domain
     size_t o_pqlat;                 // latitude rows of each domain (insolation table in LDS)
+    size_t o_pcolslot;              // first slot (thread) of each water column in its domain
     size_t o_pahaloptr, o_pahalo;   // ... for the transposed stencil (reverse sweep)
     size_t dep_capacity, halo_capacity;
     size_t total;
@@ -311,6 +312,7 @@ int validate(const tmm_desc* d, Plan& P) {
     P.o_pahaloptr = take((size_t)(kMaxDomains + 1) * 4);
     P.o_pahalo = take(P.halo_capacity * 4);
     P.o_pqlat = take((size_t)kMaxDomains * (1 + tmm::kInsLat) * 4);
+    P.o_pcolslot = take((size_t)d->ncol * 4);
     if (d->n <= kMaxPersistentRows) {
         P.o_ring = take((size_t)tmm::kRing * d->n * P.ntr * 8);
         P.o_vring = take((size_t)tmm::kRing * d->n * P.ntr * 8);
@@ -344,6 +346,9 @@ struct tmm_ctx {
     int pers_ahmax = 0;            // ... of the transposed stencil
     int pers_qmax = 0;             // most latitude rows a domain spans (its insolation table in LDS)
     bool pers_ql = false;          // the forward kernels keep that table in LDS
+    bool pers_wave_local = false;  // no water column spans two wavefronts of the forward kernels
+    bool wave_local_enabled = true;    // option TMM_OPT_WAVE_LOCAL
+    int pers_target = 0;           // option TMM_OPT_DOMAIN_ROWS as last set
     int wide_min_members = 6;      // batches of at least this many members use k_step_members
     int mem_waves = tmm::kMembersWaves;   // option TMM_OPT_MEMBER_WAVES
     int mem_band = kDefaultBandRows;      // option TMM_OPT_MEMBER_BAND_ROWS (0: natural column order)
@@ -668,6 +673,8 @@ tmm::Persist persist_args(tmm_ctx* h) {
     ps.ahalo_max = h->pers_ahmax;
     ps.qlat = h->at<int>(P.o_pqlat);
     ps.qlat_max = h->pers_qmax;
+    ps.col_slot = h->at<int>(P.o_pcolslot);
+    ps.wave_local = h->pers_wave_local ? 1 : 0;
     return ps;
 }
 
@@ -871,6 +878,7 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     h->num_cu = ncu;
     h->pers_ok = false;
     h->pers_adj_ok = false;
+    h->pers_target = target_rows;
     if (!coop || !P.o_ring || P.ew > tmm::kEllMax || P.nlayer > 32 || P.neu > tmm::kNeuMax) return TMM_OK;
     h->pers_kmax = P.nlayer <= 16 ? 16 : 32;
     if (target_rows < 1) target_rows = kDefaultDomainRows;
@@ -910,6 +918,20 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     if (maxG < 1) return TMM_OK;
     int G = std::min(maxG, std::max(1, (P.n + target_rows - 1) / target_rows));
     std::vector<int> dom;
+    // slots of a domain's columns with none spanning two wavefronts (a column
+    // that would starts the next one); returns the slots used
+    std::vector<int> col_slot(P.ncol, 0);
+    auto place = [&](int cb, int ce, bool wave_local) {
+        int slot = 0;
+        for (int c = cb; c < ce; ++c) {
+            const int nc = P.col_start[c + 1] - P.col_start[c];
+            if (wave_local && slot / 64 != (slot + nc - 1) / 64) slot = (slot / 64 + 1) * 64;
+            col_slot[c] = slot;
+            slot += nc;
+        }
+        return slot;
+    };
+    bool wave_local = false;
     for (;;) {
         dom.assign(1, 0);
         long long rows = 0;
@@ -919,14 +941,28 @@ int build_persistent(tmm_ctx* h, int target_rows) {
             if (rows >= target && (int)dom.size() < G && c + 1 < P.ncol) dom.push_back(c + 1);
         }
         dom.push_back(P.ncol);
-        int maxrows = 0;
-        for (size_t i = 0; i + 1 < dom.size(); ++i)
+        int maxrows = 0, maxslots = 0;
+        for (size_t i = 0; i + 1 < dom.size(); ++i) {
             maxrows = std::max(maxrows, P.col_start[dom[i + 1]] - P.col_start[dom[i]]);
-        if (maxrows <= tpb) break;
-        if (G >= maxG) return TMM_OK;                 // does not fit: per-step path only
+            maxslots = std::max(maxslots, place(dom[i], dom[i + 1], true));
+        }
+        // wave-aligned columns where the domains allow it (more, smaller
+        // domains if needed), else packed columns
+        if (h->wave_local_enabled && maxslots <= tpb) {
+            wave_local = true;
+            break;
+        }
+        if (G >= maxG || !h->wave_local_enabled) {
+            if (maxrows > tpb) {
+                if (G >= maxG) return TMM_OK;         // does not fit: per-step path only
+            } else {
+                break;
+            }
+        }
         G = std::min(maxG, G + std::max(1, G / 8));
     }
     G = (int)dom.size() - 1;
+    for (int q = 0; q < G; ++q) place(dom[q], dom[q + 1], wave_local);
     std::vector<int> row_dom(P.n);
     for (int q = 0; q < G; ++q)
         for (int r = P.col_start[dom[q]]; r < P.col_start[dom[q + 1]]; ++r) row_dom[r] = q;
@@ -1038,7 +1074,8 @@ int build_persistent(tmm_ctx* h, int target_rows) {
         upload(h, h->at<int>(P.o_phalo), halo.data(), halo.size() * 4) ||
         upload(h, h->at<int>(P.o_pahaloptr), ahalo_ptr.data(), ahalo_ptr.size() * 4) ||
         upload(h, h->at<int>(P.o_pahalo), ahalo.data(), ahalo.size() * 4) ||
-        upload(h, h->at<int>(P.o_pqlat), qlat.data(), qlat.size() * 4))
+        upload(h, h->at<int>(P.o_pqlat), qlat.data(), qlat.size() * 4) ||
+        upload(h, h->at<int>(P.o_pcolslot), col_slot.data(), col_slot.size() * 4))
         return TMM_EDEVICE;
     hipLaunchKernelGGL(tmm::k_fill_int, dim3(1), dim3(64), 0, h->stream, h->at<int>(P.o_pabort), 16, 0);
     TMM_LAUNCHED();
@@ -1049,6 +1086,7 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     h->pers_ahmax = ahmax;
     h->pers_qmax = qmax;
     h->pers_ql = ql;
+    h->pers_wave_local = wave_local;
     h->pers_ok = true;
     h->pers_adj_ok = ahalo_ok && (long long)ncu * occ_adj >= G;
     return TMM_OK;
@@ -1621,6 +1659,11 @@ int tmm_set_option(tmm_handle h, int option, int value) {
             if (hipStreamSynchronize(h->stream) != hipSuccess) return TMM_EDEVICE;
             return build_persistent(h, value);
         }
+        case TMM_OPT_WAVE_LOCAL: {
+            if (hipStreamSynchronize(h->stream) != hipSuccess) return TMM_EDEVICE;
+            h->wave_local_enabled = value != 0;
+            return build_persistent(h, h->pers_target);
+        }
         default: return TMM_EINVAL;
     }
 }
@@ -1636,6 +1679,7 @@ int tmm_query(tmm_handle h, int what, long long* value) {
             *value = (h->pers_ok && h->pers_adj_ok && h->P.etw <= tmm::kEllMax) ? 1 : 0;
             return TMM_OK;
         case TMM_Q_INSOLATION_LDS: *value = (h->pers_ok && h->pers_ql) ? 1 : 0; return TMM_OK;
+        case TMM_Q_WAVE_LOCAL: *value = (h->pers_ok && h->pers_wave_local) ? 1 : 0; return TMM_OK;
         default: return TMM_EINVAL;
     }
 }

@@ -94,16 +94,29 @@ struct Persist {
     const int* qlat;        // [G][1 + kInsLat]: number of distinct latitude rows of the domain's
                             // columns, then those rows (indices into the insolation table)
     int qlat_max;           // largest such number over the domains
+    const int* col_slot;    // [ncol] thread of the forward kernels that holds the first row of
+                            // each water column, within its domain's workgroup
+    int wave_local;         // 1: no water column spans two wavefronts (see k_year_persistent)
 };
 
 // Distinct latitude rows a domain may span for its insolation table in LDS.
 constexpr int kInsLat = 8;
 
 // Dynamic LDS of the forward kernel: own rows then halo rows, for y (and v),
-// then the insolation of the domain's latitude rows for every step of the year.
+// twice (states of even and odd steps), then the insolation of the domain's
+// latitude rows for every step of the year.
 __host__ __device__ inline size_t year_kernel_dyn_lds(int tpb, int halo_max, int ntr, bool tangent, int qlat_max,
                                                       int nstep) {
-    return (size_t)(tpb + halo_max) * ntr * 8 * (tangent ? 2 : 1) + (size_t)qlat_max * nstep * 8;
+    return (size_t)(tpb + halo_max) * ntr * 8 * 2 * (tangent ? 2 : 1) + (size_t)qlat_max * nstep * 8;
+}
+
+// LDS written by lanes of a wavefront and then read by other lanes of the
+// same wavefront: the LDS executes a wavefront's operations in order, so
+// this only keeps the compiler from moving them across.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Steps j0 .. j1-1 of the year for one launch, with optional state storage
@@ -319,6 +332,17 @@ __device__ __forceinline__ void sub_adjoint_lds(const Grid& g, const Model& md, 
 // evaluation per step, else internal BGC steps with SN >= neu euphotic rows
 // held in registers; QL: the insolation of the domain's latitude rows for the
 // whole year in LDS (else loaded from the global table every step).
+//
+// Thread t of a workgroup holds the row at slot t of its domain: the host
+// places each water column at a start slot (ps.col_slot).  With
+// ps.wave_local, no column spans two wavefronts (a column that would is moved
+// to the next wavefront's first slot), so the column product and the sources,
+// which read only rows of the thread's own column, need no workgroup barrier:
+// per step one barrier (after the halo has arrived) remains, and the LDS
+// state alternates between two buffers (state j in buffer j % 2) so that a
+// wavefront that has finished step j may write state j + 1 while another
+// still reads state j.  Without it the columns are packed and two more
+// workgroup barriers per step order the same accesses.
 template <int NTR, bool TANGENT, int KMAX, int TPB, int SN = 0, bool QL = false>
 __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     Grid g, Model md, Mats mt, Persist ps, StepRange sr, double dtd, const double* __restrict__ y_in,
@@ -326,39 +350,46 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     constexpr int TV = TANGENT ? NTR : 1;
     constexpr bool SUB = SN > 0;
     __shared__ double s_red[TPB];
-    __shared__ short s_rowcol[TPB];
+    __shared__ short s_rowcol[TPB];      // per slot: the domain's column held there (-1: none)
     __shared__ short s_rowk[TPB];
-    __shared__ short s_colr0[TPB];
+    __shared__ short s_rowslot[TPB];     // per row of the domain (from its first): its slot
+    __shared__ short s_colr0[TPB];       // per column of the domain: its first slot
     __shared__ short s_colnc[TPB];
     __shared__ double s_z[TPB * NTR];
     __shared__ double s_zd[TPB * TV];
     __shared__ int s_fail;
-    // own rows [0, TPB) and halo rows [TPB, TPB + halo_max) of y (and v)
+    // per buffer: own slots [0, TPB) and halo rows [TPB, TPB + halo_max) of y (and v)
     extern __shared__ double s_dyn[];
-    double* const s_y = s_dyn;
-    double* const s_v = s_dyn + (size_t)(TPB + ps.halo_max) * NTR;
+    const size_t buf_len = (size_t)(TPB + ps.halo_max) * NTR;
+    double* const s_y0 = s_dyn;
+    double* const s_v0 = s_dyn + 2 * buf_len;
+    const bool wave_local = ps.wave_local != 0;
 
     const int tid = threadIdx.x;
     const int d = ps.block_dom[blockIdx.x];
     const int c0 = ps.dom_col[d], c1 = ps.dom_col[d + 1];
     const int r0 = g.col_start[c0];
     const int nrows = g.col_start[c1] - r0;
+    for (int i = tid; i < TPB; i += blockDim.x) s_rowcol[i] = -1;
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
     for (int lc = tid; lc < c1 - c0; lc += blockDim.x) {
-        const int s = g.col_start[c0 + lc] - r0;
+        const int s = ps.col_slot[c0 + lc];
+        const int lrow = g.col_start[c0 + lc] - r0;
         const int nc = g.col_start[c0 + lc + 1] - g.col_start[c0 + lc];
         s_colr0[lc] = (short)s;
         s_colnc[lc] = (short)nc;
         for (int k = 0; k < nc; ++k) {
             s_rowcol[s + k] = (short)lc;
             s_rowk[s + k] = (short)k;
+            s_rowslot[lrow + k] = (short)(s + k);
         }
     }
-    if (tid == 0) s_fail = 0;
     __syncthreads();
 
-    const bool own = tid < nrows;
-    const int r = r0 + (own ? tid : 0);
+    const bool own = s_rowcol[tid] >= 0;
     const int lc = own ? s_rowcol[tid] : 0;
+    const int r = own ? g.col_start[c0 + lc] + s_rowk[tid] : r0;
     const int k = own ? s_rowk[tid] : 0;
     const int nc = own ? s_colnc[lc] : 1;
     const int lr0 = own ? s_colr0[lc] : 0;
@@ -387,7 +418,7 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     for (int s = 0; s < kEllMax; ++s) {
         const int cg = s < mt.ew ? mt.ae_col[(size_t)s * g.npad + r] : r;
         if ((unsigned)(cg - r0) < (unsigned)nrows) {
-            R.col[s] = cg - r0;
+            R.col[s] = s_rowslot[cg - r0];
         } else {
             int lo = 0, hi = nh - 1;
             while (lo < hi) {
@@ -411,10 +442,10 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
 #pragma unroll
     for (int t = 0; t < NTR; ++t) {
         yr[t] = own ? y_in[(size_t)r * NTR + t] : 0.0;
-        s_y[tid * NTR + t] = yr[t];
+        s_y0[tid * NTR + t] = yr[t];
         if (TANGENT) {
             vr[t % TV] = own ? v_in[(size_t)r * NTR + t] : 0.0;
-            s_v[tid * TV + t % TV] = vr[t % TV];
+            s_v0[tid * TV + t % TV] = vr[t % TV];
         }
     }
     const int dep0 = ps.dep_ptr[d], ndep = ps.dep_ptr[d + 1] - dep0;
@@ -426,7 +457,7 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     // the previous step's write-through ring stores included)
     const double* s_insq = nullptr;
     if constexpr (QL) {
-        double* const s_ins = s_dyn + (size_t)(TPB + ps.halo_max) * NTR * (TANGENT ? 2 : 1);
+        double* const s_ins = s_dyn + 2 * buf_len * (TANGENT ? 2 : 1);
         const int* const dlat = ps.qlat + (size_t)d * (1 + kInsLat);
         const int nq = dlat[0];
         for (int i = tid; i < nq * g.nstep; i += blockDim.x) {
@@ -461,6 +492,13 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     for (int jj = 0; jj < nsteps; ++jj) {
         const int j = sr.j0 + jj;
         const double Q = QL ? s_insq[jm] : Qg;
+        // state jj in buffer jj % 2 (both buffers alike without wave_local)
+        const size_t cur = wave_local ? (size_t)(jj & 1) * buf_len : 0;
+        const size_t nxt = wave_local ? (size_t)((jj + 1) & 1) * buf_len : 0;
+        double* const s_y = s_y0 + cur;
+        double* const s_v = s_v0 + cur;          // (used with TANGENT only, where TV = NTR)
+        double* const s_yn = s_y0 + nxt;
+        double* const s_vn = s_v0 + nxt;
         if (sr.store && own && jj % sr.store_every == 0) {
 #pragma unroll
             for (int t = 0; t < NTR; ++t)
@@ -559,6 +597,10 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
         if (jj % kRingK == 0) {
             const int ph = jj / kRingK;
             if (ph > 0) {
+                // every thread's ring stores of the phase (the sentinel resets of
+                // slots its neighbours read in the next phase included) before
+                // the counter
+                __syncthreads();
                 if (tid == 0) __hip_atomic_store(&ps.flags[d], ph, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 for (int qi = tid; qi < ndep; qi += blockDim.x) {
                     const int e = ps.dep_idx[dep0 + qi];
@@ -670,7 +712,8 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
                 if (TANGENT) s_zd[tid * TV + t % TV] = accd[t % TV] + sc * qd[t % TV];
             }
         }
-        __syncthreads();
+        if (wave_local) wave_lds_sync();       // the column's z: written by this wavefront
+        else __syncthreads();
 
         // y_{j+1} = Ai(t_j) z, within the water column
         const bool last = jj == nsteps - 1;
@@ -696,7 +739,7 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
 #pragma unroll
             for (int t = 0; t < NTR; ++t) {
                 yr[t] = acc[t];
-                s_y[tid * NTR + t] = acc[t];
+                s_yn[tid * NTR + t] = acc[t];
                 // agent-scope stores write through the XCD's L2 to the point
                 // where every domain's loads see them
                 if (last) y_out[(size_t)r * NTR + t] = acc[t];
@@ -704,7 +747,7 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
                                         __HIP_MEMORY_SCOPE_AGENT);
                 if (TANGENT) {
                     vr[t % TV] = accd[t % TV];
-                    s_v[tid * TV + t % TV] = accd[t % TV];
+                    s_vn[tid * TV + t % TV] = accd[t % TV];
                     if (last) v_out[(size_t)r * NTR + t] = accd[t % TV];
                     else __hip_atomic_store(&ps.vring[ring_at(wb, g.n, r, t)], publishable(accd[t % TV]),
                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -738,7 +781,10 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
         me_cnt = me_cnt + 1 == spm ? 0 : me_cnt + 1;
         jm = jn;
         Qg = Qn;
-        __syncthreads();
+        // the next step's sources read the new state of the thread's own
+        // column; its neighbours' rows are read after the next halo barrier
+        if (wave_local) wave_lds_sync();
+        else __syncthreads();
         // month-end misfit partial sums (after publishing, off the neighbours' critical path)
         if (sr.obs && month_end) {
             const int mo = (j + 1) / spm - 1;

@@ -40,12 +40,14 @@ TMM_OPT_CHECK_FINITE = 6
 TMM_OPT_MEMBER_WAVES = 7
 TMM_OPT_MEMBER_BAND_ROWS = 8
 TMM_OPT_TILE_ROWS = 9
+TMM_OPT_WAVE_LOCAL = 10
 TMM_Q_PERSISTENT = 1
 TMM_Q_DOMAINS = 2
 TMM_Q_WORKSPACE = 3
 TMM_Q_COMPUTE_UNITS = 4
 TMM_Q_PERSISTENT_ADJOINT = 5
 TMM_Q_INSOLATION_LDS = 6
+TMM_Q_WAVE_LOCAL = 7
 
 EXPORTED = (
     "tmm_workspace_bytes", "tmm_create", "tmm_destroy", "tmm_set_params", "tmm_step", "tmm_year",

@@ -242,3 +242,34 @@ def test_persistent_insolation_table_and_its_fallback(grid):
     phi, jv = t.year_jvp(t.state(y), t.state(v), mode=tmm.TMM_JVP_TANGENT)
     ephi, ejv = o.year_tangent(u, y, v)
     assert columnwise(jv.cpu().numpy(), ejv, 2, f"insolation {grid}, tangent") <= TANGENT
+
+
+def test_persistent_wave_aligned_and_packed_columns():
+    """The persistent forward kernels place every water column within one wavefront (one workgroup
+    barrier per step, the LDS state alternating between two buffers) or, with the option off, pack
+    the columns (three barriers per step).  Same arithmetic per row: both layouts give the same
+    year and tangent bit for bit, and both match the oracle."""
+    tmm = _tmm()
+    inp = synth.small_ndop()
+    print(f"[gpu] wave-aligned and packed columns: n={inp.n}", flush=True)
+    t = tmm.TMM(inp.desc_arrays(), nbatch_max=1)
+    o = oracle.Oracle(inp)
+    u = synth.nominal(inp.model)
+    t.set_params(u)
+    rng = np.random.default_rng(47)
+    y = inp.initial_state() * rng.uniform(0.8, 1.2, size=(inp.n, 2))
+    v = rng.standard_normal(y.shape) * y
+    exp, _ = o.year(u, y)
+    ephi, ejv = o.year_tangent(u, y, v)
+    out = {}
+    for wl in (1, 0):
+        t.set_option(tmm.TMM_OPT_WAVE_LOCAL, wl)
+        assert t.query(tmm.TMM_Q_PERSISTENT) == 1
+        assert t.query(tmm.TMM_Q_WAVE_LOCAL) == wl
+        got, _ = t.year(t.state(y))
+        phi, jv = t.year_jvp(t.state(y), t.state(v), mode=tmm.TMM_JVP_TANGENT)
+        got, jv = got.cpu().numpy(), jv.cpu().numpy()
+        assert pointwise(got, exp, 2, f"columns wave_local={wl}, one year") <= YEAR
+        assert columnwise(jv, ejv, 2, f"columns wave_local={wl}, tangent") <= TANGENT
+        out[wl] = (got, jv)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])

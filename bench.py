@@ -132,13 +132,16 @@ def latency_floor(t, us_per_step):
     """Per-step floor of the single-launch year kernel from the primitives it
     chains in every step, measured on this device: one hand-over of a value
     to another workgroup (half a store-and-poll round trip, the slower of
-    same-XCD and cross-XCD pairs: every step has both) and three workgroup
-    barriers."""
+    same-XCD and cross-XCD pairs: every step has both) and the step's
+    workgroup barriers (one with wave-aligned water columns, else three)."""
+    from paper_1410_0204_amd import tmm
     p = t.probe_exchange(2000)
+    nbar = 1 if t.query(tmm.TMM_Q_WAVE_LOCAL) else 3
     hop = 0.5 * max(p["round_trip_same_xcd_us"], p["round_trip_cross_xcd_us"])
-    floor = hop + 3.0 * p["barrier_us"]
-    p.update({"hop_us": hop, "floor_us_per_step": floor, "floor_over_step": floor / us_per_step,
-              "model": "one hand-over of the state (half a round trip) + 3 workgroup barriers per step"})
+    floor = hop + nbar * p["barrier_us"]
+    p.update({"hop_us": hop, "barriers_per_step": nbar, "floor_us_per_step": floor,
+              "floor_over_step": floor / us_per_step,
+              "model": f"one hand-over of the state (half a round trip) + {nbar} workgroup barrier(s) per step"})
     log(f"[bench] exchange probe: round trip {p['round_trip_same_xcd_us']:.3f} us (same XCD), "
         f"{p['round_trip_cross_xcd_us']:.3f} us (across XCDs), barrier {p['barrier_us']:.4f} us, "
         f"agent load {p['agent_load_us']:.3f} us -> floor {floor:.3f} us per step ({floor / us_per_step:.2f} of it)")

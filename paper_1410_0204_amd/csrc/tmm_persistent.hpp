@@ -355,8 +355,14 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     __shared__ short s_rowslot[TPB];     // per row of the domain (from its first): its slot
     __shared__ short s_colr0[TPB];       // per column of the domain: its first slot
     __shared__ short s_colnc[TPB];
-    __shared__ double s_z[TPB * NTR];
-    __shared__ double s_zd[TPB * TV];
+    // z (and its tangent) of the own slots; without internal steps with zero
+    // rows past the domain: the column product then reads KMAX rows from the
+    // column's first slot with fixed offsets, and the rows past the column's
+    // depth (other columns, padding slots or the zero rows) meet zero
+    // coefficients
+    constexpr int ZPAD = SUB ? 0 : KMAX;
+    __shared__ double s_z[(TPB + ZPAD) * NTR];
+    __shared__ double s_zd[(TPB + ZPAD) * TV];
     __shared__ int s_fail;
     // per buffer: own slots [0, TPB) and halo rows [TPB, TPB + halo_max) of y (and v)
     extern __shared__ double s_dyn[];
@@ -371,6 +377,10 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
     const int r0 = g.col_start[c0];
     const int nrows = g.col_start[c1] - r0;
     for (int i = tid; i < TPB; i += blockDim.x) s_rowcol[i] = -1;
+    if constexpr (!SUB) {
+        for (int i = tid; i < (TPB + ZPAD) * NTR; i += blockDim.x) s_z[i] = 0.0;
+        for (int i = tid; i < (TPB + ZPAD) * TV; i += blockDim.x) s_zd[i] = 0.0;
+    }
     if (tid == 0) s_fail = 0;
     __syncthreads();
     for (int lc = tid; lc < c1 - c0; lc += blockDim.x) {
@@ -724,16 +734,54 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
             for (int t = 0; t < NTR; ++t) acc[t] = 0.0;
 #pragma unroll
             for (int t = 0; t < TV; ++t) accd[t] = 0.0;
-            // coefficients beyond the column depth are zero; the clamped LDS index
-            // keeps the loop free of branches
+            // coefficients beyond the column depth are zero, and so is every
+            // product with the (finite) rows read there.  How the KMAX rows are
+            // read is chosen per instance (same-box timings of each): one base
+            // address with fixed offsets, all reads issued before the first
+            // product for one or two tracers, interleaved with the products for
+            // PO4-DOP-PHY; with internal BGC steps (whose sources hold more
+            // registers) a row index clamped to the column
+            [[maybe_unused]] const double* const zc = s_z + (size_t)lr0 * NTR;
+            [[maybe_unused]] const double* const zdc = s_zd + (size_t)lr0 * TV;
+            if constexpr (!SUB && NTR <= 2) {
+                double zz[KMAX][NTR], zzd[KMAX][TV];
 #pragma unroll
-            for (int s = 0; s < KMAX; ++s) {
-                const double a = om * R.a0[s] + w * R.a1[s];
-                const int ls = lr0 + (s < nc ? s : nc - 1);
+                for (int s = 0; s < KMAX; ++s)
 #pragma unroll
-                for (int t = 0; t < NTR; ++t) {
-                    acc[t] += a * s_z[ls * NTR + t];
-                    if (TANGENT) accd[t % TV] += a * s_zd[ls * TV + t % TV];
+                    for (int t = 0; t < NTR; ++t) {
+                        zz[s][t] = zc[s * NTR + t];
+                        if (TANGENT) zzd[s][t % TV] = zdc[s * TV + t % TV];
+                    }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int s = 0; s < KMAX; ++s) {
+                    const double a = om * R.a0[s] + w * R.a1[s];
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) {
+                        acc[t] += a * zz[s][t];
+                        if (TANGENT) accd[t % TV] += a * zzd[s][t % TV];
+                    }
+                }
+            } else if constexpr (!SUB) {
+#pragma unroll
+                for (int s = 0; s < KMAX; ++s) {
+                    const double a = om * R.a0[s] + w * R.a1[s];
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) {
+                        acc[t] += a * zc[s * NTR + t];
+                        if (TANGENT) accd[t % TV] += a * zdc[s * TV + t % TV];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < KMAX; ++s) {
+                    const double a = om * R.a0[s] + w * R.a1[s];
+                    const int ls = lr0 + (s < nc ? s : nc - 1);
+#pragma unroll
+                    for (int t = 0; t < NTR; ++t) {
+                        acc[t] += a * s_z[ls * NTR + t];
+                        if (TANGENT) accd[t % TV] += a * s_zd[ls * TV + t % TV];
+                    }
                 }
             }
 #pragma unroll

@@ -707,6 +707,9 @@ __global__ __launch_bounds__(TPB, 1) void k_year_persistent(
                     yy[s][t] = s_y[R.col[s] * NTR + t];
                     if (TANGENT) vv[s][t % TV] = s_v[R.col[s] * TV + t % TV];
                 }
+            // one or two tracers without internal steps: every gather issued
+            // before the first multiply (the compiler kept four in flight)
+            if constexpr (!SUB && NTR <= 2) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int s = 0; s < kEllMax; ++s) {
                 const double a = om * R.e0[s] + w * R.e1[s];

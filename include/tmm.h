@@ -231,10 +231,11 @@ enum {
     TMM_Q_COMPUTE_UNITS = 4, /* compute units of the device */
     TMM_Q_PERSISTENT_ADJOINT = 5, /* 1 if single-member adjoints use the persistent reverse kernel (its
                                     store of internal BGC steps must fit the workgroup's LDS) */
-    TMM_Q_INSOLATION_LDS = 6, /* 1 if the persistent forward kernels hold the year's insolation of each
-                                domain's latitude rows in LDS (no internal BGC steps, at most 8 latitude
-                                rows per domain, and the table fits beside the halo); 0 if they load it
-                                every step */
+    TMM_Q_INSOLATION_LDS = 6, /* 1 if the persistent forward kernel (state only) holds the year's
+                                insolation of each domain's latitude rows in LDS (no internal BGC steps,
+                                at most 8 latitude rows per domain, and the table fits beside the halo
+                                with every domain resident); 0 if it loads it every step.  The tangent
+                                kernel decides the same on its own, larger LDS */
     TMM_Q_WAVE_LOCAL = 7     /* 1 if the persistent forward kernels run with wave-aligned water
                                 columns (option TMM_OPT_WAVE_LOCAL) */
 };

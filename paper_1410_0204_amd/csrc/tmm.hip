@@ -345,7 +345,8 @@ struct tmm_ctx {
     int pers_hmax = 0;             // largest domain halo (rows)
     int pers_ahmax = 0;            // ... of the transposed stencil
     int pers_qmax = 0;             // most latitude rows a domain spans (its insolation table in LDS)
-    bool pers_ql = false;          // the forward kernels keep that table in LDS
+    bool pers_ql[2] = {false, false};   // the forward kernels keep that table in LDS (state
+                                        // only, with the tangent)
     bool pers_wave_local = false;  // no water column spans two wavefronts of the forward kernels
     bool wave_local_enabled = true;    // option TMM_OPT_WAVE_LOCAL
     int pers_target = 0;           // option TMM_OPT_DOMAIN_ROWS as last set
@@ -707,11 +708,12 @@ int launch_persistent(tmm_ctx* h, tmm::StepRange sr, const double* y, double* ou
     tmm::Persist ps = persist_args(h);
     double dtd = tmm::kDaysPerYear / P.nstep;
     void* args[] = {&g, &md, &mt, &ps, &sr, &dtd, &y, &out, &v, &vout};
+    const bool ql = h->pers_ql[v != nullptr ? 1 : 0];
     TMM_TRY(hipLaunchCooperativeKernel(persistent_kernel(P.ntr, v != nullptr, h->pers_kmax, h->pers_tpb, persistent_sn(P),
-                                                         h->pers_ql),
+                                                         ql),
                                        dim3(h->pers_G), dim3(h->pers_tpb), args,
                                        tmm::year_kernel_dyn_lds(h->pers_tpb, h->pers_hmax, P.ntr, v != nullptr,
-                                                                h->pers_qmax, P.nstep),
+                                                                ql ? h->pers_qmax : 0, P.nstep),
                                        h->stream));
     h->pers_used = true;
     return TMM_OK;
@@ -1045,21 +1047,24 @@ int build_persistent(tmm_ctx* h, int target_rows) {
         }
         qmax = std::max(qmax, e[0]);
     }
+    // decided per mode: the tangent's larger LDS may not leave room for the
+    // table (or for the co-residency of all domains) where the state's does
+    bool ql_mode[2] = {ql, ql};
     for (int t = 0; t < 2 && ql; ++t) {
         const void* fk = persistent_kernel(P.ntr, t, h->pers_kmax, tpb, sn, true);
         const size_t dyn = tmm::year_kernel_dyn_lds(tpb, hmax, P.ntr, t, qmax, P.nstep);
         hipFuncAttributes attr;
         TMM_TRY(hipFuncGetAttributes(&attr, fk));
         if (attr.sharedSizeBytes + dyn > (size_t)lds_max) {
-            ql = false;
-            break;
+            ql_mode[t] = false;
+            continue;
         }
         TMM_TRY(ensure_dyn_lds(fk, dyn));
         int o = 0;
         TMM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, fk, tpb, dyn));
-        if ((long long)ncu * o < G) ql = false;
+        if ((long long)ncu * o < G) ql_mode[t] = false;
     }
-    if (!ql) qmax = 0;
+    if (!ql_mode[0] && !ql_mode[1]) qmax = 0;
     std::vector<int> block_dom(G);
     {
         int next = 0;
@@ -1085,7 +1090,8 @@ int build_persistent(tmm_ctx* h, int target_rows) {
     h->pers_hmax = hmax;
     h->pers_ahmax = ahmax;
     h->pers_qmax = qmax;
-    h->pers_ql = ql;
+    h->pers_ql[0] = ql_mode[0];
+    h->pers_ql[1] = ql_mode[1];
     h->pers_wave_local = wave_local;
     h->pers_ok = true;
     h->pers_adj_ok = ahalo_ok && (long long)ncu * occ_adj >= G;
@@ -1678,7 +1684,7 @@ int tmm_query(tmm_handle h, int what, long long* value) {
         case TMM_Q_PERSISTENT_ADJOINT:
             *value = (h->pers_ok && h->pers_adj_ok && h->P.etw <= tmm::kEllMax) ? 1 : 0;
             return TMM_OK;
-        case TMM_Q_INSOLATION_LDS: *value = (h->pers_ok && h->pers_ql) ? 1 : 0; return TMM_OK;
+        case TMM_Q_INSOLATION_LDS: *value = (h->pers_ok && h->pers_ql[0]) ? 1 : 0; return TMM_OK;
         case TMM_Q_WAVE_LOCAL: *value = (h->pers_ok && h->pers_wave_local) ? 1 : 0; return TMM_OK;
         default: return TMM_EINVAL;
     }

@@ -555,20 +555,33 @@ def bench_grids(args):
             torch.cuda.synchronize()
             us_step = s.elapsed_time(e) * 1000.0 / args.grid_steps
             ms = us_step * inp.nstep / 1000.0
+            tiles = {"default": (ms, us_step)}
         else:
-            t.year(y0, nyears=1, out=ya, residuals=False)
-            torch.cuda.synchronize()
-            years = 2
-            s.record(stream)
-            t.year(y0, nyears=years, out=ya, residuals=False)
-            e.record(stream)
-            torch.cuda.synchronize()
-            ms = s.elapsed_time(e) / years
-            us_step = ms * 1000.0 / inp.nstep
+            # the default tiling (by state width), then every tile size of the kernel
+            tiles = {}
+            for rows_opt in (0, 32, 64, 128, 256):
+                t.set_option(tmm.TMM_OPT_TILE_ROWS, rows_opt)
+                t.year(y0, nyears=1, out=ya, residuals=False)
+                torch.cuda.synchronize()
+                years = 2
+                s.record(stream)
+                t.year(y0, nyears=years, out=ya, residuals=False)
+                e.record(stream)
+                torch.cuda.synchronize()
+                ms_t = s.elapsed_time(e) / years
+                tiles["default" if rows_opt == 0 else f"tile_rows_{rows_opt}"] = (ms_t, ms_t * 1000.0 / inp.nstep)
+            ms, us_step = tiles["default"]
+        best = min(tiles, key=lambda k: tiles[k][0])
+        ms_b, us_b = tiles[best]
         rec = {"workload": inp.name, "n": inp.n, "nnz_explicit": inp.tm.ae_nnz, "nnz_implicit": inp.tm.ai_nnz,
                "bytes_per_step": B, "ms_per_year": ms, "model_years_per_s": 1000.0 / ms, "us_per_step": us_step,
-               "GB_per_s": B / (us_step * 1e-6) / 1e9, "frac_of_peak": B / (us_step * 1e-6) / 1e9 / HBM_PEAK_GBPS}
-        log(f"[bench] {inp.name}: {ms:.2f} ms/model-year, {us_step:.1f} us/step, {rec['GB_per_s']:.0f} GB/s")
+               "GB_per_s": B / (us_step * 1e-6) / 1e9, "frac_of_peak": B / (us_step * 1e-6) / 1e9 / HBM_PEAK_GBPS,
+               "best_tiling": best, "best_ms_per_year": ms_b, "best_us_per_step": us_b,
+               "best_GB_per_s": B / (us_b * 1e-6) / 1e9, "best_frac_of_peak": B / (us_b * 1e-6) / 1e9 / HBM_PEAK_GBPS,
+               "ms_per_year_by_tiling": {k: v[0] for k, v in tiles.items()}}
+        log(f"[bench] {inp.name}: {ms:.2f} ms/model-year, {us_step:.1f} us/step, {rec['GB_per_s']:.0f} GB/s "
+            f"(default tiling); best {best}: {ms_b:.2f} ms/model-year, {us_b:.1f} us/step, "
+            f"{rec['best_GB_per_s']:.0f} GB/s ({100 * rec['best_frac_of_peak']:.0f} % of peak)")
         rows.append(rec)
         t.close()
         del t

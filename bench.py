@@ -264,6 +264,8 @@ def main():
                     help="ensemble mode: latitude rows per band of the member kernel's column order (-1: natural)")
     ap.add_argument("--member-waves", type=int, default=None,
                     help="ensemble mode: wavefronts per workgroup of the member kernel")
+    ap.add_argument("--member-tile", type=int, default=None,
+                    help="ensemble mode: columns per workgroup of the tiled member kernel (0: off)")
     ap.add_argument("--forward-only", action="store_true",
                     help="skip the per-step comparison and the adjoint (for hardware counter runs)")
     args = ap.parse_args()
@@ -650,6 +652,8 @@ def bench_ensemble(args):
         t.set_option(tmm.TMM_OPT_MEMBER_BAND_ROWS, args.member_band)
     if args.member_waves is not None:
         t.set_option(tmm.TMM_OPT_MEMBER_WAVES, args.member_waves)
+    if args.member_tile is not None:
+        t.set_option(tmm.TMM_OPT_MEMBER_TILE, args.member_tile)
     s, e = _events()
     t.set_params(U)
     y0 = t.state(inp.initial_state(nm))

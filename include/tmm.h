@@ -215,12 +215,23 @@ enum {
                                     kernels: 32, 64, 128 or 256 (a tiling no deeper than the
                                     deepest column is used as the smallest); 0 = by state width
                                     (128 up to 4 state columns, else 256) */
-    TMM_OPT_WAVE_LOCAL = 10      /* 1 (default): the persistent forward kernels place each water
+    TMM_OPT_WAVE_LOCAL = 10,     /* 1 (default): the persistent forward kernels place each water
                                     column within one wavefront where the domains allow it (more,
                                     smaller domains if needed), so that a time step needs one
                                     workgroup barrier instead of three; 0: packed columns and
                                     three barriers per step.  Rebuilds the domains; the results
                                     are the same bit for bit */
+    TMM_OPT_MEMBER_TILE = 11     /* 0 (default): member-parallel steps of two-tracer models use one
+                                    wavefront per water column that reads its stencil's state rows
+                                    itself; 4 or 8: workgroups of that many neighbouring columns
+                                    (from the band order, which must be on) load each state row
+                                    their explicit rows read once per layer into LDS.  Needs one
+                                    BGC evaluation per step, at most 5 explicit entries per row,
+                                    at most 24 layers and the descriptor's longitudes
+                                    (TMM_EUNSUPPORTED otherwise, or when a tile's layer reads
+                                    more rows than a workgroup stages: 16 for 4 columns, 24 for
+                                    8; the option is then left as it was).  The results are the
+                                    same bit for bit */
 };
 
 /* Queries (tmm_query). */

@@ -11,7 +11,9 @@ rounding order:
 * ensembles: the member-parallel kernel (one wavefront per water column,
   lane = member) with 2, 4 or 8 wavefronts per workgroup and its column order
   (bands of 4 .. 32 latitude rows swept by longitude, or the natural order),
-  and the tile kernel with each tile size.
+  the tiled member kernel (4 or 8 neighbouring columns per workgroup, each
+  state row their explicit rows read staged once per layer in LDS; bands of 2
+  latitude rows), and the tile kernel with each tile size.
 
 Each candidate runs one untimed model year, whose final state must equal the
 default configuration's to 1e-12 relative at every point (a candidate that
@@ -41,14 +43,16 @@ DOMAIN_ROWS = (128, 160, 192, 224, 256, 320, 384, 448, 512)
 TILE_ROWS = (32, 64, 128, 256)
 MEMBER_WAVES = (2, 4, 8)
 MEMBER_BANDS = (-1, 4, 8, 16, 32)
+MEMBER_TILES = (4, 8)
 
-DEFAULTS = {T.TMM_OPT_PERSISTENT: 1, T.TMM_OPT_DOMAIN_ROWS: 0, T.TMM_OPT_MEMBER_KERNEL_MIN: 6,
+# the tiled member kernel is switched off before the band order changes (it needs bands)
+DEFAULTS = {T.TMM_OPT_MEMBER_TILE: 0, T.TMM_OPT_PERSISTENT: 1, T.TMM_OPT_DOMAIN_ROWS: 0, T.TMM_OPT_MEMBER_KERNEL_MIN: 6,
             T.TMM_OPT_GRAPH: 1, T.TMM_OPT_TILE_ROWS: 0, T.TMM_OPT_MEMBER_WAVES: 0, T.TMM_OPT_MEMBER_BAND_ROWS: 0}
 
 NAMES = {T.TMM_OPT_PERSISTENT: "persistent", T.TMM_OPT_DOMAIN_ROWS: "domain_rows",
          T.TMM_OPT_MEMBER_KERNEL_MIN: "member_kernel_min", T.TMM_OPT_GRAPH: "graph",
          T.TMM_OPT_TILE_ROWS: "tile_rows", T.TMM_OPT_MEMBER_WAVES: "member_waves",
-         T.TMM_OPT_MEMBER_BAND_ROWS: "member_band_rows"}
+         T.TMM_OPT_MEMBER_BAND_ROWS: "member_band_rows", T.TMM_OPT_MEMBER_TILE: "member_tile"}
 
 
 def signature(t, nbatch):
@@ -78,6 +82,11 @@ def candidates(t, nbatch):
                 out.append({T.TMM_OPT_PERSISTENT: 0,
                             T.TMM_OPT_MEMBER_KERNEL_MIN: min(DEFAULTS[T.TMM_OPT_MEMBER_KERNEL_MIN], nbatch),
                             T.TMM_OPT_MEMBER_WAVES: waves, T.TMM_OPT_MEMBER_BAND_ROWS: band})
+        if t.ntracer == 2:
+            for tile in MEMBER_TILES:
+                out.append({T.TMM_OPT_PERSISTENT: 0,
+                            T.TMM_OPT_MEMBER_KERNEL_MIN: min(DEFAULTS[T.TMM_OPT_MEMBER_KERNEL_MIN], nbatch),
+                            T.TMM_OPT_MEMBER_BAND_ROWS: 2, T.TMM_OPT_MEMBER_TILE: tile})
     return out
 
 
@@ -141,7 +150,15 @@ def tune(t, u, y0, years=2, rtol=1e-12, log=None, only=None, steps=0):
         if steps > 0 and int(cand.get(T.TMM_OPT_PERSISTENT, 0)):
             continue
         apply(t, DEFAULTS)
-        apply(t, cand)
+        try:
+            apply(t, cand)
+        except T.TmmError as ex:          # a variant this handle cannot run (e.g. a tile too wide)
+            rec = {"options": {str(k): int(v) for k, v in cand.items()}, "named": describe(cand),
+                   "ms_per_year": float("inf"), "max_rel_diff": None, "ok": False, "refused": str(ex)}
+            results.append(rec)
+            if log:
+                log(rec)
+            continue
         err = _max_rel(run(t).cpu().numpy(), ref)
         ok = err <= tol
         if not ok:

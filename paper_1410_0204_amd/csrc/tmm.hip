@@ -126,6 +126,7 @@ struct Plan {
     std::vector<int> col_lat;
     std::vector<double> lon;        // [ncol] or empty (descriptor's optional longitudes)
     size_t o_morder;                // column order of the member-parallel kernel
+    size_t o_mstage, o_mlidx;       // tables of the tiled member kernel (0: none)
     size_t o_ins, o_collat, o_latu;
     // persistent-kernel tables (sized for up to kMaxDomains domains)
     size_t o_pblock, o_pdomcol, o_pdepptr, o_pdepidx, o_pflags, o_pabort;
@@ -147,6 +148,8 @@ constexpr int kMaxPersistentRows = 256 * tmm::kPersistThreadsMax;
 constexpr int kDefaultDomainRows = 256;     // rows per persistent workgroup unless set by option (tuned on MI355X)
 constexpr int kMembersWavesMax = 8;         // wavefronts per workgroup of the member kernel, at most
 constexpr int kDefaultBandRows = 16;        // latitude rows per band of the member kernel's column order
+constexpr int kTileKmax = 24;               // deepest columns of the tiled member kernel
+constexpr int kTileQnMax = 4;               // staged rows per wavefront and layer, at most (4 columns x 16 rows)
 constexpr int kProbeLines = 4096;           // 256-byte lines of the probe's load chain (1 MiB)
 constexpr size_t kProbeBytes = 4096 + (size_t)kProbeLines * 256;
 
@@ -295,6 +298,13 @@ int validate(const tmm_desc* d, Plan& P) {
     if (d->lon) P.lon.assign(d->lon, d->lon + d->ncol);
     else P.lon.clear();
     P.o_morder = take(((size_t)d->ncol + 8 * kMembersWavesMax) * 4);
+    if (P.ntr == 2 && d->nlayer <= kTileKmax) {
+        const size_t slots = (size_t)d->ncol + 8 * kMembersWavesMax;
+        P.o_mstage = take(slots * kTileKmax * kTileQnMax * 4);
+        P.o_mlidx = take(slots * kTileKmax * 5);
+    } else {
+        P.o_mstage = P.o_mlidx = 0;
+    }
     P.o_collat = take((size_t)d->ncol * 4);
     P.o_latu = take(P.lat_u.size() * 8);
     P.dep_capacity = 2 * (size_t)d->ae_nnz + 1;
@@ -355,6 +365,9 @@ struct tmm_ctx {
     int mem_band = kDefaultBandRows;      // option TMM_OPT_MEMBER_BAND_ROWS (0: natural column order)
     int mem_blocks = 0;            // workgroups of one member-kernel launch (per member group)
     bool mem_ordered = false;      // the order table in the workspace is in use
+    int mem_tile = 0;              // option TMM_OPT_MEMBER_TILE: columns per workgroup of the tiled
+                                   // member kernel (0: k_step_members)
+    std::vector<int> ell_col;      // Ae's ELL columns [ew][npad] (host copy, for the tile tables)
     // captured model years of the launch-per-step path, keyed by their arguments
     struct YearGraph {
         int nb;
@@ -464,17 +477,74 @@ int copy(tmm_ctx* h, double* dst, const double* src, size_t len) {
     return TMM_OK;
 }
 
-// Column order of the member-parallel kernel (see k_step_members).  With the
+// Whether the tiled member kernel can run on this handle: two tracers, one
+// BGC evaluation per step, a five-point explicit stencil, columns of at most
+// kTileKmax layers, and longitudes to build compact tiles from.
+bool member_tiles_possible(const Plan& P) {
+    return P.ntr == 2 && P.nsub == 1 && P.ew <= 5 && P.nlayer <= kTileKmax && P.o_mstage != 0 && !P.lon.empty();
+}
+
+// Tables of k_step_member_tiles for the column order `order` (T columns per
+// workgroup): per workgroup and layer the distinct state rows that the
+// explicit rows of its columns read, in order of first use, dealt to the
+// wavefronts round-robin; per column, layer and stencil entry the slot it
+// reads.  Fails if a layer needs more than RMAX rows.
+int build_member_tiles(tmm_ctx* h, const std::vector<int>& order, int T, int rmax) {
+    const Plan& P = h->P;
+    const int nblk = (int)(order.size() / T);
+    const int qn = rmax / T;
+    const int KM = kTileKmax, EL = 5;
+    std::vector<int> stage((size_t)order.size() * KM * qn, -1);
+    std::vector<unsigned char> lidx((size_t)order.size() * KM * EL, 0);
+    std::vector<int> rows;
+    for (int b = 0; b < nblk; ++b) {
+        int kt = 0;
+        for (int w = 0; w < T; ++w) {
+            const int c = order[(size_t)b * T + w];
+            if (c >= 0) kt = std::max(kt, P.col_start[c + 1] - P.col_start[c]);
+        }
+        for (int k = 0; k < kt; ++k) {
+            rows.clear();
+            for (int w = 0; w < T; ++w) {
+                const int c = order[(size_t)b * T + w];
+                if (c < 0) continue;
+                const int rs = P.col_start[c], nc = P.col_start[c + 1] - rs;
+                if (k >= nc) continue;
+                for (int sl = 0; sl < P.ew; ++sl) {
+                    const int r = h->ell_col[(size_t)sl * P.npad + rs + k];
+                    int at = (int)(std::find(rows.begin(), rows.end(), r) - rows.begin());
+                    if (at == (int)rows.size()) rows.push_back(r);
+                    if (at >= rmax) return TMM_EUNSUPPORTED;
+                    lidx[((size_t)b * T + w) * KM * EL + (size_t)k * EL + sl] = (unsigned char)at;
+                }
+            }
+            for (int i = 0; i < (int)rows.size(); ++i)
+                stage[(((size_t)b * T + i % T) * KM + k) * qn + i / T] = rows[i];
+        }
+    }
+    if (upload(h, h->at<int>(P.o_mstage), stage.data(), stage.size() * 4) ||
+        upload(h, h->at<unsigned char>(P.o_mlidx), lidx.data(), lidx.size()))
+        return TMM_EDEVICE;
+    TMM_TRY(hipStreamSynchronize(h->stream));
+    return TMM_OK;
+}
+
+// Rows per layer that one workgroup of the tiled member kernel stages.
+int member_tile_rows(int T) { return T == 8 ? 24 : 16; }
+
+// Column order of the member-parallel kernels (see k_step_members).  With the
 // columns' longitudes known and band > 0: the columns sorted by (band of
 // `band` latitude rows, longitude, latitude row), cut into 8 runs of equal
 // length, run x on the workgroups b with b % 8 == x (the XCD they are
 // dispatched to), each workgroup taking `waves` consecutive columns of its
-// run.  Otherwise the natural order.  Written to the workspace; results do
-// not depend on it.  Not called during graph capture.
+// run (T of them for the tiled kernel, whose tables are built here too).
+// Otherwise the natural order.  Written to the workspace; results do not
+// depend on it.  Not called during graph capture.
 int build_member_order(tmm_ctx* h) {
     const Plan& P = h->P;
-    const int waves = h->mem_waves;
+    const int waves = h->mem_tile > 0 ? h->mem_tile : h->mem_waves;
     if (P.lon.empty() || h->mem_band <= 0) {
+        if (h->mem_tile > 0) return TMM_EUNSUPPORTED;
         h->mem_ordered = false;
         h->mem_blocks = (P.ncol + waves - 1) / waves;
         return TMM_OK;
@@ -499,6 +569,10 @@ int build_member_order(tmm_ctx* h) {
                 if (i * waves + w < q && pos < P.ncol) order[((size_t)i * runs + x) * waves + w] = cols[pos];
             }
     if (order.size() > (size_t)P.ncol + 8 * kMembersWavesMax) return TMM_EUNSUPPORTED;
+    if (h->mem_tile > 0) {
+        const int rc = build_member_tiles(h, order, waves, member_tile_rows(waves));
+        if (rc) return rc;
+    }
     if (upload(h, h->at<int>(P.o_morder), order.data(), order.size() * 4)) return TMM_EDEVICE;
     TMM_TRY(hipStreamSynchronize(h->stream));
     h->mem_blocks = runs * m;
@@ -526,6 +600,19 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
         const int nblk = wave_opt ? h->mem_blocks : (h->P.ncol + waves - 1) / waves;
         const int* order = (wave_opt && h->mem_ordered) ? h->at<int>(h->P.o_morder) : nullptr;
         dim3 grid(nblk, (nb + 63) / 64), blk(64 * waves);
+        if (wave_opt && h->mem_tile > 0 && h->mem_ordered && kmax <= kTileKmax) {
+            const int* stage = h->at<int>(h->P.o_mstage);
+            const unsigned char* lidx = h->at<unsigned char>(h->P.o_mlidx);
+            dim3 tgrid(h->mem_blocks, (nb + 63) / 64), tblk(64 * h->mem_tile);
+            if (h->mem_tile == 8)
+                hipLaunchKernelGGL((tmm::k_step_member_tiles<kTileKmax, 8, 24, 3>), tgrid, tblk, 0, h->launch_stream(),
+                                   g, md, mt, nb, j, dtd, order, stage, lidx, y, yo);
+            else
+                hipLaunchKernelGGL((tmm::k_step_member_tiles<kTileKmax, 4, 16, 3>), tgrid, tblk, 0, h->launch_stream(),
+                                   g, md, mt, nb, j, dtd, order, stage, lidx, y, yo);
+            TMM_LAUNCHED();
+            return TMM_OK;
+        }
 #define TMM_MEMBERS(NT, KM)                                                                                  \
     do {                                                                                                     \
         if (sub)                                                                                             \
@@ -1280,6 +1367,8 @@ int tmm_create(const tmm_desc* d, void* dev_workspace, size_t bytes, void* hip_s
             }
         }
         if (upload(h, h->at<int>(P.o_aecol), col.data(), col.size() * 4)) return fail(TMM_EDEVICE);
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(TMM_EDEVICE);
+        h->ell_col = col;
         std::vector<double> val((size_t)P.ew * P.npad);
         for (int m = 0; m < P.nmat; ++m) {
             std::fill(val.begin(), val.end(), 0.0);
@@ -1657,8 +1746,28 @@ int tmm_set_option(tmm_handle h, int option, int value) {
             if (value < -1) return TMM_EINVAL;
             int rc = drop_graphs(h);
             if (rc) return rc;
+            const int old = h->mem_band;
             h->mem_band = value == 0 ? kDefaultBandRows : (value < 0 ? 0 : value);
-            return build_member_order(h);
+            rc = build_member_order(h);
+            if (rc && rc != TMM_EDEVICE) {      // the tiled kernel's tables do not fit this order
+                h->mem_band = old;
+                if (build_member_order(h)) return TMM_EDEVICE;
+            }
+            return rc;
+        }
+        case TMM_OPT_MEMBER_TILE: {
+            if (value != 0 && value != 4 && value != 8) return TMM_EINVAL;
+            if (value != 0 && !member_tiles_possible(h->P)) return TMM_EUNSUPPORTED;
+            int rc = drop_graphs(h);
+            if (rc) return rc;
+            const int old = h->mem_tile;
+            h->mem_tile = value;
+            rc = build_member_order(h);
+            if (rc && rc != TMM_EDEVICE) {      // a layer of some tile needs more rows than a workgroup stages
+                h->mem_tile = old;
+                if (build_member_order(h)) return TMM_EDEVICE;
+            }
+            return rc;
         }
         case TMM_OPT_DOMAIN_ROWS: {
             if (value < 0) return TMM_EINVAL;

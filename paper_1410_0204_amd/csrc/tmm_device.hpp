@@ -945,6 +945,205 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
 }
 
 // ---------------------------------------------------------------------------
+// Forward step for ensembles of two-tracer models, a tile of T water columns
+// per workgroup.  Lanes are members as in k_step_members and wavefront w owns
+// column order[b * T + w], but the state rows the tile's explicit rows read
+// (the explicit operator is horizontal, so for layer k these are the tile's
+// own rows at layer k and their horizontal neighbours) are loaded once per
+// workgroup into LDS instead of once per reading row.  The host lists, per
+// workgroup and layer, the distinct rows to load (at most RMAX) and, per
+// column, row and stencil entry, which of them the entry reads.  Layers are
+// loaded PF ahead into registers and written to one of two LDS buffers, one
+// workgroup barrier per layer.  The loads are buffer loads: an unused slot
+// gets an offset past the end of the state, which reads zeros without a
+// memory access, so that no load sits under a branch and the compiler can
+// keep PF layers in flight.  Results are bitwise those of k_step_members:
+// every sum is formed in the same order from the same values.
+//
+// stage[((b * T + w) * KMAX + k) * QN + q]: row that wave w loads for slot
+//     w + q * T of layer k of workgroup b, or -1;
+// lidx[(b * T + w) * KMAX * 5 + k * 5 + s]: slot of layer k read by stencil
+//     entry s of row k of wave w's column (0 where the entry is padding).
+// Requires n * W * 8 < 2^32 (byte offsets of the state in 32 bits).
+// ---------------------------------------------------------------------------
+template <int KMAX, int T, int RMAX, int PF>
+__global__ __launch_bounds__(64 * T) void k_step_member_tiles(Grid g, Model md, Mats mt, int nb, int j, double dtd,
+                                                              const int* __restrict__ order,
+                                                              const int* __restrict__ stage,
+                                                              const unsigned char* __restrict__ lidx,
+                                                              const double* __restrict__ y,
+                                                              double* __restrict__ yo) {
+    constexpr int NTR = 2, EL = 5, NEU = 4;
+    constexpr int QN = RMAX / T;                       // slots each wave loads per layer
+    constexpr int NSE = (KMAX * QN + 63) / 64;         // registers holding the wave's stage entries
+    static_assert(RMAX % T == 0, "slots per layer");
+    __shared__ double s_ai[T][KMAX * KMAX];
+    __shared__ double s_ae[T][KMAX * EL];
+    __shared__ uint32_t s_off[T][KMAX * EL];          // byte offset of the slot within a layer buffer
+    __shared__ double2 s_rows[2][RMAX][64];           // two layers of staged state rows
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * T + wave;
+    const int craw = order[slot];
+    const bool valid = craw >= 0;
+    const int c = valid ? craw : 0;                   // idle waves stage column 0 and store nothing
+    const int b = blockIdx.y * 64 + lane;
+    const bool act = valid && b < nb;
+    const int bb = b < nb ? b : 0;
+    const int W = nb * NTR;
+    const int rs = g.col_start[c];
+    const int nc = g.col_start[c + 1] - rs;
+    int k0, k1;
+    double w;
+    step_phase(j, g.nstep, g.nmat, k0, k1, w);
+    const double om = 1.0 - w;
+    const int m = md.member[bb];
+    const double* rhoc = md.rhoT + (size_t)nc * g.nlayer * md.nbm + m;   // rho_k of this depth at [k * nbm]
+
+    // this wave's stage entries, lane l holding entry l + 64 * r
+    int se[NSE];
+    {
+        const int* st = stage + (size_t)slot * KMAX * QN;
+#pragma unroll
+        for (int r = 0; r < NSE; ++r) {
+            const int i = r * 64 + lane;
+            se[r] = i < KMAX * QN ? st[i] : -1;
+        }
+    }
+    const __amdgpu_buffer_rsrc_t yrs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double*>(y), (short)0, (int)(uint32_t)((size_t)g.n * W * 8), 0x00020000);
+    const uint32_t me8 = (uint32_t)bb * NTR * 8u, rowb = (uint32_t)W * 8u;
+    double2 R[PF][QN];
+    double rR[PF];
+    // layer k's rows into registers set p (k, q, p compile-time after unrolling)
+    auto issue = [&](int k, int p) {
+        const int kk = k < nc ? k : nc - 1;
+        rR[p] = rhoc[(size_t)kk * md.nbm];
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const int i = k * QN + q;
+            const int row = __builtin_amdgcn_readlane(se[i / 64], i % 64);
+            const uint32_t off = row >= 0 ? (uint32_t)row * rowb + me8 : 0xFFFFFFF0u;
+            R[p][q] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(yrs, (int)off, 0, 0));
+        }
+    };
+#pragma unroll
+    for (int p = 0; p < PF; ++p)
+        if (p < KMAX) issue(p, p);
+
+    const double Q = g.ins[(size_t)(j % g.nstep) * g.nlat + g.col_lat[c]];
+    const BgcParams p = load_params_at(md.uT, md.model, 1, (size_t)md.nbm, m);
+    const size_t me = (size_t)bb * NTR;
+    const int ne = nc < g.neu ? nc : g.neu;
+    double Ne[NEU], le[NEU], f[NEU];
+#pragma unroll
+    for (int e = 0; e < NEU; ++e) {
+        const int re = rs + (e < nc ? e : nc - 1);
+        Ne[e] = y[(size_t)re * W + me];
+        le[e] = md.lightT[(size_t)(e < g.nlayer ? e : 0) * md.nbm + m];
+    }
+
+    // the column's interpolated matrices and stencil slots (this wave's slice)
+    {
+        const size_t bo = (size_t)g.blk_off[c];
+        const double* ai0 = mt.ai_rm + (size_t)k0 * mt.ai_month + bo;
+        const double* ai1 = mt.ai_rm + (size_t)k1 * mt.ai_month + bo;
+        constexpr int NA = (KMAX * KMAX + 63) / 64;
+#pragma unroll
+        for (int it = 0; it < NA; ++it) {
+            const int i = it * 64 + lane;
+            const int k = i / KMAX, sl = i % KMAX;
+            const bool in = i < KMAX * KMAX && k < nc && sl < nc;
+            const int at = in ? k * nc + sl : 0;
+            const double v = om * ai0[at] + w * ai1[at];
+            if (i < KMAX * KMAX) s_ai[wave][i] = in ? v : 0.0;
+        }
+        const double* ae0 = mt.ae + (size_t)k0 * mt.ae_month;
+        const double* ae1 = mt.ae + (size_t)k1 * mt.ae_month;
+        const unsigned char* li = lidx + (size_t)slot * KMAX * EL;
+        constexpr int NE = (KMAX * EL + 63) / 64;
+#pragma unroll
+        for (int it = 0; it < NE; ++it) {
+            const int i = it * 64 + lane;
+            const int k = i / EL, sl = i % EL;
+            const bool in = i < KMAX * EL && k < nc && sl < mt.ew;
+            const size_t e = in ? (size_t)sl * g.npad + rs + k : (size_t)rs;
+            const double v = om * ae0[e] + w * ae1[e];
+            const int ii = i < KMAX * EL ? i : 0;
+            const uint32_t at = (uint32_t)li[ii] * (uint32_t)(64 * sizeof(double2));
+            if (i < KMAX * EL) {
+                s_off[wave][i] = at;
+                s_ae[wave][i] = in ? v : 0.0;
+            }
+        }
+    }
+
+    double Phi = 0.0;
+#pragma unroll
+    for (int e = 0; e < NEU; ++e) {
+        f[e] = 0.0;
+        if (e < ne) {
+            f[e] = production(p, Ne[e], Q, le[e]).f;
+            Phi += g.dz[e] * f[e];
+        }
+    }
+
+    // layer by layer: stage the layer's rows, then z of this column's row k.
+    // Rows past the column's depth (k >= nc) form finite values that meet
+    // zero columns of the staged Ai block below.
+    double z[KMAX][NTR];
+    const char* lds_lane = reinterpret_cast<const char*>(&s_rows[0][0][lane]);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+#pragma unroll
+        for (int q = 0; q < QN; ++q) s_rows[k & 1][wave + q * T][lane] = R[k % PF][q];
+        const double rho = rR[k % PF];
+        __syncthreads();
+        // after the barrier, whose fence keeps the compiler from hoisting
+        // every layer's loads to the top (registers)
+        if (k + PF < KMAX) issue(k + PF, k % PF);
+        double yv[EL][NTR];
+#pragma unroll
+        for (int sl = 0; sl < EL; ++sl) {
+            const double2 v = *reinterpret_cast<const double2*>(
+                lds_lane + (size_t)(k & 1) * RMAX * 64 * sizeof(double2) + s_off[wave][k * EL + sl]);
+            yv[sl][0] = v.x;
+            yv[sl][1] = v.y;
+        }
+        const double dop = yv[0][1];          // slot of entry 0: the row itself
+        double acc[NTR] = {0.0, 0.0};
+#pragma unroll
+        for (int sl = 0; sl < EL; ++sl) {
+            const double a = s_ae[wave][k * EL + sl];
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) acc[t] += a * yv[sl][t];
+        }
+        double fk = 0.0;
+#pragma unroll
+        for (int e = 0; e < NEU; ++e)
+            if (e == k) fk = f[e];
+        const double q1 = -fk + p.lam * dop + (1.0 - p.sig) * Phi * rho;
+        z[k][0] = acc[0] + dtd * q1;
+        z[k][1] = acc[1] + dtd * (p.sig * fk - p.lam * dop);
+        // form z here: left alone, the compiler sinks this arithmetic past the
+        // remaining layers into the product below and keeps every layer's
+        // staged values live instead (spills)
+        __asm__ volatile("" : "+v"(z[k][0]), "+v"(z[k][1]));
+    }
+
+    // y_out = Ai(t_j) z within the column
+    for (int k = 0; k < nc; ++k) {
+        double acc[NTR] = {0.0, 0.0};
+#pragma unroll
+        for (int sl = 0; sl < KMAX; ++sl) {
+            const double a = s_ai[wave][k * KMAX + sl];
+#pragma unroll
+            for (int t = 0; t < NTR; ++t) acc[t] += a * z[sl][t];
+        }
+        if (act) *reinterpret_cast<double2*>(yo + (size_t)(rs + k) * W + me) = make_double2(acc[0], acc[1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint step (reverse mode of k_step).  With mu_j the cotangent of z_j:
 //   lambda_j = Ae(t_j)^T mu_j + dt_d (dq/dy)(y_j)^T mu_j + s_j
 //   mu_{j-1} = Ai(t_{j-1})^T lambda_j

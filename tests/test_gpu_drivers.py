@@ -81,8 +81,8 @@ def test_ensemble_driver(small_ndop):
 @pytest.mark.parametrize("nb", [1, 20])
 def test_autotuner_candidates_match_the_oracle(small_ndop, tmp_path, nb):
     """Every candidate the autotuner tries (domain sizes of the single-launch kernel, tile sizes of the
-    tile kernel, wave counts and column orders of the member kernel) gives the oracle's model year;
-    the tuned table round-trips and the drivers apply it."""
+    tile kernel, wave counts and column orders of the member kernel, the tiled member kernel) gives the
+    oracle's model year; the tuned table round-trips and the drivers apply it."""
     from paper_1410_0204_amd import autotune
     tmm = _tmm()
     inp = small_ndop

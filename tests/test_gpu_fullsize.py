@@ -54,11 +54,20 @@ def test_ensemble_steps_against_oracle():
     o = oracle.Oracle(inp)
     rng = np.random.default_rng(5)
     y = inp.initial_state(nm) * rng.uniform(0.8, 1.2, size=(inp.n, 2 * nm))
+    yd = t.state(y)
     for j in (0, 1439):
         print(f"[gpu] ensemble step {j} on the oracle (~10 s)", flush=True)
-        got = t.step(j, t.state(y)).cpu().numpy()
+        got = t.step(j, yd).cpu().numpy()
         exp = o.step(U, j, y)
         assert pointwise(got, exp, 2, f"ensemble step {j}") <= STEP, j
+        # the tiled member kernel (bands of 2 latitude rows, 4 or 8 columns per workgroup): bit for bit
+        t.set_option(tmm.TMM_OPT_MEMBER_BAND_ROWS, 2)
+        for tile in (4, 8):
+            print(f"[gpu] ensemble step {j}, tiled member kernel with {tile} columns", flush=True)
+            t.set_option(tmm.TMM_OPT_MEMBER_TILE, tile)
+            assert np.array_equal(t.step(j, yd).cpu().numpy(), got), (j, tile)
+        t.set_option(tmm.TMM_OPT_MEMBER_TILE, 0)
+        t.set_option(tmm.TMM_OPT_MEMBER_BAND_ROWS, 0)
 
 
 def test_one_degree_month_and_conservation():

@@ -130,6 +130,67 @@ def test_member_kernel_orders_and_waves(inputs, waves):
             assert np.array_equal(got, ref), band
 
 
+@pytest.mark.parametrize("tile", [4, 8])
+def test_member_tile_kernel(inputs, tile):
+    """The tiled member kernel (workgroups of 4 or 8 neighbouring columns that stage each state row
+    once per layer in LDS) gives the oracle's step, and the one-column-per-wavefront kernel's result
+    bit for bit: at the start of the year, at a month boundary and at the year's last step, for two
+    member groups (the second ragged) and for the kernel's smallest batch (6 members)."""
+    tmm = _lib()
+    inp = inputs["small"]
+    o = oracle.Oracle(inp)
+    for nb in (70, 6):
+        U = synth.latin_hypercube(synth.MODEL_NDOP, nb, seed=73 + nb)
+        t = _make(inp, nbatch_max=nb)
+        t.set_params(U)
+        rng = np.random.default_rng(74 + nb)
+        y = inp.initial_state(nb) * rng.uniform(0.7, 1.3, size=(inp.n, 2 * nb))
+        yd = t.state(y)
+        for j in (0, 239, 240, 2879):
+            ref = t.step(j, yd).cpu().numpy()
+            t.set_option(tmm.TMM_OPT_MEMBER_BAND_ROWS, 2)
+            t.set_option(tmm.TMM_OPT_MEMBER_TILE, tile)
+            got = t.step(j, yd).cpu().numpy()
+            t.set_option(tmm.TMM_OPT_MEMBER_TILE, 0)
+            t.set_option(tmm.TMM_OPT_MEMBER_BAND_ROWS, 0)
+            assert pointwise(got, o.step(U, j, y), 2, f"tile {tile}, {nb} members, step {j}") <= STEP, j
+            assert np.array_equal(got, ref), (nb, j)
+        t.close()
+
+
+def test_member_tile_kernel_year_and_refusals(inputs):
+    """Model years of an uneven ensemble on the tiled member kernel (graph-captured steps, members
+    compacted as they finish) equal the oracle's years member by member; the option is refused where
+    the kernel cannot run (one tracer, no band order) and leaves the handle as it was."""
+    tmm = _lib()
+    inp = inputs["small"]
+    nb = 8
+    U = synth.latin_hypercube(synth.MODEL_NDOP, nb, seed=81)
+    L = np.array([2, 1, 2, 0, 1, 2, 2, 1], dtype=np.int32)
+    t = _make(inp, nbatch_max=nb)
+    t.set_params(U)
+    t.set_option(tmm.TMM_OPT_MEMBER_BAND_ROWS, 2)
+    t.set_option(tmm.TMM_OPT_MEMBER_TILE, 8)
+    y0 = inp.initial_state(nb)
+    got, _ = t.year(t.state(y0), nyears=2, years_per_member=L)
+    got = got.cpu().numpy()
+    o = oracle.Oracle(inp)
+    for m in range(nb):
+        exp = o.year(U[m], y0[:, 2 * m:2 * m + 2], int(L[m]))[0] if L[m] else y0[:, 2 * m:2 * m + 2]
+        assert pointwise(got[:, 2 * m:2 * m + 2], exp, 2, f"tiled member kernel, member {m}") <= YEAR, m
+    with pytest.raises(tmm.TmmError):
+        t.set_option(tmm.TMM_OPT_MEMBER_BAND_ROWS, -1)      # tiles need the band order
+    with pytest.raises(tmm.TmmError):
+        t.set_option(tmm.TMM_OPT_MEMBER_TILE, 6)
+    again, _ = t.year(t.state(y0), nyears=2, years_per_member=L)
+    assert np.array_equal(again.cpu().numpy(), got)
+    t.close()
+    t1 = _make(inputs["tiny_n"], nbatch_max=8)
+    with pytest.raises(tmm.TmmError):
+        t1.set_option(tmm.TMM_OPT_MEMBER_TILE, 8)
+    t1.close()
+
+
 def test_uneven_spinup_lengths(inputs):
     """Members stop after their own number of years; finished states are kept."""
     inp = inputs["tiny_ndop"]

@@ -195,8 +195,10 @@ enum {
                                 0 = the default (256) */
     TMM_OPT_MEMBER_KERNEL_MIN = 3, /* forward steps of batches with at least this many members use the
                                      member-parallel kernel (one wavefront per water column, lane =
-                                     member); default 6, about where it overtakes the tile kernel
-                                     on grids of 50k to 500k points; 0 = never */
+                                     member); -1 = the default: 2 where its packed forms run (two
+                                     tracers, one BGC evaluation per step, at most 24 layers,
+                                     TMM_OPT_MEMBER_PACK on), else 6, about where it overtakes the
+                                     tile kernel on grids of 50k to 500k points; 0 = never */
     TMM_OPT_GRAPH = 4,           /* 1 (default): model years on the launch-per-step path are captured
                                     once per (members, buffers) into a hipGraph and replayed */
     TMM_OPT_SPIN_LIMIT = 5,      /* polls after which a wait of the persistent kernels gives up
@@ -221,7 +223,7 @@ enum {
                                     workgroup barrier instead of three; 0: packed columns and
                                     three barriers per step.  Rebuilds the domains; the results
                                     are the same bit for bit */
-    TMM_OPT_MEMBER_TILE = 11     /* 0 (default): member-parallel steps of two-tracer models use one
+    TMM_OPT_MEMBER_TILE = 11,    /* 0 (default): member-parallel steps of two-tracer models use one
                                     wavefront per water column that reads its stencil's state rows
                                     itself; 4 or 8: workgroups of that many neighbouring columns
                                     (from the band order, which must be on) load each state row
@@ -232,6 +234,11 @@ enum {
                                     more rows than a workgroup stages: 16 for 4 columns, 24 for
                                     8; the option is then left as it was).  The results are the
                                     same bit for bit */
+    TMM_OPT_MEMBER_PACK = 12     /* 1 (default): member-parallel steps of two-tracer models with at
+                                    most 32 (16) members place 2 (4) water columns in one wavefront,
+                                    32 (16) lanes each, so that the step's time follows the member
+                                    count; 0: one column per wavefront at every width.  Same
+                                    results bit for bit */
 };
 
 /* Queries (tmm_query). */

@@ -46,13 +46,15 @@ MEMBER_BANDS = (-1, 4, 8, 16, 32)
 MEMBER_TILES = (4, 8)
 
 # the tiled member kernel is switched off before the band order changes (it needs bands)
-DEFAULTS = {T.TMM_OPT_MEMBER_TILE: 0, T.TMM_OPT_PERSISTENT: 1, T.TMM_OPT_DOMAIN_ROWS: 0, T.TMM_OPT_MEMBER_KERNEL_MIN: 6,
+DEFAULTS = {T.TMM_OPT_MEMBER_TILE: 0, T.TMM_OPT_MEMBER_PACK: 1, T.TMM_OPT_PERSISTENT: 1, T.TMM_OPT_DOMAIN_ROWS: 0,
+            T.TMM_OPT_MEMBER_KERNEL_MIN: -1,
             T.TMM_OPT_GRAPH: 1, T.TMM_OPT_TILE_ROWS: 0, T.TMM_OPT_MEMBER_WAVES: 0, T.TMM_OPT_MEMBER_BAND_ROWS: 0}
 
 NAMES = {T.TMM_OPT_PERSISTENT: "persistent", T.TMM_OPT_DOMAIN_ROWS: "domain_rows",
          T.TMM_OPT_MEMBER_KERNEL_MIN: "member_kernel_min", T.TMM_OPT_GRAPH: "graph",
          T.TMM_OPT_TILE_ROWS: "tile_rows", T.TMM_OPT_MEMBER_WAVES: "member_waves",
-         T.TMM_OPT_MEMBER_BAND_ROWS: "member_band_rows", T.TMM_OPT_MEMBER_TILE: "member_tile"}
+         T.TMM_OPT_MEMBER_BAND_ROWS: "member_band_rows", T.TMM_OPT_MEMBER_TILE: "member_tile",
+         T.TMM_OPT_MEMBER_PACK: "member_pack"}
 
 
 def signature(t, nbatch):
@@ -74,18 +76,20 @@ def candidates(t, nbatch):
             out.append({T.TMM_OPT_PERSISTENT: 1, T.TMM_OPT_DOMAIN_ROWS: rows})
     for rows in TILE_ROWS:
         out.append({T.TMM_OPT_PERSISTENT: 0, T.TMM_OPT_MEMBER_KERNEL_MIN: 0, T.TMM_OPT_TILE_ROWS: rows})
+    # the library's default crossover to the member kernel (see TMM_OPT_MEMBER_KERNEL_MIN)
+    kmin = 2 if t.ntracer == 2 and max(int(t.desc.nbgc), 1) == 1 and int(t.desc.nlayer) <= 24 else 6
     if nbatch > 1 and t.ntracer <= 2:
         for waves in MEMBER_WAVES:
             for band in MEMBER_BANDS:
                 # the member kernel at this width; narrower batches (members that
                 # finish early) keep the default crossover to the tile kernel
                 out.append({T.TMM_OPT_PERSISTENT: 0,
-                            T.TMM_OPT_MEMBER_KERNEL_MIN: min(DEFAULTS[T.TMM_OPT_MEMBER_KERNEL_MIN], nbatch),
+                            T.TMM_OPT_MEMBER_KERNEL_MIN: min(kmin, nbatch),
                             T.TMM_OPT_MEMBER_WAVES: waves, T.TMM_OPT_MEMBER_BAND_ROWS: band})
         if t.ntracer == 2:
             for tile in MEMBER_TILES:
                 out.append({T.TMM_OPT_PERSISTENT: 0,
-                            T.TMM_OPT_MEMBER_KERNEL_MIN: min(DEFAULTS[T.TMM_OPT_MEMBER_KERNEL_MIN], nbatch),
+                            T.TMM_OPT_MEMBER_KERNEL_MIN: min(kmin, nbatch),
                             T.TMM_OPT_MEMBER_BAND_ROWS: 2, T.TMM_OPT_MEMBER_TILE: tile})
     return out
 

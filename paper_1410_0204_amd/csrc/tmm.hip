@@ -126,6 +126,7 @@ struct Plan {
     std::vector<int> col_lat;
     std::vector<double> lon;        // [ncol] or empty (descriptor's optional longitudes)
     size_t o_morder;                // column order of the member-parallel kernel
+    size_t o_morderp[2];            // ... of its packed forms (2 and 4 columns per wavefront)
     size_t o_mstage, o_mlidx;       // tables of the tiled member kernel (0: none)
     size_t o_ins, o_collat, o_latu;
     // persistent-kernel tables (sized for up to kMaxDomains domains)
@@ -298,6 +299,7 @@ int validate(const tmm_desc* d, Plan& P) {
     if (d->lon) P.lon.assign(d->lon, d->lon + d->ncol);
     else P.lon.clear();
     P.o_morder = take(((size_t)d->ncol + 8 * kMembersWavesMax) * 4);
+    for (auto& o_p : P.o_morderp) o_p = take(((size_t)d->ncol + 8 * kMembersWavesMax) * 4);
     if (P.ntr == 2 && d->nlayer <= kTileKmax) {
         const size_t slots = (size_t)d->ncol + 8 * kMembersWavesMax;
         P.o_mstage = take(slots * kTileKmax * kTileQnMax * 4);
@@ -360,11 +362,14 @@ struct tmm_ctx {
     bool pers_wave_local = false;  // no water column spans two wavefronts of the forward kernels
     bool wave_local_enabled = true;    // option TMM_OPT_WAVE_LOCAL
     int pers_target = 0;           // option TMM_OPT_DOMAIN_ROWS as last set
-    int wide_min_members = 6;      // batches of at least this many members use k_step_members
+    int wide_min_members = -1;     // batches of at least this many members use k_step_members
+                                   // (-1: 2 where the packed forms run, else 6)
     int mem_waves = tmm::kMembersWaves;   // option TMM_OPT_MEMBER_WAVES
     int mem_band = kDefaultBandRows;      // option TMM_OPT_MEMBER_BAND_ROWS (0: natural column order)
     int mem_blocks = 0;            // workgroups of one member-kernel launch (per member group)
     bool mem_ordered = false;      // the order table in the workspace is in use
+    bool mem_pack = true;          // option TMM_OPT_MEMBER_PACK
+    int mem_blocks_p[2] = {0, 0};  // workgroups of the packed member kernels (32, 16 members per column)
     int mem_tile = 0;              // option TMM_OPT_MEMBER_TILE: columns per workgroup of the tiled
                                    // member kernel (0: k_step_members)
     std::vector<int> ell_col;      // Ae's ELL columns [ew][npad] (host copy, for the tile tables)
@@ -543,10 +548,13 @@ int member_tile_rows(int T) { return T == 8 ? 24 : 16; }
 int build_member_order(tmm_ctx* h) {
     const Plan& P = h->P;
     const int waves = h->mem_tile > 0 ? h->mem_tile : h->mem_waves;
+    // columns per workgroup of the packed member kernels (two wavefronts of 2 or 4 columns)
+    const int pcols[2] = {2 * 2, 2 * 4};
     if (P.lon.empty() || h->mem_band <= 0) {
         if (h->mem_tile > 0) return TMM_EUNSUPPORTED;
         h->mem_ordered = false;
         h->mem_blocks = (P.ncol + waves - 1) / waves;
+        for (int i = 0; i < 2; ++i) h->mem_blocks_p[i] = (P.ncol + pcols[i] - 1) / pcols[i];
         return TMM_OK;
     }
     std::vector<int> cols(P.ncol);
@@ -558,24 +566,39 @@ int build_member_order(tmm_ctx* h) {
         if (P.lon[a] != P.lon[b]) return P.lon[a] < P.lon[b];
         return P.col_lat[a] < P.col_lat[b];
     });
+    // the sorted columns cut into 8 runs, run x on the workgroups b with
+    // b % 8 == x, each workgroup taking `per` consecutive columns of its run
     const int runs = 8;
     const int q = (P.ncol + runs - 1) / runs;          // columns per run
-    const int m = (q + waves - 1) / waves;             // workgroups per run
-    std::vector<int> order((size_t)runs * m * waves, -1);
-    for (int x = 0; x < runs; ++x)
-        for (int i = 0; i < m; ++i)
-            for (int w = 0; w < waves; ++w) {
-                const int pos = x * q + i * waves + w;
-                if (i * waves + w < q && pos < P.ncol) order[((size_t)i * runs + x) * waves + w] = cols[pos];
-            }
+    auto make = [&](int per, int& blocks) {
+        const int m = (q + per - 1) / per;             // workgroups per run
+        std::vector<int> order((size_t)runs * m * per, -1);
+        for (int x = 0; x < runs; ++x)
+            for (int i = 0; i < m; ++i)
+                for (int w = 0; w < per; ++w) {
+                    const int pos = x * q + i * per + w;
+                    if (i * per + w < q && pos < P.ncol) order[((size_t)i * runs + x) * per + w] = cols[pos];
+                }
+        blocks = runs * m;
+        return order;
+    };
+    int blocks = 0;
+    std::vector<int> order = make(waves, blocks);
     if (order.size() > (size_t)P.ncol + 8 * kMembersWavesMax) return TMM_EUNSUPPORTED;
     if (h->mem_tile > 0) {
         const int rc = build_member_tiles(h, order, waves, member_tile_rows(waves));
         if (rc) return rc;
     }
     if (upload(h, h->at<int>(P.o_morder), order.data(), order.size() * 4)) return TMM_EDEVICE;
+    int pblocks[2];
+    for (int i = 0; i < 2; ++i) {
+        std::vector<int> po = make(pcols[i], pblocks[i]);
+        if (po.size() > (size_t)P.ncol + 8 * kMembersWavesMax) return TMM_EUNSUPPORTED;
+        if (upload(h, h->at<int>(P.o_morderp[i]), po.data(), po.size() * 4)) return TMM_EDEVICE;
+    }
     TMM_TRY(hipStreamSynchronize(h->stream));
-    h->mem_blocks = runs * m;
+    h->mem_blocks = blocks;
+    for (int i = 0; i < 2; ++i) h->mem_blocks_p[i] = pblocks[i];
     h->mem_ordered = true;
     return TMM_OK;
 }
@@ -585,7 +608,12 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
     const int W = nb * h->P.ntr;
     const bool tangent = v != nullptr;
     const bool sub = h->P.nsub > 1;
-    if (!tangent && nb >= h->wide_min_members && h->P.ntr <= 2 && h->P.nlayer <= 32 &&
+    // measured crossovers with the tile kernel (50k and 500k points): 2 members
+    // for the packed member kernel, 6 for one column per wavefront
+    const bool packed = h->P.ntr == 2 && !sub && h->P.ew <= 5 && h->mem_pack && h->mem_tile == 0 &&
+                        h->P.nlayer <= 24;
+    const int min_nb = h->wide_min_members >= 0 ? h->wide_min_members : (packed ? 2 : 6);
+    if (!tangent && nb >= min_nb && h->P.ntr <= 2 && h->P.nlayer <= 32 &&
         h->P.ew <= tmm::kMembersEll && (size_t)h->P.npad * W * 8 <= UINT32_MAX) {
         // member-parallel kernel: one wavefront per column and 64 members
         const int kmax = h->P.nlayer <= 16 ? 16 : h->P.nlayer <= 24 ? 24 : 32;
@@ -600,6 +628,26 @@ int launch_step(tmm_ctx* h, int j, int nb, const double* y, double* yo, const do
         const int nblk = wave_opt ? h->mem_blocks : (h->P.ncol + waves - 1) / waves;
         const int* order = (wave_opt && h->mem_ordered) ? h->at<int>(h->P.o_morder) : nullptr;
         dim3 grid(nblk, (nb + 63) / 64), blk(64 * waves);
+        if (wave_opt && h->mem_tile == 0 && h->mem_pack && nb <= 32 && kmax <= 24) {
+            // packed: 2 (4) columns per wavefront, 32 (16) members each
+            const int pi = nb <= 16 ? 1 : 0;
+            const int* porder = h->mem_ordered ? h->at<int>(h->P.o_morderp[pi]) : nullptr;
+            dim3 pgrid(h->mem_blocks_p[pi], 1), pblk(128);
+            if (pi == 0 && kmax == 16)
+                hipLaunchKernelGGL((tmm::k_step_members<2, 16, 5, false, 2, 32>), pgrid, pblk, 0, h->launch_stream(),
+                                   g, md, mt, h->P.ncol, nb, j, dtd, porder, y, yo);
+            else if (pi == 0)
+                hipLaunchKernelGGL((tmm::k_step_members<2, 24, 5, false, 2, 32>), pgrid, pblk, 0, h->launch_stream(),
+                                   g, md, mt, h->P.ncol, nb, j, dtd, porder, y, yo);
+            else if (kmax == 16)
+                hipLaunchKernelGGL((tmm::k_step_members<2, 16, 5, false, 2, 16>), pgrid, pblk, 0, h->launch_stream(),
+                                   g, md, mt, h->P.ncol, nb, j, dtd, porder, y, yo);
+            else
+                hipLaunchKernelGGL((tmm::k_step_members<2, 24, 5, false, 2, 16>), pgrid, pblk, 0, h->launch_stream(),
+                                   g, md, mt, h->P.ncol, nb, j, dtd, porder, y, yo);
+            TMM_LAUNCHED();
+            return TMM_OK;
+        }
         if (wave_opt && h->mem_tile > 0 && h->mem_ordered && kmax <= kTileKmax) {
             const int* stage = h->at<int>(h->P.o_mstage);
             const unsigned char* lidx = h->at<unsigned char>(h->P.o_mlidx);
@@ -1716,7 +1764,8 @@ int tmm_set_option(tmm_handle h, int option, int value) {
     switch (option) {
         case TMM_OPT_PERSISTENT: h->pers_enabled = value != 0; return TMM_OK;
         case TMM_OPT_MEMBER_KERNEL_MIN:
-            h->wide_min_members = value < 1 ? 1 << 30 : value;
+            if (value < -1) return TMM_EINVAL;
+            h->wide_min_members = value < 0 ? -1 : (value == 0 ? 1 << 30 : value);
             return drop_graphs(h);
         case TMM_OPT_GRAPH:
             h->graphs_enabled = value != 0;
@@ -1754,6 +1803,12 @@ int tmm_set_option(tmm_handle h, int option, int value) {
                 if (build_member_order(h)) return TMM_EDEVICE;
             }
             return rc;
+        }
+        case TMM_OPT_MEMBER_PACK: {
+            int rc = drop_graphs(h);
+            if (rc) return rc;
+            h->mem_pack = value != 0;
+            return TMM_OK;
         }
         case TMM_OPT_MEMBER_TILE: {
             if (value != 0 && value != 4 && value != 8) return TMM_EINVAL;

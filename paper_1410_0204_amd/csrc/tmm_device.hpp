@@ -740,27 +740,37 @@ __global__ __launch_bounds__(256) void k_step(Grid g, Model md, Mats mt, int W, 
 // state rows are still in its L2, instead of one latitude row (several MB of
 // state at 64 members) later.  Without an order (nullptr) wave w of block b
 // takes column b * WAVES + w.
+//
+// Batches of at most 32 (16) members run with G = 32 (16): a wavefront then
+// holds CPW = 64 / G columns, lanes [s * G, (s + 1) * G) on column slot
+// b * WAVES * CPW + w * CPW + s of the order, member groups of G lanes, so
+// that the step's time follows the member count instead of leaving lanes
+// idle.  Each lane computes exactly what it computes with G = 64.
 // ---------------------------------------------------------------------------
 constexpr int kMembersWaves = 4;      // default wavefronts (columns) per workgroup
 constexpr int kMembersEll = 8;        // Ae nonzeros per row supported by k_step_members
 
-template <int NTR, int KMAX, int EL, bool SUB = false, int WAVES = kMembersWaves>
+template <int NTR, int KMAX, int EL, bool SUB = false, int WAVES = kMembersWaves, int G = 64>
 __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, Mats mt, int ncol, int nb, int j,
                                                              double dtd, const int* __restrict__ order,
                                                              const double* __restrict__ y,
                                                              double* __restrict__ yo) {
     constexpr int NEU = 4;
+    constexpr int CPW = 64 / G;                  // water columns per wavefront (G lanes = members each)
+    static_assert(G == 64 || G == 32 || G == 16, "members per column group");
     // zero-padded KMAX x KMAX block and KMAX x EL explicit rows, so that every
     // loop below runs to its compile-time bound without branches
-    __shared__ double s_ai[WAVES][KMAX * KMAX];
-    __shared__ double s_ae[WAVES][KMAX * EL];
-    __shared__ uint32_t s_off[WAVES][KMAX * EL];   // byte offset of the row each entry reads (< 2^32)
+    __shared__ double s_ai[WAVES * CPW][KMAX * KMAX];
+    __shared__ double s_ae[WAVES * CPW][KMAX * EL];
+    __shared__ uint32_t s_off[WAVES * CPW][KMAX * EL];   // byte offset of the row each entry reads (< 2^32)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = blockIdx.x * WAVES + wave;
+    const int ml = lane % G;                     // member lane within the column's group
+    const int cs = wave * CPW + lane / G;        // column slot within the workgroup (its LDS slice)
+    const int slot = blockIdx.x * WAVES * CPW + cs;
     const int craw = order ? order[slot] : (slot < ncol ? slot : -1);
     const bool valid = craw >= 0;                // waves without a column idle but reach the barrier
     const int c = valid ? craw : ncol - 1;
-    const int b = blockIdx.y * 64 + lane;
+    const int b = blockIdx.y * G + ml;
     const bool act = valid && b < nb;
     const int bb = b < nb ? b : 0;               // idle lanes read member 0 (in bounds) and store nothing
     const int W = nb * NTR;
@@ -797,30 +807,30 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
         const size_t bo = (size_t)g.blk_off[c];
         const double* ai0 = mt.ai_rm + (size_t)k0 * mt.ai_month + bo;
         const double* ai1 = mt.ai_rm + (size_t)k1 * mt.ai_month + bo;
-        constexpr int NA = (KMAX * KMAX + 63) / 64;
+        constexpr int NA = (KMAX * KMAX + G - 1) / G;
 #pragma unroll
         for (int it = 0; it < NA; ++it) {
-            const int i = it * 64 + lane;
+            const int i = it * G + ml;
             const int k = i / KMAX, sl = i % KMAX;
             const bool in = i < KMAX * KMAX && k < nc && sl < nc;
             const int at = in ? k * nc + sl : 0;
             const double v = om * ai0[at] + w * ai1[at];
-            if (i < KMAX * KMAX) s_ai[wave][i] = in ? v : 0.0;
+            if (i < KMAX * KMAX) s_ai[cs][i] = in ? v : 0.0;
         }
         const double* ae0 = mt.ae + (size_t)k0 * mt.ae_month;
         const double* ae1 = mt.ae + (size_t)k1 * mt.ae_month;
-        constexpr int NE = (KMAX * EL + 63) / 64;
+        constexpr int NE = (KMAX * EL + G - 1) / G;
 #pragma unroll
         for (int it = 0; it < NE; ++it) {
-            const int i = it * 64 + lane;
+            const int i = it * G + ml;
             const int k = i / EL, sl = i % EL;
             const bool in = i < KMAX * EL && k < nc && sl < mt.ew;
             const size_t e = in ? (size_t)sl * g.npad + rs + k : (size_t)rs;
             const int col = mt.ae_col[e];
             const double v = om * ae0[e] + w * ae1[e];
             if (i < KMAX * EL) {
-                s_off[wave][i] = (uint32_t)(in ? col : rs) * (uint32_t)(W * 8);
-                s_ae[wave][i] = in ? v : 0.0;
+                s_off[cs][i] = (uint32_t)(in ? col : rs) * (uint32_t)(W * 8);
+                s_ae[cs][i] = in ? v : 0.0;
             }
         }
     }
@@ -875,7 +885,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
 #pragma unroll
         for (int sl = 0; sl < EL; ++sl) {
             const double* src =
-                reinterpret_cast<const double*>(ybytes + (size_t)(s_off[wave][k * EL + sl] + me8));
+                reinterpret_cast<const double*>(ybytes + (size_t)(s_off[cs][k * EL + sl] + me8));
             if constexpr (NTR == 2) {
                 // both tracers of a member in one 16-byte load (W is even, so the pair is aligned)
                 const double2 v = *reinterpret_cast<const double2*>(src);
@@ -894,7 +904,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
         for (int t = 0; t < NTR; ++t) acc[t] = 0.0;
 #pragma unroll
         for (int sl = 0; sl < EL; ++sl) {
-            const double a = s_ae[wave][k * EL + sl];
+            const double a = s_ae[cs][k * EL + sl];
 #pragma unroll
             for (int t = 0; t < NTR; ++t) acc[t] += a * yv[sl][t];
         }
@@ -928,7 +938,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
         for (int t = 0; t < NTR; ++t) acc[t] = 0.0;
 #pragma unroll
         for (int sl = 0; sl < KMAX; ++sl) {
-            const double a = s_ai[wave][k * KMAX + sl];
+            const double a = s_ai[cs][k * KMAX + sl];
 #pragma unroll
             for (int t = 0; t < NTR; ++t) acc[t] += a * z[sl][t];
         }

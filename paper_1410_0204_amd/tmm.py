@@ -42,6 +42,7 @@ TMM_OPT_MEMBER_BAND_ROWS = 8
 TMM_OPT_TILE_ROWS = 9
 TMM_OPT_WAVE_LOCAL = 10
 TMM_OPT_MEMBER_TILE = 11
+TMM_OPT_MEMBER_PACK = 12
 TMM_Q_PERSISTENT = 1
 TMM_Q_DOMAINS = 2
 TMM_Q_WORKSPACE = 3

@@ -191,6 +191,32 @@ def test_member_tile_kernel_year_and_refusals(inputs):
     t1.close()
 
 
+@pytest.mark.parametrize("nb", [6, 16, 17, 32])
+def test_packed_member_kernel(inputs, nb):
+    """Batches of at most 32 (16) members run the member kernel with 2 (4) water columns per
+    wavefront: the oracle's step, and bit for bit the one-column-per-wavefront result, in the band
+    order and in the natural order."""
+    tmm = _lib()
+    inp = inputs["small"]
+    U = synth.latin_hypercube(synth.MODEL_NDOP, nb, seed=90 + nb)
+    t = _make(inp, nbatch_max=nb)
+    t.set_params(U)
+    rng = np.random.default_rng(91 + nb)
+    y = inp.initial_state(nb) * rng.uniform(0.7, 1.3, size=(inp.n, 2 * nb))
+    yd = t.state(y)
+    o = oracle.Oracle(inp)
+    for band in (0, -1):
+        t.set_option(tmm.TMM_OPT_MEMBER_BAND_ROWS, band)
+        for j in (0, 1439, 2879):
+            t.set_option(tmm.TMM_OPT_MEMBER_PACK, 0)
+            ref = t.step(j, yd).cpu().numpy()
+            t.set_option(tmm.TMM_OPT_MEMBER_PACK, 1)
+            got = t.step(j, yd).cpu().numpy()
+            assert pointwise(got, o.step(U, j, y), 2, f"packed, {nb} members, band {band}, step {j}") <= STEP
+            assert np.array_equal(got, ref), (band, j)
+    t.close()
+
+
 def test_uneven_spinup_lengths(inputs):
     """Members stop after their own number of years; finished states are kept."""
     inp = inputs["tiny_ndop"]

@@ -116,6 +116,18 @@ def cpu_baseline(inp, u, B):
             rows[want] = {"threads": used, "s_per_year": med, "model_years_per_s": 1.0 / med,
                           "effective_GBps": B * inp.nstep / med / 1e9, "years_s": times}
             log(f"[bench] cpu oracle, {used} thread(s): {med:.2f} s per model year (median of 3)")
+        # the oracle's own adjoint/forward ratio (full-trajectory reverse sweep), on every thread
+        import synth
+        n, W = inp.n, inp.ntracer
+        obs = (np.broadcast_to(inp.initial_state(), (12, n, W))
+               * (1 + 0.05 * synth.obs_noise((12, n, W), seed=3)))
+        t0 = time.perf_counter()
+        o.year_adjoint(u, y, obs)
+        adj_s = time.perf_counter() - t0
+        rows[allowed]["adjoint_s"] = adj_s
+        rows[allowed]["adjoint_forward_ratio"] = adj_s / rows[allowed]["s_per_year"]
+        log(f"[bench] cpu oracle adjoint year, {rows[allowed]['threads']} thread(s): {adj_s:.2f} s "
+            f"({adj_s / rows[allowed]['s_per_year']:.2f}x its forward year)")
     finally:
         shutil.rmtree(d, ignore_errors=True)
     full = rows[allowed]

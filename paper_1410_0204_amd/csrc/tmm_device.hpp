@@ -754,7 +754,7 @@ template <int NTR, int KMAX, int EL, bool SUB = false, int WAVES = kMembersWaves
 __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, Mats mt, int ncol, int nb, int j,
                                                              double dtd, const int* __restrict__ order,
                                                              const double* __restrict__ y,
-                                                             double* __restrict__ yo) {
+                                                             double* __restrict__ yo, int nt_store) {
     constexpr int NEU = 4;
     constexpr int CPW = 64 / G;                  // water columns per wavefront (G lanes = members each)
     static_assert(G == 64 || G == 32 || G == 16, "members per column group");
@@ -945,7 +945,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_members(Grid g, Model md, M
         if (act) {
             double* dst = yo + (size_t)(rs + k) * W + me;
             if constexpr (NTR == 2) {
-                *reinterpret_cast<double2*>(dst) = make_double2(acc[0], acc[1]);
+                if (nt_store) {
+                    // non-temporal: a step whose state and matrices outgrow the last-level cache
+                    // gains nothing from keeping the new state there (its rows are read again
+                    // only in the next step), and the store would evict rows still to be gathered
+                    typedef double d2v __attribute__((ext_vector_type(2)));
+                    const d2v v = {acc[0], acc[1]};
+                    __builtin_nontemporal_store(v, reinterpret_cast<d2v*>(dst));
+                } else {
+                    *reinterpret_cast<double2*>(dst) = make_double2(acc[0], acc[1]);
+                }
             } else {
 #pragma unroll
                 for (int t = 0; t < NTR; ++t) dst[t] = acc[t];

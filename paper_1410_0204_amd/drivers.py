@@ -22,6 +22,7 @@ import os
 import time
 
 import numpy as np
+import torch
 
 from . import autotune as _autotune
 from . import tmm as _tmm
@@ -121,16 +122,28 @@ def spinup(t, u, y0, years, tol=0.0, log_path=None, state_path=None, state_every
 # GMRES(m) with modified Gram-Schmidt, x0 = 0
 # ---------------------------------------------------------------------------
 
+def _norm(a):
+    return float(torch.linalg.vector_norm(a)) if torch.is_tensor(a) else float(np.linalg.norm(a))
+
+
+def _dot(a, b):
+    return float(torch.dot(a, b)) if torch.is_tensor(a) else float(np.dot(a, b))
+
+
 def gmres(matvec, b, rtol, restart=30, maxiter=300, log=None):
     """Solves A x = b to ||b - A x|| <= rtol ||b||.
 
-    Returns (x, r, matvecs) with r = b - A x the true residual at exit."""
-    bnorm = float(np.linalg.norm(b))
-    x = np.zeros_like(b)
+    b and the vectors matvec takes and returns are NumPy arrays or torch
+    tensors (on the device that holds the states: the Krylov basis then stays
+    there, and only the scalars of the Gram-Schmidt and Givens steps come to
+    the host).  Returns (x, r, matvecs) with r = b - A x the true residual at
+    exit."""
+    bnorm = _norm(b)
+    x = torch.zeros_like(b) if torch.is_tensor(b) else np.zeros_like(b)
     if bnorm == 0.0:
-        return x, b.copy(), 0
+        return x, (b.clone() if torch.is_tensor(b) else b.copy()), 0
     target = rtol * bnorm
-    r = b.copy()
+    r = b.clone() if torch.is_tensor(b) else b.copy()
     beta = bnorm
     its = 0
     while its < maxiter and beta > target:
@@ -144,9 +157,9 @@ def gmres(matvec, b, rtol, restart=30, maxiter=300, log=None):
             w = matvec(V[k])
             its += 1
             for i in range(k + 1):                 # modified Gram-Schmidt
-                H[i, k] = float(np.dot(w, V[i]))
-                w = w - H[i, k] * V[i]
-            hk1 = float(np.linalg.norm(w))
+                H[i, k] = _dot(w, V[i])
+                w = w - float(H[i, k]) * V[i]
+            hk1 = _norm(w)
             H[k + 1, k] = hk1
             for i in range(k):                     # earlier Givens rotations
                 tmp = cs[i] * H[i, k] + sn[i] * H[i + 1, k]
@@ -166,10 +179,10 @@ def gmres(matvec, b, rtol, restart=30, maxiter=300, log=None):
             V.append(w / hk1)
         coef = np.linalg.solve(np.triu(H[:k_done, :k_done]), g[:k_done])
         for i in range(k_done):
-            x = x + coef[i] * V[i]
+            x = x + float(coef[i]) * V[i]
         r = b - matvec(x)
         its += 1
-        beta = float(np.linalg.norm(r))
+        beta = _norm(r)
     return x, r, its
 
 
@@ -353,7 +366,22 @@ def newton_krylov(t, u, y0, tol=1e-8, jvp="fd", restart=30, max_newton=30, max_k
             years += 1
             return v - jv.cpu().numpy().ravel()
 
-        if pre is None:
+        def matvec_dev(v):
+            # the same product on vectors that stay where the states are
+            nonlocal years
+            vd = v.reshape(shape)
+            if jvp == "tangent":
+                _, jv = t.year_jvp(yd, vd, mode=_tmm.TMM_JVP_TANGENT, want_phi=False)
+            else:
+                _, jv = t.year_jvp(yd, vd, mode=_tmm.TMM_JVP_FD_GIVEN_PHI, phi=phi_y)
+            years += 1
+            return v - jv.reshape(-1)
+
+        if pre is None and torch.is_tensor(phi_y):
+            bF = torch.as_tensor(-F).to(phi_y.device)
+            d, rlin, mv = gmres(matvec_dev, bF, eta, restart=restart, maxiter=max_krylov)
+            d, rlin = d.cpu().numpy(), rlin.cpu().numpy()
+        elif pre is None:
             d, rlin, mv = gmres(matvec, -F, eta, restart=restart, maxiter=max_krylov)
         else:
             # right preconditioning: rlin = -F - J P z is the true residual of d = P z

@@ -188,7 +188,48 @@ def newton_leg(t, inp, u):
     return out
 
 
-def ensemble_leg(dev, stream, steps=30):
+def cpu_ensemble_sample(inp, U, L, steps=2):
+    """The oracle's time for the batched ensemble, extrapolated from a bounded
+    sample: `steps` time steps at full width (W = 2 x members) and at one
+    member (W = 2), timing build of the oracle on every thread this process
+    may use, one untimed step before each; a step at W active columns is
+    taken as linear in W between the two, summed over the years of the
+    uneven spin-up lengths (batched) or over the member-years at W = 2
+    (sequential)."""
+    import shutil
+    import tempfile
+    import oracle
+    from oracle import build as obuild
+    d = tempfile.mkdtemp(prefix="tmm_oracle_timing_")
+    try:
+        lib = obuild.build_timing(os.path.join(d, "liboracle_timing.so"))
+        o = oracle.Oracle(inp, lib_path=lib)
+        used = oracle.threads(int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0))), lib)
+        nm = U.shape[0]
+        per = {}
+        for w, uu in ((2 * nm, U), (2, U[:1])):
+            y = inp.initial_state(uu.shape[0])
+            y = o.step(uu, 0, y)                       # untimed
+            t0 = time.perf_counter()
+            for j in range(1, steps + 1):
+                y = o.step(uu, j, y)
+            per[w] = (time.perf_counter() - t0) / steps
+            log(f"[bench] cpu oracle, ensemble grid, W = {w}: {per[w]:.3f} s per step ({used} threads)")
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    wide, one = per[2 * nm], per[2]
+
+    def step_s(W):
+        return one + (wide - one) * (W - 2) / (2 * nm - 2)
+    batched = sum(inp.nstep * step_s(2 * int((L > yr).sum())) for yr in range(int(L.max())))
+    sequential = int(L.sum()) * inp.nstep * one
+    return {"threads": used, "steps_timed": steps, "s_per_step_full_width": wide, "s_per_step_one_member": one,
+            "batched_s_extrapolated": batched, "sequential_s_extrapolated": sequential,
+            "batched_member_years_per_s": int(L.sum()) / batched, "speedup": sequential / batched,
+            "note": "extrapolated from the timed steps: a step taken as linear in the number of active columns"}
+
+
+def ensemble_leg(dev, stream, steps=30, cpu=False):
     """64 N-DOP parameter vectors (Latin hypercube) with spin-up lengths of
     1..8 model years on the 256x128x23 grid (500000 points): full-width steps
     (W = 128) timed alone, then the whole batched run with compaction of
@@ -260,6 +301,12 @@ def ensemble_leg(dev, stream, steps=30):
     t.close()
     del t, y0, buf, out_b, y1
     torch.cuda.empty_cache()
+    if cpu:
+        res["cpu_oracle"] = cpu_ensemble_sample(inp, U, L)
+        c = res["cpu_oracle"]
+        log(f"[bench] cpu oracle ensemble (extrapolated): batched {c['batched_s_extrapolated']:.0f} s, "
+            f"sequential {c['sequential_s_extrapolated']:.0f} s ({c['speedup']:.2f}x); the GPU batch "
+            f"{c['batched_s_extrapolated'] / (ms_b / 1000.0):.0f}x faster than the oracle's")
     return res
 
 
@@ -420,7 +467,7 @@ def main():
 
     ensemble = None
     if not args.no_ensemble and not args.forward_only:
-        ensemble = ensemble_leg(dev, stream)
+        ensemble = ensemble_leg(dev, stream, cpu=not args.no_cpu_baseline)
 
     cpu = None
     if not args.no_cpu_baseline and not args.forward_only:

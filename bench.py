@@ -497,7 +497,10 @@ def main():
                                            if traffic else None),
                      "traffic_note": "traffic = FETCH_SIZE + WRITE_SIZE per launch (bytes past the L2, "
                                      "calibrated on a plain copy) from the committed counter summary of this "
-                                     "kernel source; null if the source changed since",
+                                     "kernel source; null if the source changed since. The year's working set "
+                                     "(state ring 108 MB, 12 monthly matrix pairs) fits the 256 MB Infinity "
+                                     "Cache, so these bytes need not all reach HBM: hbm_frac_measured is an "
+                                     "upper bound on the HBM share",
                      "kernel": kernel, "us_per_launch": us_per_launch, "bytes_per_launch": B * units,
                      "us_per_time_step": us_per_step,
                      "binding": "latency" if persistent else "hbm",

@@ -191,11 +191,11 @@ def test_member_tile_kernel_year_and_refusals(inputs):
     t1.close()
 
 
-@pytest.mark.parametrize("nb", [6, 16, 17, 32])
+@pytest.mark.parametrize("nb", [2, 6, 16, 17, 32])
 def test_packed_member_kernel(inputs, nb):
     """Batches of at most 32 (16) members run the member kernel with 2 (4) water columns per
-    wavefront: the oracle's step, and bit for bit the one-column-per-wavefront result, in the band
-    order and in the natural order."""
+    wavefront (from 2 members on by default): the oracle's step, and bit for bit the
+    one-column-per-wavefront result, in the band order and in the natural order."""
     tmm = _lib()
     inp = inputs["small"]
     U = synth.latin_hypercube(synth.MODEL_NDOP, nb, seed=90 + nb)
@@ -209,7 +209,9 @@ def test_packed_member_kernel(inputs, nb):
         t.set_option(tmm.TMM_OPT_MEMBER_BAND_ROWS, band)
         for j in (0, 1439, 2879):
             t.set_option(tmm.TMM_OPT_MEMBER_PACK, 0)
+            t.set_option(tmm.TMM_OPT_MEMBER_KERNEL_MIN, 1)      # one column per wavefront at any width
             ref = t.step(j, yd).cpu().numpy()
+            t.set_option(tmm.TMM_OPT_MEMBER_KERNEL_MIN, -1)     # the default crossover
             t.set_option(tmm.TMM_OPT_MEMBER_PACK, 1)
             got = t.step(j, yd).cpu().numpy()
             assert pointwise(got, o.step(U, j, y), 2, f"packed, {nb} members, band {band}, step {j}") <= STEP
